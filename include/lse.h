@@ -1,0 +1,185 @@
+/*
+ * lse.h -- C ABI of the MI355X (gfx950) fast level set evolution library.
+ *
+ * The library implements the two fast level set evolutions (LSE) of Li, Shi,
+ * Wang and Miao, "Extracting Man-Made Objects From Remote Sensing Images via
+ * Fast Level Set Evolutions" (arXiv 1409.7474):
+ *   - region LSE, eq. (17): phi_t = R(I; c+, c-) |grad phi|,
+ *       R = (c+ - c-)(2I - c+ - c-) / max |(c+ - c-)(2I - c+ - c-)|,
+ *     c+ / c- the band means over {phi >= 0} / {phi < 0} (eq. (15));
+ *   - edge LSE, eq. (14): phi_t = g(I) |grad phi|, g = 1 / (1 + |grad G*I|^2);
+ * iterated as Table I: (1) binary initial LSF, eq. (13); (2) data term and
+ * explicit Euler update, eq. (18); (3) reinitialisation to a binary function;
+ * (4) Gaussian smoothing of the LSF in place of curvature regularisation;
+ * (5) stop when the result stops changing; (6) return the binary result.
+ *
+ * Conventions used everywhere:
+ *   - images are H x W x B, row-major, band fastest (pixel (y, x) band b at
+ *     ((y * W) + x) * B + b); masks and LSF planes are H x W row-major;
+ *   - ties phi == 0 (and u == 0) belong to the + side (+1, inside);
+ *   - convolutions use zero padding and same-size output; gradients are
+ *     central differences inside and one-sided at the image border;
+ *   - all arithmetic on the GPU is FP32 (no FP64 anywhere on the device).
+ *
+ * Memory ownership: the caller allocates every device buffer (image, masks,
+ * workspace, outputs).  The library never allocates device memory; it needs
+ * one caller-provided workspace of lse_workspace_bytes() bytes that must stay
+ * alive, and untouched, until lse_destroy().  All calls taking a `stream`
+ * (a hipStream_t; NULL = the default stream) enqueue work on it and return
+ * without synchronising, except lse_stats() and lse_profile_read(), which
+ * synchronise that stream.  One context must not be used from two streams at
+ * the same time; distinct contexts are independent.
+ *
+ * Errors: every call returns an lse_status and never throws or aborts.
+ * Arguments are validated on the host before anything is enqueued.  A HIP
+ * launch or runtime error is returned as LSE_ERR_DEVICE.
+ */
+#ifndef LSE_H
+#define LSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSE_OK = 0,
+    LSE_ERR_INVALID_ARG = -1, /* bad parameter, size, pointer or alignment   */
+    LSE_ERR_BAD_VALUE = -2,   /* non-finite or out-of-range value in the image */
+    LSE_ERR_WORKSPACE = -3,   /* workspace missing, too small or misaligned  */
+    LSE_ERR_DEVICE = -4,      /* HIP runtime / launch error                  */
+    LSE_ERR_STATE = -5,       /* call not valid in the context's state       */
+    LSE_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+} lse_status;
+
+/* Data term: region, eq. (17); edge, eq. (14). */
+typedef enum { LSE_TERM_REGION = 0, LSE_TERM_EDGE = 1 } lse_term;
+
+/* Element types of caller buffers and of the device-resident image copy. */
+typedef enum { LSE_F32 = 0, LSE_F16 = 1, LSE_BF16 = 2 } lse_dtype;
+
+/* Step order.  TABLE1: update -> binarise -> smooth (Table I steps 2-4).
+ * LISTING: update -> smooth -> binarise (the appendix code). */
+typedef enum { LSE_ORDER_TABLE1 = 0, LSE_ORDER_LISTING = 1 } lse_order;
+
+typedef struct {
+    int32_t height, width; /* H, W >= 2, H * W < 2^31                         */
+    int32_t bands;         /* B in 1..4                                       */
+    int32_t term;          /* lse_term                                        */
+    int32_t order;         /* lse_order (this build: TABLE1)                  */
+    int32_t image_dtype;   /* lse_dtype of the caller's image buffer          */
+    int32_t storage;       /* lse_dtype of the device copy (this build: F32)  */
+    float dt;              /* time step of eq. (18), finite, > 0 (paper: 15)  */
+    float sigma;           /* LSF smoothing: sigma of (17) / sigma2 of (14)   */
+    int32_t ksize;         /* its template side TS, odd 3..31; 0 = 2*ceil(3 sigma)+1 */
+    float sigma_img;       /* edge term: image pre-smoothing sigma1 (listing: 1) */
+    int32_t ksize_img;     /* edge term: its template side, odd 3..31 (listing: 9) */
+    float edge_scale;      /* edge term: intensity scale applied to the band
+                              mean before g(I) (255 = 8-bit numbers as in the
+                              listing, for images given in [0, 1])            */
+    int32_t reinit_every;  /* 1 = binarise every iteration (this build: 1)    */
+} lse_params;
+
+/* Fill *p with the defaults (region term, Table I order, dt 15, sigma 1,
+ * TS 7, sigma1 1, TS1 9, edge scale 255, FP32 image and storage) for an
+ * H x W x B image. */
+void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t bands);
+
+/* State after the last executed iteration (see lse_stats). */
+typedef struct {
+    uint64_t n_plus;     /* #{phi >= 0} of the current LSF                    */
+    uint64_t flips;      /* pixels whose binary result changed in the last iteration */
+    int32_t iters_done;  /* iterations executed since lse_init / lse_set_mask */
+    int32_t converged;   /* 1 once an iteration changed no pixel (Step 5)     */
+    int32_t bad_value;   /* 1 if lse_init found a non-finite / out-of-range value */
+    int32_t reserved;
+    float c_plus[4];     /* c+ used by the last iteration (region term)       */
+    float c_minus[4];    /* c- used by the last iteration (region term)       */
+    float M;             /* normaliser max|D| used by the last iteration      */
+    float pad[3];
+} lse_stats_t;
+
+/* Kernel time accumulated while profiling is enabled (see lse_profile). */
+typedef struct {
+    double step_ms;      /* fused update/binarise/smooth/statistics kernel    */
+    double mpass_ms;     /* normaliser pass of eq. (17) (B > 1)               */
+    int64_t step_launches;
+    int64_t mpass_launches;
+} lse_profile_t;
+
+typedef struct lse_ctx lse_ctx; /* opaque, host-side */
+
+/* Bytes of device workspace lse_init needs for *p; 0 if *p is invalid. */
+size_t lse_workspace_bytes(const lse_params *p);
+
+/* Table I step 1.  Copies/converts the image (H x W x B, p->image_dtype) into
+ * the workspace, builds the binary initial LSF of eq. (13) from init_mask
+ * (H x W uint8, nonzero = inside the initial curve = +1), computes the edge
+ * map g of eq. (14) (edge term) or the initial region statistics (region
+ * term).  Image values must be finite with |value| < 65536; the check runs on
+ * the device and is reported by lse_stats().bad_value / lse_check() (the
+ * iteration then leaves the LSF unchanged).  image_dev and init_mask_dev are
+ * read in stream order and may be reused once the stream has passed this
+ * call.  workspace_dev must be 256-byte aligned.  On success *out receives a
+ * new context. */
+lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
+                    void *workspace_dev, size_t workspace_bytes, void *stream, lse_ctx **out);
+
+/* One iteration: Table I steps 2-4 (data term, Euler update eq. (18),
+ * binarisation, Gaussian smoothing). */
+lse_status lse_step(lse_ctx *c, void *stream);
+
+/* Up to max_iters iterations (steps 2-5).  With stop_when_unchanged != 0 the
+ * device stops after the first iteration that changes no pixel; the host does
+ * not synchronise (iterations past that point become no-ops). */
+lse_status lse_run(lse_ctx *c, int32_t max_iters, int32_t stop_when_unchanged, void *stream);
+
+/* Step 6: the binary result (1 = inside, phi >= 0) as H x W uint8. */
+lse_status lse_mask(const lse_ctx *c, uint8_t *mask_dev, void *stream);
+
+/* The current LSF as H x W float32: the Gaussian-smoothed binary function
+ * after at least one iteration, the binary initial LSF before the first. */
+lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream);
+
+/* Load a state (checkpoint / resume): mask_dev (H x W uint8) becomes the
+ * binary function; smoothed = 0 makes it the initial LSF of eq. (13),
+ * smoothed = 1 makes the LSF its Gaussian smoothing (the state after an
+ * iteration).  Region statistics are recomputed; the iteration counter and
+ * the converged flag are reset. */
+lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, void *stream);
+
+/* Copy the state summary to *host_out; synchronises `stream`. */
+lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream);
+
+/* Synchronise `stream`; LSE_ERR_BAD_VALUE if lse_init found a bad value,
+ * LSE_ERR_DEVICE on a pending device error, LSE_OK otherwise. */
+lse_status lse_check(const lse_ctx *c, void *stream);
+
+/* Enable (1) / disable (0) HIP-event timing of every kernel launch of this
+ * context; enabling resets the totals. */
+lse_status lse_profile(lse_ctx *c, int32_t enable);
+
+/* Totals since profiling was enabled; synchronises the stream last used. */
+lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out);
+
+/* Algorithmic HBM bytes per pixel and iteration of the fused step kernel for
+ * this context (image or edge map read once, binary state read and written
+ * once); used for roofline figures.  0 if c is NULL. */
+double lse_step_bytes_per_pixel(const lse_ctx *c);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void lse_destroy(lse_ctx *c);
+
+/* Human-readable name of a status code. */
+const char *lse_status_str(lse_status s);
+
+/* ABI version (major * 100 + minor). */
+int32_t lse_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSE_H */

@@ -1,0 +1,474 @@
+// C ABI of the fast level set evolution library: argument validation,
+// workspace layout, the host-side constant tables and the launch sequence of
+// Table I (arXiv 1409.7474).  Declarations and contracts are in include/lse.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "lse_internal.h"
+
+using namespace lse;
+
+struct lse_ctx {
+    lse_params p;
+    int NB;             // stored bands (1, 2 or 4)
+    int r, ts, nch;     // LSF smoothing
+    int r1, ts1;        // edge term: image pre-smoothing
+    int WW;             // bit words per row
+    long long hw;
+    float fix, inv_fix;
+    int n;              // iterations enqueued since init / set_mask
+    int raw_next;       // next iteration starts from the binary LSF itself
+    DevState *st;
+    Taps *taps;
+    float *img;         // region: storage image; edge: edge map g
+    uint32_t *bits[2];
+    float *tmp[2];
+    Taps host_taps;
+    hipStream_t last_stream;
+    // profiling
+    int prof;
+    struct Ev {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Ev> pending, pool;
+    double prof_ms[2];
+    long long prof_n[2];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int auto_ksize(float sigma) {
+    const int r = (int)ceil(3.0 * (double)sigma);
+    return 2 * r + 1;
+}
+
+int resolved_ksize(int k, float sigma) { return k > 0 ? k : auto_ksize(sigma); }
+
+bool valid_ts(int ts) { return ts >= 3 && ts <= 31 && (ts & 1); }
+
+lse_status validate(const lse_params *p) {
+    if (!p) return LSE_ERR_INVALID_ARG;
+    if (p->height < 2 || p->width < 2) return LSE_ERR_INVALID_ARG;
+    if ((long long)p->height * (long long)p->width >= (1ll << 31)) return LSE_ERR_INVALID_ARG;
+    if (p->bands < 1 || p->bands > 4) return LSE_ERR_INVALID_ARG;
+    if (p->term != LSE_TERM_REGION && p->term != LSE_TERM_EDGE) return LSE_ERR_INVALID_ARG;
+    if (p->order != LSE_ORDER_TABLE1 && p->order != LSE_ORDER_LISTING) return LSE_ERR_INVALID_ARG;
+    if (p->image_dtype != LSE_F32 && p->image_dtype != LSE_F16 && p->image_dtype != LSE_BF16)
+        return LSE_ERR_INVALID_ARG;
+    if (p->storage != LSE_F32 && p->storage != LSE_F16 && p->storage != LSE_BF16) return LSE_ERR_INVALID_ARG;
+    if (!(isfinite(p->dt) && p->dt > 0.f)) return LSE_ERR_INVALID_ARG;
+    if (!(isfinite(p->sigma) && p->sigma > 0.f)) return LSE_ERR_INVALID_ARG;
+    if (p->ksize < 0 || !valid_ts(resolved_ksize(p->ksize, p->sigma))) return LSE_ERR_INVALID_ARG;
+    if (p->term == LSE_TERM_EDGE) {
+        if (!(isfinite(p->sigma_img) && p->sigma_img > 0.f)) return LSE_ERR_INVALID_ARG;
+        if (p->ksize_img < 0 || !valid_ts(resolved_ksize(p->ksize_img, p->sigma_img))) return LSE_ERR_INVALID_ARG;
+        if (!(isfinite(p->edge_scale) && p->edge_scale > 0.f)) return LSE_ERR_INVALID_ARG;
+    }
+    if (p->reinit_every < 0) return LSE_ERR_INVALID_ARG;
+    // Valid requests that this build does not implement.
+    if (p->order != LSE_ORDER_TABLE1) return LSE_ERR_UNSUPPORTED;
+    if (p->storage != LSE_F32) return LSE_ERR_UNSUPPORTED;
+    if (p->reinit_every != 1) return LSE_ERR_UNSUPPORTED;
+    return LSE_OK;
+}
+
+struct Layout {
+    size_t state, taps, img, bits0, bits1, tmp0, tmp1, total;
+};
+
+Layout layout_of(const lse_params *p) {
+    const size_t hw = (size_t)p->height * p->width;
+    const int NB = p->bands == 3 ? 4 : p->bands;
+    const size_t WW = ((size_t)p->width + 31) / 32;
+    Layout L;
+    size_t o = 0;
+    L.state = o;
+    o = align_up(o + sizeof(DevState));
+    L.taps = o;
+    o = align_up(o + sizeof(Taps));
+    L.img = o;
+    o = align_up(o + (p->term == LSE_TERM_REGION ? hw * NB * 4 : hw * 4));
+    L.bits0 = o;
+    o = align_up(o + (size_t)p->height * WW * 4);
+    L.bits1 = o;
+    o = align_up(o + (size_t)p->height * WW * 4);
+    if (p->term == LSE_TERM_EDGE) {
+        L.tmp0 = o;
+        o = align_up(o + hw * 4);
+        L.tmp1 = o;
+        o = align_up(o + hw * 4);
+    } else {
+        L.tmp0 = L.tmp1 = 0;
+    }
+    L.total = o;
+    return L;
+}
+
+// 1-D normalised Gaussian taps of side ts: k[j] = exp(-(j-r)^2 / (2 sigma^2)) / sum.
+void gauss_taps(double sigma, int ts, double *k) {
+    const int r = ts / 2;
+    double s = 0.0;
+    for (int j = 0; j < ts; ++j) {
+        const double d = j - r;
+        k[j] = exp(-d * d / (2.0 * sigma * sigma));
+        s += k[j];
+    }
+    for (int j = 0; j < ts; ++j) k[j] /= s;
+}
+
+void build_taps(Taps &t, double sigma, int ts, double sigma1, int ts1) {
+    memset(&t, 0, sizeof(t));
+    double k[32] = {0};
+    gauss_taps(sigma, ts, k);
+    for (int j = 0; j < ts; ++j) t.k[j] = (float)k[j];
+    double acc = 0.0;
+    t.cum[0] = 0.f;
+    for (int m = 1; m <= ts; ++m) {
+        acc += k[m - 1];
+        t.cum[m] = (float)acc;
+    }
+    const int nch = (ts + kChunkBits - 1) / kChunkBits;
+    for (int c = 0; c < nch; ++c) {
+        for (int m = 0; m < 64; ++m) {
+            double s = 0.0;
+            for (int j = 0; j < kChunkBits; ++j) {
+                const int tap = c * kChunkBits + j;
+                if (tap >= ts) break;
+                s += ((m >> j) & 1) ? k[tap] : -k[tap];
+            }
+            t.lut[c][m] = (float)s;
+        }
+    }
+    if (ts1 > 0) {
+        double k1[32] = {0};
+        gauss_taps(sigma1, ts1, k1);
+        for (int j = 0; j < ts1; ++j) t.k1[j] = (float)k1[j];
+    }
+}
+
+int fix_shift(long long hw) {
+    int lg = 0;
+    while ((1ll << lg) < hw) ++lg;
+    int s = 62 - 16 - lg;  // |I| < 2^16: total |sum| * 2^s < 2^62
+    if (s > 40) s = 40;
+    if (s < 8) s = 8;
+    return s;
+}
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+StepArgs step_args(const lse_ctx *c) {
+    StepArgs a;
+    a.img = c->img;
+    a.bits_in = c->bits[c->n & 1];
+    a.bits_out = c->bits[(c->n + 1) & 1];
+    a.st = c->st;
+    a.taps = c->taps;
+    a.H = c->p.height;
+    a.W = c->p.width;
+    a.WW = c->WW;
+    a.r = c->r;
+    a.ts = c->ts;
+    a.nch = c->nch;
+    a.dt = c->p.dt;
+    a.n = c->n;
+    a.raw = c->raw_next;
+    a.stop = 0;
+    a.fix = c->fix;
+    a.inv_fix = c->inv_fix;
+    a.hw = c->hw;
+    return a;
+}
+
+lse_status dev_status(hipError_t e) { return e == hipSuccess ? LSE_OK : LSE_ERR_DEVICE; }
+
+void prof_begin(lse_ctx *c, int kind, hipStream_t s, lse_ctx::Ev *ev) {
+    if (!c->prof) return;
+    if (c->pool.empty()) {
+        lse_ctx::Ev e;
+        if (hipEventCreate(&e.a) != hipSuccess) return;
+        if (hipEventCreate(&e.b) != hipSuccess) {
+            (void)hipEventDestroy(e.a);
+            return;
+        }
+        c->pool.push_back(e);
+    }
+    *ev = c->pool.back();
+    c->pool.pop_back();
+    ev->kind = kind;
+    (void)hipEventRecord(ev->a, s);
+}
+
+void prof_end(lse_ctx *c, hipStream_t s, lse_ctx::Ev *ev) {
+    if (!c->prof || ev->kind < 0) return;
+    (void)hipEventRecord(ev->b, s);
+    c->pending.push_back(*ev);
+}
+
+lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
+    StepArgs a = step_args(c);
+    a.stop = stop;
+    hipError_t e = hipSuccess;
+    const bool region = c->p.term == LSE_TERM_REGION;
+    if (region && c->NB > 1) {
+        lse_ctx::Ev ev{nullptr, nullptr, -1};
+        prof_begin(c, 1, s, &ev);
+        e = launch_mpass(a, c->NB, s);
+        prof_end(c, s, &ev);
+        if (e != hipSuccess) return LSE_ERR_DEVICE;
+    }
+    lse_ctx::Ev ev{nullptr, nullptr, -1};
+    prof_begin(c, 0, s, &ev);
+    e = launch_step(a, c->NB, region ? 0 : 1, s);
+    prof_end(c, s, &ev);
+    if (e != hipSuccess) return LSE_ERR_DEVICE;
+    c->n += 1;
+    c->raw_next = 0;
+    c->last_stream = s;
+    return LSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t bands) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->height = height;
+    p->width = width;
+    p->bands = bands;
+    p->term = LSE_TERM_REGION;
+    p->order = LSE_ORDER_TABLE1;
+    p->image_dtype = LSE_F32;
+    p->storage = LSE_F32;
+    p->dt = 15.f;
+    p->sigma = 1.f;
+    p->ksize = 7;
+    p->sigma_img = 1.f;
+    p->ksize_img = 9;
+    p->edge_scale = 255.f;
+    p->reinit_every = 1;
+}
+
+size_t lse_workspace_bytes(const lse_params *p) {
+    const lse_status v = validate(p);
+    if (v != LSE_OK && v != LSE_ERR_UNSUPPORTED) return 0;
+    return layout_of(p).total;
+}
+
+lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,
+                    size_t workspace_bytes, void *stream, lse_ctx **out) {
+    if (!out) return LSE_ERR_INVALID_ARG;
+    *out = nullptr;
+    lse_status v = validate(p);
+    if (v != LSE_OK) return v;
+    if (!image_dev || !init_mask_dev) return LSE_ERR_INVALID_ARG;
+    const size_t esz = p->image_dtype == LSE_F32 ? 4 : 2;
+    if (reinterpret_cast<uintptr_t>(image_dev) % esz) return LSE_ERR_INVALID_ARG;
+    if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign)) return LSE_ERR_WORKSPACE;
+    const Layout L = layout_of(p);
+    if (workspace_bytes < L.total) return LSE_ERR_WORKSPACE;
+
+    lse_ctx *c = new (std::nothrow) lse_ctx();
+    if (!c) return LSE_ERR_INVALID_ARG;
+    c->p = *p;
+    c->NB = p->bands == 3 ? 4 : p->bands;
+    c->ts = resolved_ksize(p->ksize, p->sigma);
+    c->r = c->ts / 2;
+    c->nch = (c->ts + kChunkBits - 1) / kChunkBits;
+    c->ts1 = p->term == LSE_TERM_EDGE ? resolved_ksize(p->ksize_img, p->sigma_img) : 0;
+    c->r1 = c->ts1 / 2;
+    c->WW = (p->width + 31) / 32;
+    c->hw = (long long)p->height * p->width;
+    const int s = fix_shift(c->hw);
+    c->fix = ldexpf(1.f, s);
+    c->inv_fix = ldexpf(1.f, -s);
+    c->n = 0;
+    c->raw_next = 1;
+    char *base = static_cast<char *>(workspace_dev);
+    c->st = reinterpret_cast<DevState *>(base + L.state);
+    c->taps = reinterpret_cast<Taps *>(base + L.taps);
+    c->img = reinterpret_cast<float *>(base + L.img);
+    c->bits[0] = reinterpret_cast<uint32_t *>(base + L.bits0);
+    c->bits[1] = reinterpret_cast<uint32_t *>(base + L.bits1);
+    c->tmp[0] = L.tmp0 ? reinterpret_cast<float *>(base + L.tmp0) : nullptr;
+    c->tmp[1] = L.tmp1 ? reinterpret_cast<float *>(base + L.tmp1) : nullptr;
+    c->prof = 0;
+    c->prof_ms[0] = c->prof_ms[1] = 0.0;
+    c->prof_n[0] = c->prof_n[1] = 0;
+    build_taps(c->host_taps, p->sigma, c->ts, p->sigma_img, c->ts1);
+
+    hipStream_t st = as_stream(stream);
+    c->last_stream = st;
+    hipError_t e = hipMemcpyAsync(c->taps, &c->host_taps, sizeof(Taps), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_init_state(c->st, st);
+    if (e == hipSuccess) {
+        if (p->term == LSE_TERM_REGION) {
+            e = launch_init_image(image_dev, p->image_dtype, p->bands, c->NB, c->img, c->hw, c->st, c->fix, 0, 0.f, st);
+        } else {
+            e = launch_init_image(image_dev, p->image_dtype, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
+                                  p->edge_scale, st);
+            if (e == hipSuccess)
+                e = launch_edge_map(c->tmp[1], p->height, p->width, c->taps, c->r1, c->tmp[0], c->tmp[1], c->img, st);
+        }
+    }
+    if (e == hipSuccess) e = launch_pack_mask(init_mask_dev, c->bits[0], p->height, p->width, c->WW, st);
+    if (e == hipSuccess && p->term == LSE_TERM_REGION) {
+        StepArgs a = step_args(c);
+        a.bits_in = c->bits[0];
+        e = launch_stats(a, c->NB, 1, 0, st);
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return LSE_ERR_DEVICE;
+    }
+    *out = c;
+    return LSE_OK;
+}
+
+lse_status lse_step(lse_ctx *c, void *stream) {
+    if (!c) return LSE_ERR_INVALID_ARG;
+    return enqueue_step(c, 0, as_stream(stream));
+}
+
+lse_status lse_run(lse_ctx *c, int32_t max_iters, int32_t stop_when_unchanged, void *stream) {
+    if (!c || max_iters < 0) return LSE_ERR_INVALID_ARG;
+    const hipStream_t s = as_stream(stream);
+    for (int i = 0; i < max_iters; ++i) {
+        const lse_status v = enqueue_step(c, stop_when_unchanged ? 1 : 0, s);
+        if (v != LSE_OK) return v;
+    }
+    return LSE_OK;
+}
+
+lse_status lse_mask(const lse_ctx *c, uint8_t *mask_dev, void *stream) {
+    if (!c || !mask_dev) return LSE_ERR_INVALID_ARG;
+    const uint32_t *const b[2] = {c->bits[0], c->bits[1]};
+    return dev_status(launch_mask_out(b, c->st, mask_dev, c->p.height, c->p.width, c->WW, as_stream(stream)));
+}
+
+lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream) {
+    if (!c || !lsf_dev || (reinterpret_cast<uintptr_t>(lsf_dev) & 3)) return LSE_ERR_INVALID_ARG;
+    const uint32_t *const b[2] = {c->bits[0], c->bits[1]};
+    StepArgs a = step_args(c);
+    return dev_status(launch_lsf_out(a, b, c->raw_next, lsf_dev, as_stream(stream)));
+}
+
+lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, void *stream) {
+    if (!c || !mask_dev) return LSE_ERR_INVALID_ARG;
+    const hipStream_t s = as_stream(stream);
+    hipError_t e = launch_reset_state(c->st, s);
+    if (e == hipSuccess) e = launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
+    c->n = 0;
+    c->raw_next = smoothed ? 0 : 1;
+    if (e == hipSuccess && c->p.term == LSE_TERM_REGION) {
+        StepArgs a = step_args(c);
+        a.bits_in = c->bits[0];
+        e = launch_stats(a, c->NB, c->raw_next, 0, s);
+    }
+    c->last_stream = s;
+    return dev_status(e);
+}
+
+lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream) {
+    if (!c || !host_out) return LSE_ERR_INVALID_ARG;
+    const hipStream_t s = as_stream(stream);
+    DevState h;
+    if (hipMemcpyAsync(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess) return LSE_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return LSE_ERR_DEVICE;
+    memset(host_out, 0, sizeof(*host_out));
+    const Slot &cur = h.slot[h.iters % 3];
+    host_out->n_plus = cur.nplus;
+    host_out->flips = h.iters > 0 ? cur.flips : 0;
+    host_out->iters_done = h.iters;
+    host_out->converged = h.done;
+    host_out->bad_value = h.bad ? 1 : 0;
+    for (int b = 0; b < 4; ++b) {
+        host_out->c_plus[b] = h.last_cp[b];
+        host_out->c_minus[b] = h.last_cm[b];
+    }
+    host_out->M = h.last_M;
+    return LSE_OK;
+}
+
+lse_status lse_check(const lse_ctx *c, void *stream) {
+    lse_stats_t st;
+    const lse_status v = lse_stats(c, &st, stream);
+    if (v != LSE_OK) return v;
+    if (hipGetLastError() != hipSuccess) return LSE_ERR_DEVICE;
+    return st.bad_value ? LSE_ERR_BAD_VALUE : LSE_OK;
+}
+
+lse_status lse_profile(lse_ctx *c, int32_t enable) {
+    if (!c) return LSE_ERR_INVALID_ARG;
+    if (enable) {
+        for (auto &e : c->pending) c->pool.push_back(e);
+        c->pending.clear();
+        c->prof_ms[0] = c->prof_ms[1] = 0.0;
+        c->prof_n[0] = c->prof_n[1] = 0;
+    }
+    c->prof = enable ? 1 : 0;
+    return LSE_OK;
+}
+
+lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out) {
+    if (!c || !host_out) return LSE_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess) return LSE_ERR_DEVICE;
+    for (auto &e : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            c->prof_ms[e.kind] += ms;
+            c->prof_n[e.kind] += 1;
+        }
+        c->pool.push_back(e);
+    }
+    c->pending.clear();
+    host_out->step_ms = c->prof_ms[0];
+    host_out->mpass_ms = c->prof_ms[1];
+    host_out->step_launches = c->prof_n[0];
+    host_out->mpass_launches = c->prof_n[1];
+    return LSE_OK;
+}
+
+double lse_step_bytes_per_pixel(const lse_ctx *c) {
+    if (!c) return 0.0;
+    const double state = 2.0 / 8.0;  // binary state: one bit read, one bit written
+    if (c->p.term == LSE_TERM_EDGE) return 4.0 + state;
+    return 4.0 * c->NB + state;
+}
+
+void lse_destroy(lse_ctx *c) {
+    if (!c) return;
+    for (auto &e : c->pending) c->pool.push_back(e);
+    for (auto &e : c->pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    delete c;
+}
+
+const char *lse_status_str(lse_status s) {
+    switch (s) {
+        case LSE_OK: return "LSE_OK";
+        case LSE_ERR_INVALID_ARG: return "LSE_ERR_INVALID_ARG";
+        case LSE_ERR_BAD_VALUE: return "LSE_ERR_BAD_VALUE";
+        case LSE_ERR_WORKSPACE: return "LSE_ERR_WORKSPACE";
+        case LSE_ERR_DEVICE: return "LSE_ERR_DEVICE";
+        case LSE_ERR_STATE: return "LSE_ERR_STATE";
+        case LSE_ERR_UNSUPPORTED: return "LSE_ERR_UNSUPPORTED";
+    }
+    return "LSE_ERR_UNKNOWN";
+}
+
+int32_t lse_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,879 @@
+// HIP kernels of the fast level set evolution (arXiv 1409.7474) for gfx950.
+//
+// State representation.  With reinitialisation every iteration (Table I
+// step 3) the LSF after step 4 is phi^{n+1} = G * b^n, the Gaussian smoothing
+// of a binary function.  The device therefore keeps only the binary function
+// b (1 bit per pixel, 32-pixel words per row) and recomputes phi on the fly in
+// FP32: a horizontal pass turns each 1 x TS window of bits into a weighted sum
+// through 64-entry lookup tables (6 bits per lookup), a vertical pass applies
+// the taps with FMAs.  Zero padding at the image border is exact: taps that
+// fall outside are forced to +1 and their weight subtracted.
+//
+// One iteration of the region term is one fused kernel per 64 x 32 tile
+// (plus, for B > 1, a read-only pass for the normaliser of eq. (17)):
+//   A. stage b^{n-1} on the tile plus a halo of 2r+1 in LDS;
+//   B. phi^n = G * b^{n-1} on the tile plus a halo of r+1;
+//   C. data term, |grad phi^n|, Euler update eq. (18) and sign -> b^n on the
+//      tile plus a halo of r (wave64 ballots build the bit words);
+//   D. sign(G * b^n) on the tile -> region sums for iteration n+1 (eq. (15)),
+//      reduced per wave, per workgroup, then one 64-bit atomic per band.
+// The halo of phase C is recomputed by neighbouring tiles with the same
+// position-only arithmetic, so every tile sees identical bits.  The edge term
+// (eq. (14)) needs no statistics: its tile halo is only r+1.
+//
+// Region sums: FP32 within a workgroup, converted per workgroup to 64-bit
+// fixed point (scale 2^s) and added atomically, so totals do not depend on
+// workgroup scheduling.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "lse_internal.h"
+
+namespace lse {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ unsigned int float_key(float f) {
+    unsigned int u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_float(unsigned int k) {
+    unsigned int u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+template <int NB>
+struct Px {
+    float v[NB];
+};
+
+template <int NB>
+__device__ __forceinline__ Px<NB> load_px(const float *__restrict__ img, long long pix) {
+    Px<NB> p;
+    if constexpr (NB == 4) {
+        float4 f = *reinterpret_cast<const float4 *>(img + pix * 4);
+        p.v[0] = f.x;
+        p.v[1] = f.y;
+        p.v[2] = f.z;
+        p.v[3] = f.w;
+    } else if constexpr (NB == 2) {
+        float2 f = *reinterpret_cast<const float2 *>(img + pix * 2);
+        p.v[0] = f.x;
+        p.v[1] = f.y;
+    } else {
+        p.v[0] = img[pix];
+    }
+    return p;
+}
+
+// Band means of eq. (15) from the fixed-point sums of one slot.
+template <int NB>
+__device__ __forceinline__ void slot_means(const DevState *st, int sl, long long hw, float inv_fix,
+                                           float (&cp)[NB], float (&cm)[NB]) {
+    const unsigned long long np = st->slot[sl].nplus;
+    const long long nm = hw - (long long)np;
+    const float fnp = (float)np, fnm = (float)nm;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const long long S = st->slot[sl].sum[b];
+        const long long T = st->total[b];
+        cp[b] = np > 0 ? ((float)S * inv_fix) / fnp : 0.f;
+        cm[b] = nm > 0 ? ((float)(T - S) * inv_fix) / fnm : 0.f;
+    }
+}
+
+// Numerator of eq. (17): D = sum_b (c+ - c-)(2 I_b - c+ - c-), with
+// a_b = c+ - c- and m_b = c+ + c-.  The same expression is used by every
+// kernel so that the normaliser pass and the update agree bit for bit.
+template <int NB>
+__device__ __forceinline__ float region_D(const Px<NB> &p, const float (&a)[NB], const float (&m)[NB]) {
+    float d = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) d = fmaf(a[b], fmaf(2.f, p.v[b], -m[b]), d);
+    return d;
+}
+
+// Horizontal Gaussian of a binary row at image column x (eq. (13) values
+// +1 / -1, zero outside the image).  `row` holds kRowWords bit words whose bit
+// 0 is image column x0 - 32; xb is the bit position of column x.
+__device__ __forceinline__ float hconv_bits(const uint32_t *row, int xb, int x, int W, int r, int ts,
+                                            int nch, const float *lut, const float *cum) {
+    const int ws = xb - r;
+    const int wi = ws >> 5;
+    const uint32_t lo = row[wi], hi = row[wi + 1];
+    const uint32_t full = (1u << ts) - 1u;
+    uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(ws & 31)) & full;
+    float corr = 0.f;
+    const int left = r - x;             // taps left of column 0
+    const int right = x + r - (W - 1);  // taps right of column W - 1
+    if (left > 0) {
+        win |= (1u << left) - 1u;
+        corr = cum[left];
+    }
+    if (right > 0) {
+        win |= full & ~((1u << (ts - right)) - 1u);
+        corr += cum[right];
+    }
+    float h = lut[win & 63u];
+    for (int c = 1; c < nch; ++c) h += lut[c * 64 + ((win >> (6 * c)) & 63u)];
+    return h - corr;
+}
+
+// Vertical Gaussian: acc = sum_j k[j] col[j * stride], j = 0 .. ts-1, in order.
+__device__ __forceinline__ float vconv(const float *col, int stride, const float *k, int ts) {
+    float acc = 0.f;
+    for (int j = 0; j < ts; ++j) acc = fmaf(k[j], col[j * stride], acc);
+    return acc;
+}
+
+// LDS carve-up shared by the tile kernels.
+struct TileSmem {
+    float *lut, *cum, *k, *h, *phi, *red;
+    uint32_t *bits, *bn;
+};
+
+__host__ __device__ inline int tile_ru(int edge, int r) { return edge ? 0 : r; }
+
+__host__ __device__ inline size_t tile_smem_words(int r, int nch, int edge) {
+    const int RU = tile_ru(edge, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    size_t hwords = (size_t)BH * PW;
+    if ((size_t)UH * kTileX > hwords) hwords = (size_t)UH * kTileX;
+    return (size_t)nch * 64 + 36 + 32 + (size_t)BH * kRowWords + (size_t)UH * kRowWords + hwords +
+           (size_t)PH * PW + 4 * 8;
+}
+
+__device__ __forceinline__ TileSmem carve(float *smem, int r, int nch, int edge) {
+    const int RU = tile_ru(edge, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    size_t hwords = (size_t)BH * PW;
+    if ((size_t)UH * kTileX > hwords) hwords = (size_t)UH * kTileX;
+    TileSmem t;
+    float *p = smem;
+    t.lut = p;
+    p += nch * 64;
+    t.cum = p;
+    p += 36;
+    t.k = p;
+    p += 32;
+    t.bits = reinterpret_cast<uint32_t *>(p);
+    p += BH * kRowWords;
+    t.bn = reinterpret_cast<uint32_t *>(p);
+    p += UH * kRowWords;
+    t.h = p;
+    p += hwords;
+    t.phi = p;
+    p += PH * PW;
+    t.red = p;
+    return t;
+}
+
+__device__ __forceinline__ void stage_tables(const TileSmem &s, const Taps *__restrict__ taps, int ts, int nch) {
+    for (int i = threadIdx.x; i < nch * 64; i += kThreads) s.lut[i] = (&taps->lut[0][0])[i];
+    for (int i = threadIdx.x; i <= ts; i += kThreads) s.cum[i] = taps->cum[i];
+    for (int i = threadIdx.x; i < ts; i += kThreads) s.k[i] = taps->k[i];
+}
+
+// Stage bit rows [row0, row0 + nrows) of the tile's 4-word window starting
+// at global word (x0 / 32) - 1; out-of-image rows and words read as 0.
+__device__ __forceinline__ void stage_bits(uint32_t *dst, const uint32_t *__restrict__ bits, int row0, int nrows,
+                                           int x0, int H, int WW) {
+    const int wb0 = (x0 >> 5) - 1;
+    for (int i = threadIdx.x; i < nrows * kRowWords; i += kThreads) {
+        const int row = i / kRowWords, wc = i - row * kRowWords;
+        const int y = row0 + row, gw = wb0 + wc;
+        uint32_t v = 0;
+        if (wc < 4 && y >= 0 && y < H && gw >= 0 && gw < WW) v = bits[(size_t)y * WW + gw];
+        dst[i] = v;
+    }
+}
+
+// Phase D: sign of G * b on the owned tile (b given in s.bn for rows
+// y0 - r .. y0 + kTileY + r), accumulated into per-thread sums.  When raw is
+// set the LSF is b itself.  Shared by the step kernel and the statistics
+// kernel so that both produce identical partial sums.
+template <int NB>
+__device__ __forceinline__ void stats_tile(const TileSmem &s, const float *__restrict__ img, int x0, int y0,
+                                           int H, int W, int r, int ts, int nch, int raw, float (&acc)[NB],
+                                           int &cnt) {
+    const int UH = kTileY + 2 * r;
+    if (!raw) {
+        for (int i = threadIdx.x; i < UH * kTileX; i += kThreads) {
+            const int uy = i / kTileX, ox = i - uy * kTileX;
+            const int y = y0 - r + uy, x = x0 + ox;
+            float h = 0.f;
+            if (y >= 0 && y < H && x < W) h = hconv_bits(s.bn + uy * kRowWords, ox + 32, x, W, r, ts, nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    cnt = 0;
+    for (int k = 0; k < (kTileX * kTileY) / kThreads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int oy = i / kTileX, ox = i - oy * kTileX;
+        const int y = y0 + oy, x = x0 + ox;
+        if (y < H && x < W) {
+            bool inside;
+            if (raw) {
+                const uint32_t w = s.bn[(oy + r) * kRowWords + ((ox + 32) >> 5)];
+                inside = (w >> ((ox + 32) & 31)) & 1u;
+            } else {
+                inside = vconv(s.h + oy * kTileX + ox, kTileX, s.k, ts) >= 0.f;
+            }
+            if (inside) {
+                const Px<NB> p = load_px<NB>(img, (long long)y * W + x);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+                ++cnt;
+            }
+        }
+    }
+}
+
+// Workgroup reduction of (NB sums, count, flips) and one atomic per value.
+template <int NB>
+__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Slot *out,
+                                             float fix, bool with_sums) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (with_sums) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = wave_sum_f(acc[b]);
+        cnt = wave_sum_i(cnt);
+    }
+    flips = wave_sum_i(flips);
+    if (lane == 0) {
+        float *rw = s.red + wave * 8;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rw[b] = acc[b];
+        reinterpret_cast<int *>(rw)[6] = cnt;
+        reinterpret_cast<int *>(rw)[7] = flips;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float S[NB];
+        int C = 0, F = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) S[b] = 0.f;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const float *rw = s.red + w * 8;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) S[b] += rw[b];
+            C += reinterpret_cast<const int *>(rw)[6];
+            F += reinterpret_cast<const int *>(rw)[7];
+        }
+        if (with_sums) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]),
+                          (unsigned long long)__float2ll_rn(S[b] * fix));
+            atomicAdd(&out->nplus, (unsigned long long)C);
+        }
+        if (F) atomicAdd(&out->flips, (unsigned long long)F);
+    }
+}
+
+// ------------------------------------------------------------- init kernels
+
+__global__ void init_state_kernel(DevState *st, int keep_image_stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int s = 0; s < 3; ++s) {
+        for (int b = 0; b < 4; ++b) st->slot[s].sum[b] = 0;
+        st->slot[s].nplus = 0;
+        st->slot[s].flips = 0;
+    }
+    st->slot[0].flips = kNoFlips;
+    st->mbits[0] = st->mbits[1] = 0;
+    st->done = 0;
+    st->iters = 0;
+    for (int b = 0; b < 4; ++b) st->last_cp[b] = st->last_cm[b] = 0.f;
+    st->last_M = 0.f;
+    if (!keep_image_stats) {
+        for (int b = 0; b < 4; ++b) {
+            st->total[b] = 0;
+            st->imin_key[b] = 0xffffffffu;
+            st->imax_key[b] = 0u;
+        }
+        st->bad = 0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ float to_f32(T v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+
+// Convert the caller's image to the FP32 interleaved storage (NB >= B bands,
+// extra bands zero), check values, and reduce per-band min / max and totals.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restrict__ src, int B, int NB,
+                                                              float *__restrict__ dst, long long npx,
+                                                              DevState *st, float fix, int want_gray,
+                                                              float gray_scale) {
+    float sum[4] = {0.f, 0.f, 0.f, 0.f};
+    float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < npx; i += (long long)gridDim.x * kThreads) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b < B) {
+                v[b] = to_f32<T>(src[i * B + b]);
+                if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // also catches NaN / Inf
+            }
+        }
+        if (want_gray) {
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < B) s += v[b];
+            dst[i] = gray_scale * (s / (float)B);
+        } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < NB) dst[i * NB + b] = v[b];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b < B) {
+                sum[b] += v[b];
+                mn[b] = fminf(mn[b], v[b]);
+                mx[b] = fmaxf(mx[b], v[b]);
+            }
+        }
+    }
+    __shared__ float red[kThreads / 64][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (bad) st->bad = 1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (b >= B) break;
+        const float s = wave_sum_f(sum[b]);
+        const float lo = wave_min_f(mn[b]);
+        const float hi = wave_max_f(mx[b]);
+        if (lane == 0) {
+            red[wave][b] = s;
+            atomicMin(&st->imin_key[b], float_key(lo));
+            atomicMax(&st->imax_key[b], float_key(hi));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && !want_gray) {
+        for (int b = 0; b < B; ++b) {
+            float s = 0.f;
+            for (int w = 0; w < kThreads / 64; ++w) s += red[w][b];
+            atomicAdd(reinterpret_cast<unsigned long long *>(&st->total[b]),
+                      (unsigned long long)__float2ll_rn(s * fix));
+        }
+    }
+}
+
+// uint8 mask (nonzero = inside) -> bit words, bit i of word w = column 32 w + i.
+__global__ void pack_mask_kernel(const uint8_t *__restrict__ mask, uint32_t *__restrict__ bits, int H, int W,
+                                 int WW) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * WW) return;
+    const int y = (int)(i / WW), w = (int)(i - (long long)y * WW);
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int x = w * 32 + b;
+        if (x < W && mask[(size_t)y * W + x]) v |= 1u << b;
+    }
+    bits[i] = v;
+}
+
+// Region statistics of the LSF given by `bits` (raw: phi = b; else phi = G * b).
+template <int NB>
+__global__ __launch_bounds__(kThreads) void stats_kernel(StepArgs A, int raw, int slot) {
+    extern __shared__ float smem[];
+    const TileSmem s = carve(smem, A.r, A.nch, 0);
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    stage_tables(s, A.taps, A.ts, A.nch);
+    stage_bits(s.bn, A.bits_in, y0 - A.r, kTileY + 2 * A.r, x0, A.H, A.WW);
+    __syncthreads();
+    float acc[NB];
+    int cnt;
+    stats_tile<NB>(s, static_cast<const float *>(A.img), x0, y0, A.H, A.W, A.r, A.ts, A.nch, raw, acc, cnt);
+    reduce_commit<NB>(s, acc, cnt, 0, &A.st->slot[slot], A.fix, true);
+}
+
+// ------------------------------------------------------------ edge map init
+
+// out(y, x) = sum_j k[j] in(y, x + j - r)   (zero outside)
+__global__ void hconv_f32_kernel(const float *__restrict__ in, float *__restrict__ out, int H, int W,
+                                 const Taps *__restrict__ taps, int r) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * W) return;
+    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    float acc = 0.f;
+    for (int j = 0; j <= 2 * r; ++j) {
+        const int xx = x + j - r;
+        if (xx >= 0 && xx < W) acc = fmaf(taps->k1[j], in[(size_t)y * W + xx], acc);
+    }
+    out[i] = acc;
+}
+
+// out(y, x) = sum_j k[j] in(y + j - r, x)   (zero outside)
+__global__ void vconv_f32_kernel(const float *__restrict__ in, float *__restrict__ out, int H, int W,
+                                 const Taps *__restrict__ taps, int r) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * W) return;
+    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    float acc = 0.f;
+    for (int j = 0; j <= 2 * r; ++j) {
+        const int yy = y + j - r;
+        if (yy >= 0 && yy < H) acc = fmaf(taps->k1[j], in[(size_t)yy * W + x], acc);
+    }
+    out[i] = acc;
+}
+
+// g = 1 / (1 + |grad Is|^2), eq. (14); central differences inside, one-sided
+// at the border.
+__global__ void edge_g_kernel(const float *__restrict__ Is, float *__restrict__ g, int H, int W) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * W) return;
+    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    const float *row = Is + (size_t)y * W;
+    float gx, gy;
+    if (x == 0)
+        gx = row[1] - row[0];
+    else if (x == W - 1)
+        gx = row[W - 1] - row[W - 2];
+    else
+        gx = 0.5f * (row[x + 1] - row[x - 1]);
+    if (y == 0)
+        gy = Is[(size_t)W + x] - Is[x];
+    else if (y == H - 1)
+        gy = Is[(size_t)(H - 1) * W + x] - Is[(size_t)(H - 2) * W + x];
+    else
+        gy = 0.5f * (Is[(size_t)(y + 1) * W + x] - Is[(size_t)(y - 1) * W + x]);
+    g[i] = 1.f / (1.f + (gx * gx + gy * gy));
+}
+
+// ------------------------------------------------------------ normaliser
+
+// M = max_x |D(x)| of eq. (17), for B > 1 (B = 1 uses the closed form from
+// the image min / max, since D is then monotone in I).
+template <int NB>
+__global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    if (st->done || st->bad || (A.stop && st->slot[sl].flips == 0)) return;
+    float cp[NB], cm[NB], a[NB], m[NB];
+    slot_means<NB>(st, sl, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        a[b] = cp[b] - cm[b];
+        m[b] = cp[b] + cm[b];
+    }
+    const float *img = static_cast<const float *>(A.img);
+    float mx = 0.f;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < A.hw; i += (long long)gridDim.x * kThreads)
+        mx = fmaxf(mx, fabsf(region_D<NB>(load_px<NB>(img, i), a, m)));
+    mx = wave_max_f(mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(&st->mbits[A.n & 1], __float_as_uint(mx));
+}
+
+// ------------------------------------------------------------------- step
+
+template <int NB, bool EDGE>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
+    extern __shared__ float smem[];
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    {
+        int done = st->done | st->bad;
+        if (!done && A.stop && st->slot[sl].flips == 0) done = 1;
+        if (done) {
+            if (lead && !st->bad) st->done = 1;
+            return;
+        }
+    }
+    const int r = A.r, ts = A.ts, nch = A.nch, H = A.H, W = A.W;
+    const int RU = tile_ru(EDGE, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    const int by0 = y0 - RU - 1 - r;      // image row of staged bit row 0
+    const int px0 = x0 - RU - 1, py0 = y0 - RU - 1;  // image coords of phi(0, 0)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const TileSmem s = carve(smem, r, nch, EDGE);
+
+    // A: tables and b^{n-1}
+    stage_tables(s, A.taps, ts, nch);
+    stage_bits(s.bits, A.bits_in, by0, BH, x0, H, A.WW);
+    __syncthreads();
+
+    // Data-term coefficients (identical in every workgroup).
+    float a[NB], m[NB], w = 0.f;
+    float cp[NB], cm[NB], M = 0.f;
+    if constexpr (!EDGE) {
+        slot_means<NB>(st, sl, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            a[b] = cp[b] - cm[b];
+            m[b] = cp[b] + cm[b];
+        }
+        if constexpr (NB == 1) {
+            Px<1> lo, hi;
+            lo.v[0] = key_float(st->imin_key[0]);
+            hi.v[0] = key_float(st->imax_key[0]);
+            M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
+        } else {
+            M = __uint_as_float(st->mbits[A.n & 1]);
+        }
+        w = M > 0.f ? A.dt / M : 0.f;
+    }
+
+    // B: phi^n on the tile + (RU + 1) halo.
+    if (A.raw) {
+        for (int i = tid; i < PH * PW; i += kThreads) {
+            const int q = i / PW, p = i - q * PW;
+            const int y = py0 + q, x = px0 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                const int xb = x - x0 + 32;
+                const uint32_t wd = s.bits[(q + r) * kRowWords + (xb >> 5)];
+                v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+            }
+            s.phi[i] = v;
+        }
+    } else {
+        for (int i = tid; i < BH * PW; i += kThreads) {
+            const int row = i / PW, p = i - row * PW;
+            const int y = by0 + row, x = px0 + p;
+            float h = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                h = hconv_bits(s.bits + row * kRowWords, x - x0 + 32, x, W, r, ts, nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+        for (int i = tid; i < PH * PW; i += kThreads) {
+            const int q = i / PW, p = i - q * PW;
+            const int y = py0 + q, x = px0 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) v = vconv(s.h + q * PW + p, PW, s.k, ts);
+            s.phi[i] = v;
+        }
+    }
+    __syncthreads();
+
+    // C: update eq. (18) and binarisation on the tile + RU halo.
+    for (int t = wave; t < UH * 2; t += kThreads / 64) {
+        const int uy = t >> 1, half = t & 1;
+        const int xb = half * 64 + lane;
+        const int x = x0 - 32 + xb, y = y0 - RU + uy;
+        bool pred = false;
+        if (xb >= 32 - RU && xb < 96 + RU && x >= 0 && x < W && y >= 0 && y < H) {
+            const int q = uy + 1, p = x - px0;
+            const float *c = s.phi + q * PW + p;
+            float gx, gy;
+            if (x == 0)
+                gx = c[1] - c[0];
+            else if (x == W - 1)
+                gx = c[0] - c[-1];
+            else
+                gx = 0.5f * (c[1] - c[-1]);
+            if (y == 0)
+                gy = c[PW] - c[0];
+            else if (y == H - 1)
+                gy = c[0] - c[-PW];
+            else
+                gy = 0.5f * (c[PW] - c[-PW]);
+            const float gm = sqrtf(gx * gx + gy * gy);
+            const long long pix = (long long)y * W + x;
+            float coef;
+            if constexpr (EDGE) {
+                coef = A.dt * static_cast<const float *>(A.img)[pix];
+            } else {
+                coef = w * region_D<NB>(load_px<NB>(static_cast<const float *>(A.img), pix), a, m);
+            }
+            pred = fmaf(coef, gm, c[0]) >= 0.f;
+        }
+        const unsigned long long bal = __ballot(pred);
+        if (lane == 0) {
+            s.bn[uy * kRowWords + 2 * half] = (uint32_t)bal;
+            s.bn[uy * kRowWords + 2 * half + 1] = (uint32_t)(bal >> 32);
+            if (half) s.bn[uy * kRowWords + 4] = 0u;
+        }
+    }
+    __syncthreads();
+
+    // Owned words of b^n to global memory, and flips against b^{n-1}.
+    int flips = 0;
+    if (tid < kTileY * 2) {
+        const int row = tid >> 1, wsel = tid & 1;
+        const int y = y0 + row, gw = (x0 >> 5) + wsel;
+        if (y < H && gw < A.WW) {
+            const int xs = gw * 32;
+            const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+            const uint32_t nw = s.bn[(row + RU) * kRowWords + 1 + wsel] & valid;
+            const uint32_t ow = s.bits[(row + RU + 1 + r) * kRowWords + 1 + wsel] & valid;
+            A.bits_out[(size_t)y * A.WW + gw] = nw;
+            flips = __popc(nw ^ ow);
+        }
+    }
+
+    Slot *out = &st->slot[(A.n + 1) % 3];
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    int cnt = 0;
+    if constexpr (!EDGE) {
+        // D: statistics of phi^{n+1} = G * b^n for the next iteration.
+        stats_tile<NB>(s, static_cast<const float *>(A.img), x0, y0, H, W, r, ts, nch, 0, acc, cnt);
+    }
+    reduce_commit<NB>(s, acc, cnt, flips, out, A.fix, !EDGE);
+
+    if (lead) {
+        Slot &z = st->slot[(A.n + 2) % 3];
+        for (int b = 0; b < 4; ++b) z.sum[b] = 0;
+        z.nplus = 0;
+        z.flips = 0;
+        st->mbits[(A.n + 1) & 1] = 0u;
+        st->iters += 1;
+        if constexpr (!EDGE) {
+            for (int b = 0; b < NB; ++b) {
+                st->last_cp[b] = cp[b];
+                st->last_cm[b] = cm[b];
+            }
+            st->last_M = M;
+        }
+    }
+}
+
+// --------------------------------------------------------------- exports
+
+__global__ void mask_out_kernel(const uint32_t *__restrict__ b0, const uint32_t *__restrict__ b1,
+                                const DevState *__restrict__ st, uint8_t *__restrict__ mask, int H, int W, int WW) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * W) return;
+    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    const uint32_t *bits = (st->iters & 1) ? b1 : b0;
+    mask[i] = (bits[(size_t)y * WW + (x >> 5)] >> (x & 31)) & 1u;
+}
+
+// phi = G * b (or b itself when raw) on 64 x 32 tiles, with the same
+// arithmetic as the step kernel.
+__global__ __launch_bounds__(kThreads) void lsf_out_kernel(StepArgs A, const uint32_t *__restrict__ b0,
+                                                           const uint32_t *__restrict__ b1, int raw,
+                                                           float *__restrict__ out) {
+    extern __shared__ float smem[];
+    const TileSmem s = carve(smem, A.r, A.nch, 0);
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    const uint32_t *bits = (A.st->iters & 1) ? b1 : b0;
+    stage_tables(s, A.taps, A.ts, A.nch);
+    stage_bits(s.bn, bits, y0 - A.r, kTileY + 2 * A.r, x0, A.H, A.WW);
+    __syncthreads();
+    if (!raw) {
+        for (int i = threadIdx.x; i < (kTileY + 2 * A.r) * kTileX; i += kThreads) {
+            const int uy = i / kTileX, ox = i - uy * kTileX;
+            const int y = y0 - A.r + uy, x = x0 + ox;
+            float h = 0.f;
+            if (y >= 0 && y < A.H && x < A.W)
+                h = hconv_bits(s.bn + uy * kRowWords, ox + 32, x, A.W, A.r, A.ts, A.nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < (kTileX * kTileY) / kThreads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int oy = i / kTileX, ox = i - oy * kTileX;
+        const int y = y0 + oy, x = x0 + ox;
+        if (y < A.H && x < A.W) {
+            float v;
+            if (raw) {
+                const uint32_t wd = s.bn[(oy + A.r) * kRowWords + ((ox + 32) >> 5)];
+                v = ((wd >> ((ox + 32) & 31)) & 1u) ? 1.f : -1.f;
+            } else {
+                v = vconv(s.h + oy * kTileX + ox, kTileX, s.k, A.ts);
+            }
+            out[(size_t)y * A.W + x] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Workgroups may use more than 64 KB of LDS (gfx950 has 160 KB per CU) for
+// large templates; raise the per-kernel limit when a launch needs it.
+template <typename K>
+static hipError_t ensure_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+static inline dim3 tile_grid(int H, int W) { return dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY); }
+
+static inline unsigned int stream_blocks(long long n, int per_thread = 1) {
+    long long b = (n + (long long)kThreads * per_thread - 1) / ((long long)kThreads * per_thread);
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (unsigned int)b;
+}
+
+hipError_t launch_init_state(DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_state(DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_image(const void *src, int src_dtype, int B, int NB, float *dst, long long npx, DevState *st,
+                             float fix, int want_gray, float gray_scale, hipStream_t s) {
+    const dim3 grid(stream_blocks(npx, 4)), block(kThreads);
+    switch (src_dtype) {
+        case LSE_F32:
+            hipLaunchKernelGGL(init_image_kernel<float>, grid, block, 0, s, static_cast<const float *>(src), B, NB,
+                               dst, npx, st, fix, want_gray, gray_scale);
+            break;
+        case LSE_F16:
+            hipLaunchKernelGGL(init_image_kernel<__half>, grid, block, 0, s, static_cast<const __half *>(src), B, NB,
+                               dst, npx, st, fix, want_gray, gray_scale);
+            break;
+        case LSE_BF16:
+            hipLaunchKernelGGL(init_image_kernel<__hip_bfloat16>, grid, block, 0, s,
+                               static_cast<const __hip_bfloat16 *>(src), B, NB, dst, npx, st, fix, want_gray,
+                               gray_scale);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
+    const long long n = (long long)H * WW;
+    hipLaunchKernelGGL(pack_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mask, bits, H, W, WW);
+    return hipGetLastError();
+}
+
+size_t tile_smem_bytes(int r, int nch, int edge) { return tile_smem_words(r, nch, edge) * 4; }
+
+hipError_t launch_stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, 0);
+    const dim3 grid = tile_grid(a.H, a.W);
+    hipError_t e = hipSuccess;
+    switch (NB) {
+        case 1:
+            if ((e = ensure_lds(stats_kernel<1>, sm)) != hipSuccess) return e;
+            hipLaunchKernelGGL(stats_kernel<1>, grid, dim3(kThreads), sm, s, a, raw, slot);
+            break;
+        case 2:
+            if ((e = ensure_lds(stats_kernel<2>, sm)) != hipSuccess) return e;
+            hipLaunchKernelGGL(stats_kernel<2>, grid, dim3(kThreads), sm, s, a, raw, slot);
+            break;
+        case 4:
+            if ((e = ensure_lds(stats_kernel<4>, sm)) != hipSuccess) return e;
+            hipLaunchKernelGGL(stats_kernel<4>, grid, dim3(kThreads), sm, s, a, raw, slot);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
+                           float *g, hipStream_t s) {
+    const long long n = (long long)H * W;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(hconv_f32_kernel, grid, block, 0, s, gray, tmp, H, W, taps, r1);
+    hipLaunchKernelGGL(vconv_f32_kernel, grid, block, 0, s, tmp, Is, H, W, taps, r1);
+    hipLaunchKernelGGL(edge_g_kernel, grid, block, 0, s, Is, g, H, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s) {
+    const dim3 grid(stream_blocks(a.hw, 8)), block(kThreads);
+    switch (NB) {
+        case 2: hipLaunchKernelGGL(mpass_kernel<2>, grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(mpass_kernel<4>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, edge);
+    const dim3 grid = tile_grid(a.H, a.W), block(kThreads);
+    hipError_t e = hipSuccess;
+    if (edge) {
+        if ((e = ensure_lds(step_kernel<1, true>, sm)) != hipSuccess) return e;
+        hipLaunchKernelGGL((step_kernel<1, true>), grid, block, sm, s, a);
+    } else {
+        switch (NB) {
+            case 1:
+                if ((e = ensure_lds(step_kernel<1, false>, sm)) != hipSuccess) return e;
+                hipLaunchKernelGGL((step_kernel<1, false>), grid, block, sm, s, a);
+                break;
+            case 2:
+                if ((e = ensure_lds(step_kernel<2, false>, sm)) != hipSuccess) return e;
+                hipLaunchKernelGGL((step_kernel<2, false>), grid, block, sm, s, a);
+                break;
+            case 4:
+                if ((e = ensure_lds(step_kernel<4, false>, sm)) != hipSuccess) return e;
+                hipLaunchKernelGGL((step_kernel<4, false>), grid, block, sm, s, a);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W, int WW,
+                           hipStream_t s) {
+    const long long n = (long long)H * W;
+    hipLaunchKernelGGL(mask_out_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bits[0], bits[1], st,
+                       mask, H, W, WW);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsf_out(const StepArgs &a, const uint32_t *const bits[2], int raw, float *out, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, 0);
+    const hipError_t e = ensure_lds(lsf_out_kernel, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lsf_out_kernel, tile_grid(a.H, a.W), dim3(kThreads), sm, s, a, bits[0], bits[1], raw, out);
+    return hipGetLastError();
+}
+
+}  // namespace lse

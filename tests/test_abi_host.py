@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and validates arguments before touching the device.  No GPU needed:
+none of these calls reaches a HIP runtime function."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1409_7474_amd import lse
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lse.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(lse_[a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_exports():
+    assert sorted(lse.EXPORTS) == declared_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lse.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version():
+    assert lse.status_str(0) == "LSE_OK"
+    assert lse.status_str(-2) == "LSE_ERR_BAD_VALUE"
+    assert lse.lse_version() >= 100
+
+
+def test_params_default():
+    p = lse.lse_params_default(256, 300, 4)
+    assert (p.height, p.width, p.bands, p.term, p.order) == (256, 300, 4, 0, 0)
+    assert p.dt == 15.0 and p.sigma == 1.0 and p.ksize == 7 and p.ksize_img == 9
+    assert p.edge_scale == 255.0 and p.reinit_every == 1
+
+
+def test_workspace_bytes_scales_with_image():
+    small = lse.lse_workspace_bytes(lse.make_params(256, 256, 1))
+    big = lse.lse_workspace_bytes(lse.make_params(4096, 4096, 4, sigma=1.5, ksize=11))
+    assert small > 256 * 256 * 4
+    # image (16 B/px) + two bit planes (1/4 B/px) + fixed overhead
+    assert 4096 * 4096 * 16 < big < 4096 * 4096 * 16.5 + 65536
+    edge = lse.lse_workspace_bytes(lse.make_params(1000, 1000, 3, term="edge"))
+    assert 1000 * 1000 * 12 < edge < 1000 * 1000 * 12.5 + 65536
+
+
+@pytest.mark.parametrize("field,value", [
+    ("height", 1), ("width", 0), ("bands", 0), ("bands", 5), ("term", 7), ("dt", 0.0),
+    ("dt", float("nan")), ("sigma", -1.0), ("ksize", 8), ("ksize", 33), ("image_dtype", 9),
+])
+def test_invalid_params_rejected(field, value):
+    p = lse.make_params(64, 64, 1)
+    setattr(p, field, value)
+    assert lse.lse_workspace_bytes(p) == 0
+    ctx = ctypes.c_void_p()
+    st = lse.load().lse_init(ctypes.byref(p), 16, 16, 256, 1 << 30, None, ctypes.byref(ctx))
+    assert st == lse.LSE_ERR_INVALID_ARG and not ctx.value
+
+
+def test_huge_image_rejected():
+    p = lse.make_params(65536, 65536, 1)
+    assert lse.lse_workspace_bytes(p) == 0
+
+
+def test_unsupported_modes_reported():
+    for kw in ({"order": "listing"}, {"storage": "f16"}, {"reinit_every": 0}):
+        p = lse.make_params(64, 64, 1, **kw)
+        ctx = ctypes.c_void_p()
+        st = lse.load().lse_init(ctypes.byref(p), 16, 16, 256, 1 << 30, None, ctypes.byref(ctx))
+        assert st == lse.LSE_ERR_UNSUPPORTED, kw
+
+
+def test_init_pointer_and_workspace_checks():
+    lib = lse.load()
+    p = lse.make_params(64, 64, 1)
+    need = lse.lse_workspace_bytes(p)
+    ctx = ctypes.c_void_p()
+    assert lib.lse_init(ctypes.byref(p), None, 16, 256, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_init(ctypes.byref(p), 16, None, 256, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_init(ctypes.byref(p), 18, 16, 256, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_init(ctypes.byref(p), 16, 16, 260, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_WORKSPACE
+    assert lib.lse_init(ctypes.byref(p), 16, 16, 256, need - 1, None, ctypes.byref(ctx)) == lse.LSE_ERR_WORKSPACE
+    assert lib.lse_init(ctypes.byref(p), 16, 16, None, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_WORKSPACE
+    assert lib.lse_init(None, 16, 16, 256, need, None, ctypes.byref(ctx)) == lse.LSE_ERR_INVALID_ARG
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = lse.load()
+    assert lib.lse_step(None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_run(None, 3, 0, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_mask(None, 16, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_lsf(None, 16, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_set_mask(None, 16, 0, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_stats(None, None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_profile(None, 1) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_step_bytes_per_pixel(None) == 0.0
+    lib.lse_destroy(None)

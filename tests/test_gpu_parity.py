@@ -1,0 +1,254 @@
+"""GPU (HIP, gfx950) parity with the FP64 oracle, through the C ABI.
+
+Bars:
+  * one step from identical state: the LSF after the step within 1e-5
+    max-abs, excluding only the Gaussian footprint of pixels whose oracle
+    update value |u| is below 1e-5 * max(1, dt) (a sign decision FP32 cannot
+    make like FP64 -- counted and reported, expected 0);
+  * whole runs: at most 1e-4 of the final mask's pixels differ in sign.
+Inputs are handed to the oracle exactly as the GPU received them (the float32
+or float16 values, promoted to float64).
+"""
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from paper_1409_7474_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+LSF_TOL = 1e-5
+MASK_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1409_7474_amd import lse
+    lse.load()
+    return torch.device("cuda:0")
+
+
+def _as_gpu(img, dev, dtype=torch.float32):
+    t = torch.tensor(img, dtype=dtype, device=dev)
+    return t, t.float().cpu().double().numpy()
+
+
+def _make(dev, img, mask, **kw):
+    from paper_1409_7474_amd import lse
+    return lse.LSE(img, torch.tensor(mask, dtype=torch.uint8, device=dev), **kw)
+
+
+def one_step(job, img64, *, term="region", dt=15.0, sigma=1.0, ts=7, g=None):
+    """Advance the GPU one iteration and compare with the oracle from the
+    GPU's own LSF.  Returns (max error outside ambiguity, ambiguous count)."""
+    phi = job.lsf().cpu().double().numpy()
+    ref = oracle.step(phi, img64 if term == "region" else None, term=term, dt=dt, sigma=sigma, ts=ts, g=g)
+    job.step()
+    got = job.lsf().cpu().double().numpy()
+    amb = np.abs(ref.u) < 1e-5 * max(1.0, dt)
+    excl = ndi.binary_dilation(amb, structure=np.ones((ts, ts), bool)) if amb.any() else amb
+    err = float(np.abs(got - ref.phi)[~excl].max()) if (~excl).any() else 0.0
+    return err, int(amb.sum()), ref
+
+
+def mask_disagreement(a, b):
+    return float(np.mean(a.astype(bool) != b.astype(bool)))
+
+
+# ------------------------------------------------------------ one step ---
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_tiny_workload_one_step_parity(dev, seed):
+    """256 x 256 x 1, three rectangles, sigma 1 / 7 x 7, dt 15: every one of
+    the first 12 iterations (the first starts from the binary LSF of eq. (13))."""
+    sc = synth.scene_tiny(seed)
+    img, img64 = _as_gpu(sc.image, dev)
+    job = _make(dev, img, sc.init_region, sigma=1.0, ksize=7)
+    for it in range(12):
+        err, amb, ref = one_step(job, img64, sigma=1.0, ts=7)
+        assert err <= LSF_TOL, (seed, it, err)
+        assert amb == 0, (seed, it, amb)
+        st = job.stats()
+        np.testing.assert_allclose(st["c_plus"], ref.c_plus, rtol=2e-6, atol=1e-7)
+        np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6, atol=1e-7)
+        assert st["M"] == pytest.approx(ref.M, rel=5e-6)
+
+
+@pytest.mark.parametrize("bands,h,w,ts,sigma", [
+    (4, 200, 333, 11, 1.5), (2, 97, 130, 7, 1.0), (3, 150, 77, 13, 2.0), (1, 65, 257, 9, 3.0),
+    (4, 130, 200, 31, 5.0),
+])
+def test_multiband_ragged_one_step_parity(dev, bands, h, w, ts, sigma):
+    sc = synth.scene_multiband(7, size=max(h, w), bands=bands, n_roofs=12, n_roads=2, height=h, width=w)
+    img, img64 = _as_gpu(sc.image, dev)
+    job = _make(dev, img, sc.init_region, sigma=sigma, ksize=ts)
+    for it in range(6):
+        err, amb, _ = one_step(job, img64, sigma=sigma, ts=ts)
+        assert err <= LSF_TOL, (it, err)
+        assert amb == 0
+
+
+@pytest.mark.parametrize("h,w,ts", [(2, 2, 3), (3, 5, 3), (5, 7, 31), (2, 100, 11), (40, 33, 7), (33, 65, 9),
+                                    (31, 2, 5)])
+def test_degenerate_shapes_one_step_parity(dev, h, w, ts):
+    """Images smaller than the template, one-pixel tails in the last bit word
+    and tile, two-pixel extents (one-sided gradients on both sides)."""
+    rng = np.random.default_rng(h * 1000 + w)
+    image = rng.random((h, w, 2))
+    mask = (rng.random((h, w)) > 0.5).astype(np.uint8)
+    mask[0, 0], mask[-1, -1] = 1, 0
+    img, img64 = _as_gpu(image, dev)
+    job = _make(dev, img, mask, sigma=1.0, ksize=ts)
+    for it in range(4):
+        err, _, _ = one_step(job, img64, sigma=1.0, ts=ts)
+        assert err <= LSF_TOL, (it, err)
+
+
+def test_edge_term_one_step_parity(dev):
+    sc = synth.scene_multiband(3, size=300, bands=4, n_roofs=10, n_roads=2, height=260, width=300)
+    img, img64 = _as_gpu(sc.image, dev)
+    g = oracle.edge_map(img64, 1.0, 9, 255.0)
+    job = _make(dev, img, sc.init_edge, term="edge", sigma=1.5, ksize=11, sigma_img=1.0, ksize_img=9)
+    for it in range(8):
+        err, amb, _ = one_step(job, img64, term="edge", sigma=1.5, ts=11, g=g)
+        assert err <= LSF_TOL, (it, err)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_half_precision_inputs(dev, dtype):
+    sc = synth.scene_multiband(4, size=160, bands=4, n_roofs=6, n_roads=1)
+    img, img64 = _as_gpu(sc.image, dev, dtype=dtype)
+    job = _make(dev, img, sc.init_region, sigma=1.0, ksize=7)
+    for it in range(4):
+        err, _, _ = one_step(job, img64, sigma=1.0, ts=7)
+        assert err <= LSF_TOL
+
+
+# --------------------------------------------------------- trajectories ---
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_tiny_workload_trajectory(dev, seed):
+    """Tiny workload, 100 iterations: final masks agree within 1e-4."""
+    sc = synth.scene_tiny(seed)
+    img, img64 = _as_gpu(sc.image, dev)
+    job = _make(dev, img, sc.init_region, sigma=1.0, ksize=7)
+    job.run(100)
+    got = job.mask().cpu().numpy()
+    ref = oracle.run(img64, sc.init_region, iters=100, sigma=1.0, ts=7)
+    assert mask_disagreement(got, ref.mask) <= MASK_TOL
+    assert job.stats()["iters_done"] == 100
+
+
+def test_multiband_trajectory_region_and_edge(dev):
+    sc = synth.scene_multiband(5, size=384, bands=4, n_roofs=10, n_roads=2)
+    img, img64 = _as_gpu(sc.image, dev)
+    for term, mask in (("region", sc.init_region), ("edge", sc.init_edge)):
+        job = _make(dev, img, mask, term=term, sigma=1.5, ksize=11)
+        job.run(60)
+        got = job.mask().cpu().numpy()
+        ref = oracle.run(img64, mask, term=term, iters=60, sigma=1.5, ts=11)
+        assert mask_disagreement(got, ref.mask) <= MASK_TOL, term
+
+
+def test_noise_free_rectangle_exact_and_stops(dev):
+    image, truth = synth.rectangle_scene()
+    img, img64 = _as_gpu(image, dev)
+    init = synth.centred_square(256, 256, 128, 128)
+    job = _make(dev, img, init, sigma=1.0, ksize=7)
+    job.run(300, stop_when_unchanged=True)
+    st = job.stats()
+    ref = oracle.run(img64, init, iters=300, stop_unchanged=True)
+    assert st["converged"] and st["iters_done"] == ref.iters_done
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), truth)
+
+
+# ------------------------------------------------------- state handling ---
+
+def test_initial_lsf_and_mask_roundtrip(dev):
+    sc = synth.scene_tiny(1, size=100, n_rects=2)
+    img, _ = _as_gpu(sc.image, dev)
+    job = _make(dev, img, sc.init_region)
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), sc.init_region)
+    np.testing.assert_array_equal(job.lsf().cpu().numpy(), np.where(sc.init_region > 0, 1.0, -1.0))
+    st = job.stats()
+    assert st["iters_done"] == 0 and st["n_plus"] == int(sc.init_region.sum())
+
+
+def test_runs_are_bitwise_deterministic(dev):
+    sc = synth.scene_multiband(6, size=256, bands=4, n_roofs=8, n_roads=2)
+    img, _ = _as_gpu(sc.image, dev)
+    outs = []
+    for _ in range(2):
+        job = _make(dev, img, sc.init_region, sigma=1.5, ksize=11)
+        job.run(25)
+        outs.append((job.lsf().cpu().numpy(), job.stats()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+
+
+def test_checkpoint_resume_is_bitwise(dev):
+    sc = synth.scene_multiband(8, size=256, bands=4, n_roofs=8, n_roads=2)
+    img, _ = _as_gpu(sc.image, dev)
+    full = _make(dev, img, sc.init_region, sigma=1.5, ksize=11)
+    full.run(9)
+    part = _make(dev, img, sc.init_region, sigma=1.5, ksize=11)
+    part.run(4)
+    ckpt = part.mask()
+    resumed = _make(dev, img, sc.init_region, sigma=1.5, ksize=11)
+    resumed.set_mask(ckpt, smoothed=True)
+    resumed.run(5)
+    np.testing.assert_array_equal(resumed.lsf().cpu().numpy(), full.lsf().cpu().numpy())
+    np.testing.assert_array_equal(resumed.mask().cpu().numpy(), full.mask().cpu().numpy())
+    # set_mask(smoothed=False) restarts from the binary LSF of eq. (13)
+    resumed.set_mask(torch.tensor(sc.init_region, device=dev), smoothed=False)
+    resumed.run(9)
+    np.testing.assert_array_equal(resumed.lsf().cpu().numpy(), full.lsf().cpu().numpy())
+
+
+def test_bad_values_are_reported(dev):
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_tiny(0, size=64, n_rects=1)
+    image = sc.image.copy()
+    image[10, 10, 0] = np.nan
+    img, _ = _as_gpu(image, dev)
+    job = _make(dev, img, sc.init_region)
+    job.run(3)
+    assert job.check() == lse.LSE_ERR_BAD_VALUE
+    assert job.stats()["bad_value"] and job.stats()["iters_done"] == 0
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), sc.init_region)
+
+
+def test_constant_image_moves_nothing(dev):
+    """A dyadic constant image: c+ == c- exactly, R == 0; Table I order then
+    only rounds corners (the square loses its 4 corner pixels)."""
+    img, img64 = _as_gpu(np.full((256, 256, 1), 0.25), dev)
+    sq = synth.centred_square(256, 256, 128, 128)
+    job = _make(dev, img, sq, sigma=1.0, ksize=7)
+    job.run(2)
+    ref = oracle.run(img64, sq, iters=2)
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), ref.mask)
+    assert job.stats()["M"] == 0.0
+
+
+# ----------------------------------------------------------- full sizes ---
+
+@pytest.mark.parametrize("term", ["region", "edge"])
+def test_large_multiband_one_step_parity(dev, term):
+    """4096 x 4096 x 4 scene (40 roofs, 6 roads), sigma 1.5 / 11 x 11, in the
+    launch configuration the benchmark times: one step from the GPU state
+    after 5 iterations, checked on every pixel."""
+    sc = synth.scene_large(0)
+    img, img64 = _as_gpu(sc.image, dev)
+    del sc.image
+    mask = sc.init_region if term == "region" else sc.init_edge
+    job = _make(dev, img, mask, term=term, sigma=1.5, ksize=11)
+    job.run(5)
+    g = oracle.edge_map(img64, 1.0, 9, 255.0) if term == "edge" else None
+    err, amb, _ = one_step(job, img64, term=term, sigma=1.5, ts=11, g=g)
+    assert err <= LSF_TOL
+    assert amb <= 16

@@ -386,9 +386,13 @@ lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream) {
     if (hipMemcpyAsync(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess) return LSE_ERR_DEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return LSE_ERR_DEVICE;
     memset(host_out, 0, sizeof(*host_out));
-    const Slot &cur = h.slot[h.iters % 3];
-    host_out->n_plus = cur.nplus;
-    host_out->flips = h.iters > 0 ? cur.flips : 0;
+    unsigned long long nplus = 0, flips = 0;
+    for (int i = 0; i < kBins; ++i) {
+        nplus += h.slot[h.iters % 3][i].nplus;
+        flips += h.slot[h.iters % 3][i].flips;
+    }
+    host_out->n_plus = nplus;
+    host_out->flips = h.iters > 0 ? flips : 0;
     host_out->iters_done = h.iters;
     host_out->converged = h.done;
     host_out->bad_value = h.bad ? 1 : 0;

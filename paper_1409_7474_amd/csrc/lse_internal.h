@@ -18,22 +18,37 @@ constexpr int kThreads = 256;    // 4 wave64 per workgroup
 constexpr int kRowWords = 5;     // bit words staged per row in LDS (4 used + 1 pad)
 constexpr uint64_t kNoFlips = ~0ull;  // "no previous iteration" marker
 
-// Region statistics of one LSF: fixed-point band sums over {phi >= 0}, the
-// count, and the flip count of the iteration that produced the LSF.
-struct Slot {
+constexpr int kBins = 64;             // accumulation lines (one per lane of a wave)
+
+// One accumulation line of the region statistics of one LSF: fixed-point band
+// sums over {phi >= 0}, the count, the flip count of the iteration that
+// produced the LSF, and the normaliser max|D| (float bits) used with it.
+// Workgroup w adds into line w % kBins, so atomics spread over kBins cache
+// lines instead of serialising on one; readers sum the lines (integer sums,
+// exact and order-independent).
+struct alignas(128) Bin {
     long long sum[4];
     unsigned long long nplus;
     unsigned long long flips;
-    unsigned long long pad[2];
+    unsigned int mbits;
+    unsigned int pad0;
+    unsigned long long pad[9];
 };
+static_assert(sizeof(Bin) == 128, "one bin per 128-byte line");
+
+// Per-image statistics lines (band totals, min / max keys), filled by init.
+struct alignas(128) ImgBin {
+    long long total[4];
+    unsigned int imin_key[4];
+    unsigned int imax_key[4];
+    unsigned long long pad[8];
+};
+static_assert(sizeof(ImgBin) == 128, "one bin per 128-byte line");
 
 // Device-resident state, at the start of the workspace.
 struct DevState {
-    Slot slot[3];                 // triple-buffered: read n%3, write (n+1)%3, clear (n+2)%3
-    long long total[4];           // fixed-point band sums over the whole image
-    unsigned int mbits[2];        // max|D| (float bits) per iteration parity
-    unsigned int imin_key[4];     // order-preserving keys of per-band min / max
-    unsigned int imax_key[4];
+    Bin slot[3][kBins];           // triple-buffered: read n%3, write (n+1)%3, clear (n+2)%3
+    ImgBin img[kBins];
     int bad;                      // nonzero: bad value found by init
     int done;                     // sticky "stopped" flag (Step 5)
     int iters;                    // iterations executed since init / set_mask

@@ -67,6 +67,76 @@ __device__ __forceinline__ float wave_min_f(float v) {
     return v;
 }
 
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_max_u(unsigned int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned int)__shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, (unsigned int)__shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// Totals of one statistics slot and of the image lines, reduced over the
+// kBins accumulation lines: wave 0 takes the slot (line i in lane i), wave 1
+// the image lines.  Called by every thread of the workgroup.
+struct Totals {
+    long long sum[4];
+    unsigned long long nplus, flips;
+    unsigned int mbits, pad;
+    long long total[4];
+    unsigned int imin_key[4], imax_key[4];
+};
+
+__device__ __forceinline__ void load_totals(const DevState *st, int sl, bool want_img, Totals *t) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        const Bin &b = st->slot[sl][lane];
+        long long v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = wave_sum_ll(b.sum[k]);
+        const long long np = wave_sum_ll((long long)b.nplus);
+        const long long fl = wave_sum_ll((long long)b.flips);
+        const unsigned int mb = wave_max_u(b.mbits);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t->sum[k] = v[k];
+            t->nplus = (unsigned long long)np;
+            t->flips = (unsigned long long)fl;
+            t->mbits = mb;
+        }
+    } else if (wave == 1 && want_img) {
+        const ImgBin &b = st->img[lane];
+        long long v[4];
+        unsigned int lo[4], hi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = wave_sum_ll(b.total[k]);
+            lo[k] = wave_min_u(b.imin_key[k]);
+            hi[k] = wave_max_u(b.imax_key[k]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                t->total[k] = v[k];
+                t->imin_key[k] = lo[k];
+                t->imax_key[k] = hi[k];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <int NB>
 struct Px {
     float v[NB];
@@ -93,15 +163,15 @@ __device__ __forceinline__ Px<NB> load_px(const float *__restrict__ img, long lo
 
 // Band means of eq. (15) from the fixed-point sums of one slot.
 template <int NB>
-__device__ __forceinline__ void slot_means(const DevState *st, int sl, long long hw, float inv_fix,
-                                           float (&cp)[NB], float (&cm)[NB]) {
-    const unsigned long long np = st->slot[sl].nplus;
+__device__ __forceinline__ void slot_means(const Totals &t, long long hw, float inv_fix, float (&cp)[NB],
+                                           float (&cm)[NB]) {
+    const unsigned long long np = t.nplus;
     const long long nm = hw - (long long)np;
     const float fnp = (float)np, fnm = (float)nm;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const long long S = st->slot[sl].sum[b];
-        const long long T = st->total[b];
+        const long long S = t.sum[b];
+        const long long T = t.total[b];
         cp[b] = np > 0 ? ((float)S * inv_fix) / fnp : 0.f;
         cm[b] = nm > 0 ? ((float)(T - S) * inv_fix) / fnm : 0.f;
     }
@@ -263,7 +333,7 @@ __device__ __forceinline__ void stats_tile(const TileSmem &s, const float *__res
 
 // Workgroup reduction of (NB sums, count, flips) and one atomic per value.
 template <int NB>
-__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Slot *out,
+__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Bin *out,
                                              float fix, bool with_sums) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (with_sums) {
@@ -305,26 +375,25 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
 
 // ------------------------------------------------------------- init kernels
 
+// Zero the statistics lines (and, unless keep_image_stats, the image lines and
+// the bad-value flag); mark slot 0 as having no previous iteration.
 __global__ void init_state_kernel(DevState *st, int keep_image_stats) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int s = 0; s < 3; ++s) {
-        for (int b = 0; b < 4; ++b) st->slot[s].sum[b] = 0;
-        st->slot[s].nplus = 0;
-        st->slot[s].flips = 0;
-    }
-    st->slot[0].flips = kNoFlips;
-    st->mbits[0] = st->mbits[1] = 0;
-    st->done = 0;
-    st->iters = 0;
-    for (int b = 0; b < 4; ++b) st->last_cp[b] = st->last_cm[b] = 0.f;
-    st->last_M = 0.f;
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(&st->slot[0][0]);
+    for (int i = threadIdx.x; i < (int)(sizeof(st->slot) / 8); i += blockDim.x) slots[i] = 0ull;
     if (!keep_image_stats) {
-        for (int b = 0; b < 4; ++b) {
-            st->total[b] = 0;
-            st->imin_key[b] = 0xffffffffu;
-            st->imax_key[b] = 0u;
-        }
-        st->bad = 0;
+        unsigned long long *img = reinterpret_cast<unsigned long long *>(&st->img[0]);
+        for (int i = threadIdx.x; i < (int)(sizeof(st->img) / 8); i += blockDim.x) img[i] = 0ull;
+    }
+    __syncthreads();
+    if (!keep_image_stats && threadIdx.x < kBins)
+        for (int b = 0; b < 4; ++b) st->img[threadIdx.x].imin_key[b] = 0xffffffffu;
+    if (threadIdx.x == 0) {
+        st->slot[0][0].flips = kNoFlips;
+        st->done = 0;
+        st->iters = 0;
+        for (int b = 0; b < 4; ++b) st->last_cp[b] = st->last_cm[b] = 0.f;
+        st->last_M = 0.f;
+        if (!keep_image_stats) st->bad = 0;
     }
 }
 
@@ -377,28 +446,35 @@ __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restric
             }
         }
     }
-    __shared__ float red[kThreads / 64][4];
+    __shared__ float red[kThreads / 64][4][3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (bad) st->bad = 1;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        if (b >= B) break;
         const float s = wave_sum_f(sum[b]);
         const float lo = wave_min_f(mn[b]);
         const float hi = wave_max_f(mx[b]);
         if (lane == 0) {
-            red[wave][b] = s;
-            atomicMin(&st->imin_key[b], float_key(lo));
-            atomicMax(&st->imax_key[b], float_key(hi));
+            red[wave][b][0] = s;
+            red[wave][b][1] = lo;
+            red[wave][b][2] = hi;
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && !want_gray) {
+    if (threadIdx.x == 0) {
+        ImgBin &bin = st->img[blockIdx.x % kBins];
         for (int b = 0; b < B; ++b) {
-            float s = 0.f;
-            for (int w = 0; w < kThreads / 64; ++w) s += red[w][b];
-            atomicAdd(reinterpret_cast<unsigned long long *>(&st->total[b]),
-                      (unsigned long long)__float2ll_rn(s * fix));
+            float s = 0.f, lo = INFINITY, hi = -INFINITY;
+            for (int w = 0; w < kThreads / 64; ++w) {
+                s += red[w][b][0];
+                lo = fminf(lo, red[w][b][1]);
+                hi = fmaxf(hi, red[w][b][2]);
+            }
+            if (!want_gray)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&bin.total[b]),
+                          (unsigned long long)__float2ll_rn(s * fix));
+            atomicMin(&bin.imin_key[b], float_key(lo));
+            atomicMax(&bin.imax_key[b], float_key(hi));
         }
     }
 }
@@ -429,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StepArgs A, int raw, in
     float acc[NB];
     int cnt;
     stats_tile<NB>(s, static_cast<const float *>(A.img), x0, y0, A.H, A.W, A.r, A.ts, A.nch, raw, acc, cnt);
-    reduce_commit<NB>(s, acc, cnt, 0, &A.st->slot[slot], A.fix, true);
+    reduce_commit<NB>(s, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
 }
 
 // ------------------------------------------------------------ edge map init
@@ -493,9 +569,12 @@ template <int NB>
 __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
     DevState *st = A.st;
     const int sl = A.n % 3;
-    if (st->done || st->bad || (A.stop && st->slot[sl].flips == 0)) return;
+    __shared__ Totals tot;
+    __shared__ float wmax[kThreads / 64];
+    load_totals(st, sl, true, &tot);
+    if (st->done || st->bad || (A.stop && tot.flips == 0)) return;
     float cp[NB], cm[NB], a[NB], m[NB];
-    slot_means<NB>(st, sl, A.hw, A.inv_fix, cp, cm);
+    slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         a[b] = cp[b] - cm[b];
@@ -506,7 +585,12 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < A.hw; i += (long long)gridDim.x * kThreads)
         mx = fmaxf(mx, fabsf(region_D<NB>(load_px<NB>(img, i), a, m)));
     mx = wave_max_f(mx);
-    if ((threadIdx.x & 63) == 0) atomicMax(&st->mbits[A.n & 1], __float_as_uint(mx));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
+        atomicMax(&st->slot[sl][blockIdx.x % kBins].mbits, __float_as_uint(mx));
+    }
 }
 
 // ------------------------------------------------------------------- step
@@ -514,12 +598,15 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
 template <int NB, bool EDGE>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
     extern __shared__ float smem[];
+    __shared__ Totals tot;
     DevState *st = A.st;
     const int sl = A.n % 3;
-    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
+    load_totals(st, sl, !EDGE, &tot);
     {
         int done = st->done | st->bad;
-        if (!done && A.stop && st->slot[sl].flips == 0) done = 1;
+        if (!done && A.stop && tot.flips == 0) done = 1;
         if (done) {
             if (lead && !st->bad) st->done = 1;
             return;
@@ -545,7 +632,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
     float a[NB], m[NB], w = 0.f;
     float cp[NB], cm[NB], M = 0.f;
     if constexpr (!EDGE) {
-        slot_means<NB>(st, sl, A.hw, A.inv_fix, cp, cm);
+        slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             a[b] = cp[b] - cm[b];
@@ -553,11 +640,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
         }
         if constexpr (NB == 1) {
             Px<1> lo, hi;
-            lo.v[0] = key_float(st->imin_key[0]);
-            hi.v[0] = key_float(st->imax_key[0]);
+            lo.v[0] = key_float(tot.imin_key[0]);
+            hi.v[0] = key_float(tot.imax_key[0]);
             M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
         } else {
-            M = __uint_as_float(st->mbits[A.n & 1]);
+            M = __uint_as_float(tot.mbits);
         }
         w = M > 0.f ? A.dt / M : 0.f;
     }
@@ -651,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
         }
     }
 
-    Slot *out = &st->slot[(A.n + 1) % 3];
+    Bin *out = &st->slot[(A.n + 1) % 3][block_linear_id() % kBins];
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.f;
@@ -662,12 +749,12 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
     }
     reduce_commit<NB>(s, acc, cnt, flips, out, A.fix, !EDGE);
 
+    if (lead_block) {
+        // Clear the slot of iteration n + 2 (nobody reads or writes it now).
+        unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
+        for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+    }
     if (lead) {
-        Slot &z = st->slot[(A.n + 2) % 3];
-        for (int b = 0; b < 4; ++b) z.sum[b] = 0;
-        z.nplus = 0;
-        z.flips = 0;
-        st->mbits[(A.n + 1) & 1] = 0u;
         st->iters += 1;
         if constexpr (!EDGE) {
             for (int b = 0; b < NB; ++b) {
@@ -751,12 +838,12 @@ static inline unsigned int stream_blocks(long long n, int per_thread = 1) {
 }
 
 hipError_t launch_init_state(DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, 0);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, s, st, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_reset_state(DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, 1);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, s, st, 1);
     return hipGetLastError();
 }
 
@@ -824,7 +911,10 @@ hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, in
 }
 
 hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s) {
-    const dim3 grid(stream_blocks(a.hw, 8)), block(kThreads);
+    long long nb = (a.hw + (long long)kThreads * 16 - 1) / ((long long)kThreads * 16);
+    if (nb > 2048) nb = 2048;
+    if (nb < 1) nb = 1;
+    const dim3 grid((unsigned)nb), block(kThreads);
     switch (NB) {
         case 2: hipLaunchKernelGGL(mpass_kernel<2>, grid, block, 0, s, a); break;
         case 4: hipLaunchKernelGGL(mpass_kernel<4>, grid, block, 0, s, a); break;

@@ -766,6 +766,485 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
     }
 }
 
+// ------------------------------------------------------------- fast step
+//
+// Same arithmetic as step_kernel, organised for throughput when the template
+// radius R is a compile-time constant: tiles of 96 owned columns x 64 owned
+// rows, lanes mapped to columns, each wave taking a vertical segment of rows
+// so that the vertical Gaussian runs over a register window (each horizontal
+// sum computed once per segment).  The 6-bit lookup tables live in one VGPR
+// per chunk and are read with ds_bpermute (a crossbar, no bank conflicts).
+
+constexpr int kFX = 96;        // owned columns (3 bit words)
+constexpr int kFY = 64;        // owned rows
+constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 - 1 .. x0/32 + 4
+constexpr int kPStride = 128;  // phi row stride in floats
+
+constexpr int kSB = 8;         // rows per block of the rolling vertical window
+
+template <int R, bool EDGE>
+struct FastGeom {
+    static constexpr int TS = 2 * R + 1;
+    static constexpr int RU = EDGE ? 0 : R;      // halo of the binarised field
+    static constexpr int UH = kFY + 2 * RU;      // rows where b^n is computed
+    static constexpr int PH = UH + 2;            // rows of phi^n
+    static constexpr int PW = kFX + 2 * RU + 2;  // columns of phi^n (<= 128)
+    static constexpr int NBLK = (PH + 2 * kSB - 1) / (2 * kSB);  // window blocks per segment
+    static constexpr int SEG = NBLK * kSB;       // phi rows per wave (2 segments x 2 chunks)
+    static constexpr int PHP = 2 * SEG;          // phi rows allocated (>= PH)
+    static constexpr int BH = PHP + 2 * R;       // staged rows of b^{n-1}
+    static constexpr int SEGD = kFY / 2;         // statistics rows per wave
+    static constexpr int NCH = (TS + 5) / 6;     // lookup chunks
+    static constexpr int smem_words = BH * kFWords + PHP * kPStride + UH * kFWords + BH * 2 + 16;
+};
+
+template <int NCH>
+__device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, int (&lut)[NCH]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) lut[c] = __float_as_int(taps->lut[c][lane]);
+}
+
+// Horizontal Gaussian of a binary row, as hconv_bits; must be called with all
+// 64 lanes active (ds_bpermute).  `border` (uniform) enables the zero-padding
+// correction, needed only by tiles that touch the left or right image edge.
+template <int R, int NCH>
+__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, int x, int W, bool border,
+                                            const int (&lut)[NCH], const float *__restrict__ cum) {
+    constexpr int TS = 2 * R + 1;
+    constexpr uint32_t FULL = (1u << TS) - 1u;
+    const int ws = xb - R;
+    const int wi = ws >> 5;
+    uint32_t win = __builtin_amdgcn_alignbit(row[wi + 1], row[wi], (uint32_t)(ws & 31)) & FULL;
+    float corr = 0.f;
+    if (border) {
+        const int left = min(R - x, TS);
+        const int right = min(x + R - (W - 1), TS);
+        if (left > 0) {
+            win |= (1u << left) - 1u;
+            corr = cum[left];
+        }
+        if (right > 0) {
+            win |= FULL & ~((1u << (TS - right)) - 1u);
+            corr += cum[right];
+        }
+    }
+    float h = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int idx = (int)((win >> (6 * c)) & 63u);
+        h += __int_as_float(__builtin_amdgcn_ds_bpermute(idx << 2, lut[c]));
+    }
+    return h - corr;
+}
+
+__device__ __forceinline__ uint32_t bits_extract(unsigned long long m, int off, int k) {
+    const int d = 32 * k - off;  // right shift that brings word k of the row to bit 0
+    if (d >= 64 || d <= -32) return 0u;
+    return d >= 0 ? (uint32_t)(m >> d) : (uint32_t)(m << (-d));
+}
+
+// 0 if bits [lo, hi) of a staged row are all 0, 1 if all 1, 2 if mixed.
+__device__ __forceinline__ int range_code(const uint32_t *row, int lo, int hi) {
+    uint32_t any1 = 0u, any0 = 0u;
+    const int j0 = lo >> 5, j1 = (hi - 1) >> 5;
+    for (int j = j0; j <= j1; ++j) {
+        uint32_t m = ~0u;
+        if (j == j0) m &= ~0u << (lo & 31);
+        if (j == j1) m &= ~0u >> (31 - ((hi - 1) & 31));
+        any1 |= row[j] & m;
+        any0 |= ~row[j] & m;
+    }
+    return (any1 && any0) ? 2 : (any1 ? 1 : 0);
+}
+
+// Wave-uniform test: do rows [row0, row0 + n) all carry code c (0 or 1)?
+// Returns 1 (all ones), 0 (all zeros) or -1.  n <= 64.
+__device__ __forceinline__ int block_code(const int *codes, int row0, int n, int chunk) {
+    const int lane = threadIdx.x & 63;
+    const int c = lane < n ? codes[(row0 + lane) * 2 + chunk] : -1;
+    const unsigned long long full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    if (__ballot(c == 1) == full) return 1;
+    if (__ballot(c == 0) == full) return 0;
+    return -1;
+}
+
+// Stage bit rows [row0, row0 + nrows) of global words x0/32 - 1 .. x0/32 + 4.
+__device__ __forceinline__ void stage_bits_fast(uint32_t *dst, const uint32_t *__restrict__ bits, int row0,
+                                                int nrows, int x0, int H, int WW) {
+    const int wb0 = (x0 >> 5) - 1;
+    for (int i = threadIdx.x; i < nrows * kFWords; i += kThreads) {
+        const int row = i / kFWords, wc = i - row * kFWords;
+        const int y = row0 + row, gw = wb0 + wc;
+        uint32_t v = 0;
+        if (wc < kFWords - 1 && y >= 0 && y < H && gw >= 0 && gw < WW) v = bits[(size_t)y * WW + gw];
+        dst[i] = v;
+    }
+}
+
+// Codes of the owned-column spans of the U rows (b^n): chunk 0 = owned
+// columns 0..63, chunk 1 = 64..95, each with its R halo.
+template <int R>
+__device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, int *codes) {
+    for (int i = threadIdx.x; i < nrows * 2; i += kThreads) {
+        const int row = i >> 1, c = i & 1;
+        codes[i] = c == 0 ? range_code(bn + row * kFWords, 32 - R, 96 + R)
+                          : range_code(bn + row * kFWords, 96 - R, 128 + R);
+    }
+}
+
+// Statistics of phi^{n+1} = G * b on the owned 96 x 64 tile (b in `bn`, rows
+// y0 - R .. y0 + 64 + R, bit 0 of each row = column x0 - 32).  raw: phi = b.
+// Every owned pixel of the image is read once (dense streaming); blocks of
+// 8 rows whose whole bit window is uniform take the sign without the
+// Gaussian sums (their value would be the same constant in every pixel).
+template <int R, int NB>
+__device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes, const float *__restrict__ img,
+                                           int x0, int y0, int H, int W, bool border, bool raw,
+                                           const int (&lut)[FastGeom<R, false>::NCH], const float (&kk)[2 * R + 1],
+                                           const float *__restrict__ cum, float (&acc)[NB], int &cnt) {
+    using G = FastGeom<R, false>;
+    static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = wave & 1, seg = wave >> 1;
+    const int ox = chunk * 64 + lane;
+    const int x = x0 + ox;
+    const bool colok = ox < kFX && x < W;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    cnt = 0;
+    const int urow0 = seg * G::SEGD;  // U row of output row 0 of this segment's window
+    auto accumulate = [&](int oy, bool inside) {
+        const int y = y0 + oy;
+        if (colok && y < H) {
+            const Px<NB> p = load_px<NB>(img, (long long)y * W + x);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] += inside ? p.v[b] : 0.f;
+            cnt += inside ? 1 : 0;
+        }
+    };
+    if (raw) {
+        for (int j = 0; j < G::SEGD; ++j) {
+            const int oy = urow0 + j;
+            const uint32_t wd = bn[(oy + R) * kFWords + ((ox + 32) >> 5)];
+            accumulate(oy, (wd >> ((ox + 32) & 31)) & 1u);
+        }
+        return;
+    }
+    constexpr int NW = 2 * R + kSB;
+    float win[NW];
+    bool have_win = false;  // win[0 .. 2R) holds rows rb .. rb + 2R of the current block
+#pragma unroll 1
+    for (int blk = 0; blk < G::SEGD / kSB; ++blk) {
+        const int rb = urow0 + blk * kSB;
+        const int yb = y0 - R + rb;  // image row of U row rb
+        int uni = -1;
+        if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
+        if (uni >= 0) {
+#pragma unroll
+            for (int j = 0; j < kSB; ++j) accumulate(rb + j, uni == 1);
+            have_win = false;
+            continue;
+        }
+        if (!have_win) {
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) {
+                const int y = yb + t;
+                const float v = hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, x, W, border, lut, cum);
+                win[t] = (y >= 0 && y < H) ? v : 0.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kSB; ++t) {
+            const int urow = rb + 2 * R + t;
+            const int y = y0 - R + urow;
+            const float v = hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, x, W, border, lut, cum);
+            win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kSB; ++j) {
+            float ph = 0.f;
+#pragma unroll
+            for (int i = 0; i < 2 * R + 1; ++i) ph = fmaf(kk[i], win[j + i], ph);
+            accumulate(rb + j, ph >= 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
+        have_win = true;
+    }
+}
+
+template <int R, int NB, bool EDGE>
+__global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
+    using G = FastGeom<R, EDGE>;
+    constexpr int TS = G::TS;
+    extern __shared__ float smem[];
+    __shared__ Totals tot;
+    __shared__ float red[kThreads / 64 * 8];
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
+    load_totals(st, sl, !EDGE, &tot);
+    {
+        int done = st->done | st->bad;
+        if (!done && A.stop && tot.flips == 0) done = 1;
+        if (done) {
+            if (lead && !st->bad) st->done = 1;
+            return;
+        }
+    }
+    const int H = A.H, W = A.W;
+    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * kFY;
+    const int by0 = y0 - G::RU - 1 - R;              // image row of staged bit row 0
+    const int px0 = x0 - G::RU - 1, py0 = y0 - G::RU - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
+    float *s_phi = smem + G::BH * kFWords;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PHP * kPStride);
+    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);  // [max(BH, UH)][2]
+    uint32_t *s_const = reinterpret_cast<uint32_t *>(s_codes + G::BH * 2);  // all-ones / all-zeros rows
+
+    int lut[G::NCH];
+    load_luts<G::NCH>(A.taps, lut);
+    float kk[TS];
+#pragma unroll
+    for (int i = 0; i < TS; ++i) kk[i] = A.taps->k[i];
+    const float *cum = A.taps->cum;
+
+    stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
+
+    float a[NB], m[NB], w = 0.f;
+    float cp[NB], cm[NB], M = 0.f;
+    if constexpr (!EDGE) {
+        slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            a[b] = cp[b] - cm[b];
+            m[b] = cp[b] + cm[b];
+        }
+        if constexpr (NB == 1) {
+            Px<1> lo, hi;
+            lo.v[0] = key_float(tot.imin_key[0]);
+            hi.v[0] = key_float(tot.imax_key[0]);
+            M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
+        } else {
+            M = __uint_as_float(tot.mbits);
+        }
+        w = M > 0.f ? A.dt / M : 0.f;
+    }
+    __syncthreads();
+    // Codes of the staged rows over each chunk's window span, and the LSF
+    // value of an all-ones / all-zeros window (same arithmetic as any pixel).
+    for (int i = tid; i < G::BH * 2; i += kThreads) {
+        const int row = i >> 1, c = i & 1;
+        s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, 95 - G::RU + R)
+                            : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
+    }
+    float phi_one = 0.f, phi_zero = 0.f;
+    {
+        const float h1 = hconv_fast<R, G::NCH>(s_const, 64, 64, 1 << 30, false, lut, cum);
+        const float h0 = hconv_fast<R, G::NCH>(s_const + 8, 64, 64, 1 << 30, false, lut, cum);
+#pragma unroll
+        for (int i = 0; i < TS; ++i) {
+            phi_one = fmaf(kk[i], h1, phi_one);
+            phi_zero = fmaf(kk[i], h0, phi_zero);
+        }
+    }
+    __syncthreads();
+
+    // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
+    {
+        const int chunk = wave & 1, seg = wave >> 1;
+        const int p = chunk * 64 + lane;
+        const int x = px0 + p;
+        const int xb = x - x0 + 32;
+        const bool colok = p < G::PW && x >= 0 && x < W;
+        if (A.raw) {
+            for (int j = 0; j < G::SEG; ++j) {
+                const int q = seg * G::SEG + j, y = py0 + q;
+                float v = 0.f;
+                if (colok && y >= 0 && y < H) {
+                    const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
+                    v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+                }
+                s_phi[q * kPStride + p] = v;
+            }
+        } else {
+            constexpr int NW = 2 * R + kSB;
+            float win[NW];
+            const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
+            bool have_win = false;
+#pragma unroll 1
+            for (int blk = 0; blk < G::NBLK; ++blk) {
+                const int rb = brow0 + blk * kSB;
+                int uni = -1;
+                if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
+                    uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
+                if (uni >= 0) {
+                    const float v = uni ? phi_one : phi_zero;
+#pragma unroll
+                    for (int j = 0; j < kSB; ++j) {
+                        const int q = rb + j, y = py0 + q;
+                        s_phi[q * kPStride + p] = (colok && y >= 0 && y < H) ? v : 0.f;
+                    }
+                    have_win = false;
+                    continue;
+                }
+                if (!have_win) {
+#pragma unroll
+                    for (int t = 0; t < 2 * R; ++t) {
+                        const int y = by0 + rb + t;
+                        const float v =
+                            hconv_fast<R, G::NCH>(s_bits + (rb + t) * kFWords, xb, x, W, border, lut, cum);
+                        win[t] = (y >= 0 && y < H) ? v : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kSB; ++t) {
+                    const int brow = rb + 2 * R + t;
+                    const int y = by0 + brow;
+                    const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
+                    win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
+                }
+#pragma unroll
+                for (int j = 0; j < kSB; ++j) {
+                    float ph = 0.f;
+#pragma unroll
+                    for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                    const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
+                    s_phi[q * kPStride + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
+                }
+#pragma unroll
+                for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
+                have_win = true;
+            }
+        }
+    }
+    __syncthreads();
+
+    // C: update eq. (18) and binarisation on U = tile + RU halo, one row per
+    // wave task, two 64-lane chunks per row; owned words go to global memory.
+    int flips = 0;
+    for (int uy = wave; uy < G::UH; uy += kThreads / 64) {
+        const int y = y0 - G::RU + uy;
+        const bool rowok = y >= 0 && y < H;
+        unsigned long long mk[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int xb = 32 - G::RU + c * 64 + lane;
+            const int x = x0 - 32 + xb;
+            bool pred = false;
+            if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
+                const int p = c * 64 + lane + 1;
+                const float *cc = s_phi + (uy + 1) * kPStride + p;
+                float gx, gy;
+                if (x == 0)
+                    gx = cc[1] - cc[0];
+                else if (x == W - 1)
+                    gx = cc[0] - cc[-1];
+                else
+                    gx = 0.5f * (cc[1] - cc[-1]);
+                if (y == 0)
+                    gy = cc[kPStride] - cc[0];
+                else if (y == H - 1)
+                    gy = cc[0] - cc[-kPStride];
+                else
+                    gy = 0.5f * (cc[kPStride] - cc[-kPStride]);
+                if (gx == 0.f && gy == 0.f) {
+                    pred = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                } else {
+                    const float gm = sqrtf(gx * gx + gy * gy);
+                    const long long pix = (long long)y * W + x;
+                    float coef;
+                    if constexpr (EDGE) {
+                        coef = A.dt * static_cast<const float *>(A.img)[pix];
+                    } else {
+                        coef = w * region_D<NB>(load_px<NB>(static_cast<const float *>(A.img), pix), a, m);
+                    }
+                    pred = fmaf(coef, gm, cc[0]) >= 0.f;
+                }
+            }
+            mk[c] = __ballot(pred);
+        }
+        if (lane < kFWords) {
+            const uint32_t word =
+                bits_extract(mk[0], 32 - G::RU, lane) | bits_extract(mk[1], 96 - G::RU, lane);
+            s_bn[uy * kFWords + lane] = word;
+            const int gw = (x0 >> 5) - 1 + lane;
+            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                const int xs = gw * 32;
+                const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                const uint32_t nw = word & valid;
+                const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                A.bits_out[(size_t)y * A.WW + gw] = nw;
+                flips += __popc(nw ^ ow);
+            }
+        }
+    }
+    __syncthreads();
+
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    int cnt = 0;
+    if constexpr (!EDGE) {
+        code_rows_owned<R>(s_bn, G::UH, s_codes);
+        __syncthreads();
+        stats_fast<R, NB>(s_bn, s_codes, static_cast<const float *>(A.img), x0, y0, H, W, border, false, lut, kk,
+                          cum, acc, cnt);
+    }
+    TileSmem rs;
+    rs.red = red;
+    reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][block_linear_id() % kBins], A.fix, !EDGE);
+
+    if (lead_block) {
+        unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
+        for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+    }
+    if (lead) {
+        st->iters += 1;
+        if constexpr (!EDGE) {
+            for (int b = 0; b < NB; ++b) {
+                st->last_cp[b] = cp[b];
+                st->last_cm[b] = cm[b];
+            }
+            st->last_M = M;
+        }
+    }
+}
+
+// Region statistics on the fast tiling (used at init and by set_mask so that
+// its partial sums equal the step kernel's bit for bit).
+template <int R, int NB>
+__global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int raw, int slot) {
+    extern __shared__ float smem[];
+    __shared__ float red[kThreads / 64 * 8];
+    using G = FastGeom<R, false>;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
+    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * kFY;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > A.W;
+    int lut[G::NCH];
+    load_luts<G::NCH>(A.taps, lut);
+    float kk[2 * R + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * R + 1; ++i) kk[i] = A.taps->k[i];
+    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);
+    stage_bits_fast(s_bn, A.bits_in, y0 - R, G::UH, x0, A.H, A.WW);
+    __syncthreads();
+    code_rows_owned<R>(s_bn, G::UH, s_codes);
+    __syncthreads();
+    float acc[NB];
+    int cnt;
+    stats_fast<R, NB>(s_bn, s_codes, static_cast<const float *>(A.img), x0, y0, A.H, A.W, border, raw != 0, lut,
+                      kk, A.taps->cum, acc, cnt);
+    TileSmem rs;
+    rs.red = red;
+    reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
+}
+
 // --------------------------------------------------------------- exports
 
 __global__ void mask_out_kernel(const uint32_t *__restrict__ b0, const uint32_t *__restrict__ b1,
@@ -878,7 +1357,7 @@ hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, i
 
 size_t tile_smem_bytes(int r, int nch, int edge) { return tile_smem_words(r, nch, edge) * 4; }
 
-hipError_t launch_stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+hipError_t launch_stats_generic(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
     const size_t sm = tile_smem_bytes(a.r, a.nch, 0);
     const dim3 grid = tile_grid(a.H, a.W);
     hipError_t e = hipSuccess;
@@ -923,7 +1402,46 @@ hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s) {
+template <int R, int NB, bool EDGE>
+static hipError_t launch_step_fast_t(const StepArgs &a, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
+    const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE>, sm);
+    if (e != hipSuccess) return e;
+    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFY - 1) / kFY);
+    hipLaunchKernelGGL((step_fast_kernel<R, NB, EDGE>), grid, dim3(kThreads), sm, s, a);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_step_fast_r(const StepArgs &a, int NB, int edge, hipStream_t s) {
+    if (edge) return launch_step_fast_t<R, 1, true>(a, s);
+    switch (NB) {
+        case 1: return launch_step_fast_t<R, 1, false>(a, s);
+        case 2: return launch_step_fast_t<R, 2, false>(a, s);
+        case 4: return launch_step_fast_t<R, 4, false>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int R, int NB>
+static hipError_t launch_stats_fast_t(const StepArgs &a, int raw, int slot, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, false>::UH * (kFWords + 2) * 4;
+    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFY - 1) / kFY);
+    hipLaunchKernelGGL((stats_fast_kernel<R, NB>), grid, dim3(kThreads), sm, s, a, raw, slot);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_stats_fast_r(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+    switch (NB) {
+        case 1: return launch_stats_fast_t<R, 1>(a, raw, slot, s);
+        case 2: return launch_stats_fast_t<R, 2>(a, raw, slot, s);
+        case 4: return launch_stats_fast_t<R, 4>(a, raw, slot, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_step_generic(const StepArgs &a, int NB, int edge, hipStream_t s) {
     const size_t sm = tile_smem_bytes(a.r, a.nch, edge);
     const dim3 grid = tile_grid(a.H, a.W), block(kThreads);
     hipError_t e = hipSuccess;
@@ -944,10 +1462,37 @@ hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s) {
                 if ((e = ensure_lds(step_kernel<4, false>, sm)) != hipSuccess) return e;
                 hipLaunchKernelGGL((step_kernel<4, false>), grid, block, sm, s, a);
                 break;
-            default: return hipErrorInvalidValue;
+            default:
+                return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
+}
+
+// The statistics kernel must use the same tiling as the step kernel that
+// would have produced the statistics, so that resumed runs match bit for bit.
+hipError_t launch_stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+    switch (a.r) {
+        case 3: return launch_stats_fast_r<3>(a, NB, raw, slot, s);
+        case 4: return launch_stats_fast_r<4>(a, NB, raw, slot, s);
+        case 5: return launch_stats_fast_r<5>(a, NB, raw, slot, s);
+        case 6: return launch_stats_fast_r<6>(a, NB, raw, slot, s);
+        case 7: return launch_stats_fast_r<7>(a, NB, raw, slot, s);
+        default: break;
+    }
+    return launch_stats_generic(a, NB, raw, slot, s);
+}
+
+hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s) {
+    switch (a.r) {
+        case 3: return launch_step_fast_r<3>(a, NB, edge, s);
+        case 4: return launch_step_fast_r<4>(a, NB, edge, s);
+        case 5: return launch_step_fast_r<5>(a, NB, edge, s);
+        case 6: return launch_step_fast_r<6>(a, NB, edge, s);
+        case 7: return launch_step_fast_r<7>(a, NB, edge, s);
+        default: break;
+    }
+    return launch_step_generic(a, NB, edge, s);
 }
 
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W, int WW,

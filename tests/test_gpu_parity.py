@@ -88,7 +88,7 @@ def test_tiny_workload_one_step_parity(dev, seed):
 
 @pytest.mark.parametrize("bands,h,w,ts,sigma", [
     (4, 200, 333, 11, 1.5), (2, 97, 130, 7, 1.0), (3, 150, 77, 13, 2.0), (1, 65, 257, 9, 3.0),
-    (4, 130, 200, 31, 5.0),
+    (4, 130, 200, 31, 5.0), (4, 180, 250, 15, 2.5), (1, 300, 420, 9, 1.5),
 ])
 def test_multiband_ragged_one_step_parity(dev, bands, h, w, ts, sigma):
     sc = synth.scene_multiband(7, size=max(h, w), bands=bands, n_roofs=12, n_roads=2, height=h, width=w)

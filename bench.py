@@ -41,7 +41,23 @@ def parse():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations per term in the CPU sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="instead of the benchmark, run a plain device copy of this many MiB (reads and writes "
+                         "that many bytes) so that profiler byte counters can be scaled against a known size")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy kernel of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "launches": 3}), flush=True)
 
 
 def make_scene(name):
@@ -77,6 +93,9 @@ def cpu_baseline(scene, sigma, ksize, iters, terms):
 
 def main():
     args = parse()
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "

@@ -24,6 +24,7 @@ struct lse_ctx {
     DevState *st;
     Taps *taps;
     float *img;         // region: storage image; edge: edge map g
+    float *boxes;       // region, B > 1: per-block band min / max for the normaliser
     uint32_t *bits[2];
     float *tmp[2];
     Taps host_taps;
@@ -81,7 +82,7 @@ lse_status validate(const lse_params *p) {
 }
 
 struct Layout {
-    size_t state, taps, img, bits0, bits1, tmp0, tmp1, total;
+    size_t state, taps, img, boxes, bits0, bits1, tmp0, tmp1, total;
 };
 
 Layout layout_of(const lse_params *p) {
@@ -96,6 +97,11 @@ Layout layout_of(const lse_params *p) {
     o = align_up(o + sizeof(Taps));
     L.img = o;
     o = align_up(o + (p->term == LSE_TERM_REGION ? hw * NB * 4 : hw * 4));
+    L.boxes = 0;
+    if (p->term == LSE_TERM_REGION && NB > 1) {
+        L.boxes = o;
+        o = align_up(o + mbox_floats(p->height, p->width, NB) * 4);
+    }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
     L.bits1 = o;
@@ -168,6 +174,7 @@ inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 StepArgs step_args(const lse_ctx *c) {
     StepArgs a;
     a.img = c->img;
+    a.boxes = c->boxes;
     a.bits_in = c->bits[c->n & 1];
     a.bits_out = c->bits[(c->n + 1) & 1];
     a.st = c->st;
@@ -298,6 +305,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     c->st = reinterpret_cast<DevState *>(base + L.state);
     c->taps = reinterpret_cast<Taps *>(base + L.taps);
     c->img = reinterpret_cast<float *>(base + L.img);
+    c->boxes = L.boxes ? reinterpret_cast<float *>(base + L.boxes) : nullptr;
     c->bits[0] = reinterpret_cast<uint32_t *>(base + L.bits0);
     c->bits[1] = reinterpret_cast<uint32_t *>(base + L.bits1);
     c->tmp[0] = L.tmp0 ? reinterpret_cast<float *>(base + L.tmp0) : nullptr;
@@ -314,6 +322,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     if (e == hipSuccess) {
         if (p->term == LSE_TERM_REGION) {
             e = launch_init_image(image_dev, p->image_dtype, p->bands, c->NB, c->img, c->hw, c->st, c->fix, 0, 0.f, st);
+            if (e == hipSuccess && c->NB > 1) e = launch_mbox(c->img, p->height, p->width, c->NB, c->boxes, st);
         } else {
             e = launch_init_image(image_dev, p->image_dtype, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
                                   p->edge_scale, st);

@@ -22,7 +22,9 @@ constexpr int kBins = 64;             // accumulation lines (one per lane of a w
 
 // One accumulation line of the region statistics of one LSF: fixed-point band
 // sums over {phi >= 0}, the count, the flip count of the iteration that
-// produced the LSF, and the normaliser max|D| (float bits) used with it.
+// produced the LSF, and the normaliser key used with it: (bits of max|D|) << 32
+// | (0xffffffff - pixel index of the maximum), so that the maximum and its
+// pixel (smallest index on ties) come out of one 64-bit atomic max.
 // Workgroup w adds into line w % kBins, so atomics spread over kBins cache
 // lines instead of serialising on one; readers sum the lines (integer sums,
 // exact and order-independent).
@@ -30,8 +32,7 @@ struct alignas(128) Bin {
     long long sum[4];
     unsigned long long nplus;
     unsigned long long flips;
-    unsigned int mbits;
-    unsigned int pad0;
+    unsigned long long mkey;
     unsigned long long pad[9];
 };
 static_assert(sizeof(Bin) == 128, "one bin per 128-byte line");
@@ -69,6 +70,7 @@ struct Taps {
 
 struct StepArgs {
     const void *img;          // storage image (NB interleaved bands) or edge map
+    const float *boxes;       // region term, B > 1: per-block band min / max (normaliser pruning)
     const uint32_t *bits_in;  // binary state b^{n-1}
     uint32_t *bits_out;       // binary state b^n
     DevState *st;
@@ -95,6 +97,8 @@ hipError_t launch_stats(const StepArgs &a, int NB, int raw, int slot, hipStream_
 hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
                            float *g, hipStream_t s);
 hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s);
+size_t mbox_floats(int H, int W, int NB);
+hipError_t launch_mbox(const float *img, int H, int W, int NB, float *boxes, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s);
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W,
                            int WW, hipStream_t s);

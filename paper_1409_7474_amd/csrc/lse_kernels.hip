@@ -79,6 +79,15 @@ __device__ __forceinline__ unsigned int wave_max_u(unsigned int v) {
     return v;
 }
 
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)v, m, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
 __device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = min(v, (unsigned int)__shfl_xor(v, m, 64));
@@ -87,13 +96,13 @@ __device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
 
 __device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
+
 // Totals of one statistics slot and of the image lines, reduced over the
 // kBins accumulation lines: wave 0 takes the slot (line i in lane i), wave 1
 // the image lines.  Called by every thread of the workgroup.
 struct Totals {
     long long sum[4];
-    unsigned long long nplus, flips;
-    unsigned int mbits, pad;
+    unsigned long long nplus, flips, mkey;
     long long total[4];
     unsigned int imin_key[4], imax_key[4];
 };
@@ -107,13 +116,13 @@ __device__ __forceinline__ void load_totals(const DevState *st, int sl, bool wan
         for (int k = 0; k < 4; ++k) v[k] = wave_sum_ll(b.sum[k]);
         const long long np = wave_sum_ll((long long)b.nplus);
         const long long fl = wave_sum_ll((long long)b.flips);
-        const unsigned int mb = wave_max_u(b.mbits);
+        const unsigned long long mk = wave_max_u64(b.mkey);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) t->sum[k] = v[k];
             t->nplus = (unsigned long long)np;
             t->flips = (unsigned long long)fl;
-            t->mbits = mb;
+            t->mkey = mk;
         }
     } else if (wave == 1 && want_img) {
         const ImgBin &b = st->img[lane];
@@ -563,14 +572,87 @@ __global__ void edge_g_kernel(const float *__restrict__ Is, float *__restrict__ 
 
 // ------------------------------------------------------------ normaliser
 
-// M = max_x |D(x)| of eq. (17), for B > 1 (B = 1 uses the closed form from
-// the image min / max, since D is then monotone in I).
+// Normaliser M = max_x |D(x)| of eq. (17), for B > 1 (B = 1 uses the closed
+// form from the image min / max, since D is then monotone in I).
+//
+// Exact, with pruning: the image is cut into 64 x 32 blocks whose per-band
+// min / max are stored at init.  D is affine in the pixel value, so over a
+// block |D| is bounded by its value at the box corners; a rounding margin
+// makes the bound hold for the FP32 D of every pixel.  The previous
+// iteration's maximising pixel, evaluated with the current means, gives a
+// lower bound LB <= M; only blocks whose bound reaches LB can hold the
+// maximum, and only those are read.  With no previous pixel (LB = 0) every
+// block is read.  The result (value and pixel) equals a full scan bit for bit.
+constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 8;
+
+size_t mbox_floats(int H, int W, int NB) {
+    const size_t nbx = (W + kMBX - 1) / kMBX, nby = (H + kMBY - 1) / kMBY;
+    return nbx * nby * 2 * NB;
+}
+
+template <int NB>
+__global__ __launch_bounds__(kThreads) void mbox_kernel(const float *__restrict__ img, int H, int W,
+                                                         float *__restrict__ boxes) {
+    __shared__ float red[kThreads / 64][2 * NB];
+    const int nbx = (W + kMBX - 1) / kMBX;
+    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float lo[NB], hi[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        lo[b] = INFINITY;
+        hi[b] = -INFINITY;
+    }
+    const int x = bx * kMBX + lane;
+    for (int r = wave; r < kMBY; r += kThreads / 64) {
+        const int y = by * kMBY + r;
+        if (x < W && y < H) {
+            const Px<NB> p = load_px<NB>(img, (long long)y * W + x);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                lo[b] = fminf(lo[b], p.v[b]);
+                hi[b] = fmaxf(hi[b], p.v[b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        lo[b] = wave_min_f(lo[b]);
+        hi[b] = wave_max_f(hi[b]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            red[wave][b] = lo[b];
+            red[wave][NB + b] = hi[b];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NB) {
+        const int k = threadIdx.x;
+        float v = red[0][k];
+        for (int w = 1; w < kThreads / 64; ++w) v = k < NB ? fminf(v, red[w][k]) : fmaxf(v, red[w][k]);
+        boxes[(size_t)blockIdx.x * 2 * NB + k] = v;
+    }
+}
+
+__device__ __forceinline__ unsigned long long mkey_of(float absd, unsigned int pix) {
+    return ((unsigned long long)__float_as_uint(absd) << 32) | (unsigned long long)(0xffffffffu - pix);
+}
+
 template <int NB>
 __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
     DevState *st = A.st;
     const int sl = A.n % 3;
     __shared__ Totals tot;
-    __shared__ float wmax[kThreads / 64];
+    __shared__ unsigned long long prev_key, wkey[kThreads / 64];
+    __shared__ int scan_list[kMBlocksPerWG];
+    __shared__ int nscan;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 2) {  // previous iteration's maximum (slot n - 1 == (n + 2) % 3)
+        const unsigned long long k = wave_max_u64(st->slot[(A.n + 2) % 3][lane].mkey);
+        if (lane == 0) prev_key = k;
+    }
     load_totals(st, sl, true, &tot);
     if (st->done || st->bad || (A.stop && tot.flips == 0)) return;
     float cp[NB], cm[NB], a[NB], m[NB];
@@ -581,15 +663,55 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
         m[b] = cp[b] + cm[b];
     }
     const float *img = static_cast<const float *>(A.img);
-    float mx = 0.f;
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < A.hw; i += (long long)gridDim.x * kThreads)
-        mx = fmaxf(mx, fabsf(region_D<NB>(load_px<NB>(img, i), a, m)));
-    mx = wave_max_f(mx);
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    const unsigned int ppix = 0xffffffffu - (unsigned int)(prev_key & 0xffffffffu);
+    const float lb = (long long)ppix < A.hw ? fabsf(region_D<NB>(load_px<NB>(img, ppix), a, m)) : 0.f;
+
+    const int nbx = (A.W + kMBX - 1) / kMBX, nby = (A.H + kMBY - 1) / kMBY, nblk = nbx * nby;
+    if (wave == 0) {
+        const int blk = blockIdx.x * kMBlocksPerWG + lane;
+        bool need = false;
+        if (lane < kMBlocksPerWG && blk < nblk) {
+            const float *bx = A.boxes + (size_t)blk * 2 * NB;
+            float dmax = 0.f, dmin = 0.f, scale = 0.f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float lo = bx[b], hi = bx[NB + b];
+                const float tl = a[b] * (2.f * lo - m[b]), th = a[b] * (2.f * hi - m[b]);
+                dmax += fmaxf(tl, th);
+                dmin += fminf(tl, th);
+                scale += fabsf(a[b]) * (2.f * fmaxf(fabsf(lo), fabsf(hi)) + fabsf(m[b]));
+            }
+            // |FP32 D - exact D| <= ~6 u scale at any pixel and for dmax/dmin;
+            // 2^-18 scale is a wide margin over both.
+            const float ub = fmaxf(fabsf(dmax), fabsf(dmin)) + scale * 3.814697265625e-06f;
+            need = ub >= lb;
+        }
+        const unsigned long long bal = __ballot(need);
+        if (lane == 0) nscan = __popcll(bal);
+        if (need) scan_list[__popcll(bal & ((1ull << lane) - 1ull))] = blk;
+    }
+    __syncthreads();
+    unsigned long long best = 0ull;
+    for (int k = 0; k < nscan; ++k) {
+        const int blk = scan_list[k];
+        const int bx = blk % nbx, by = blk / nbx;
+        const int x = bx * kMBX + lane;
+        for (int r = wave; r < kMBY; r += kThreads / 64) {
+            const int y = by * kMBY + r;
+            if (x < A.W && y < A.H) {
+                const unsigned int pix = (unsigned int)((long long)y * A.W + x);
+                const float d = fabsf(region_D<NB>(load_px<NB>(img, pix), a, m));
+                const unsigned long long key = mkey_of(d, pix);
+                best = key > best ? key : best;
+            }
+        }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) wkey[wave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kThreads / 64; ++w) mx = fmaxf(mx, wmax[w]);
-        atomicMax(&st->slot[sl][blockIdx.x % kBins].mbits, __float_as_uint(mx));
+        for (int w = 1; w < kThreads / 64; ++w) best = wkey[w] > best ? wkey[w] : best;
+        if (best) atomicMax(&st->slot[sl][blockIdx.x % kBins].mkey, best);
     }
 }
 
@@ -644,7 +766,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
             hi.v[0] = key_float(tot.imax_key[0]);
             M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
         } else {
-            M = __uint_as_float(tot.mbits);
+            M = __uint_as_float((unsigned int)(tot.mkey >> 32));
         }
         w = M > 0.f ? A.dt / M : 0.f;
     }
@@ -778,7 +900,6 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
 constexpr int kFX = 96;        // owned columns (3 bit words)
 constexpr int kFY = 64;        // owned rows
 constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 - 1 .. x0/32 + 4
-constexpr int kPStride = 128;  // phi row stride in floats
 
 constexpr int kSB = 8;         // rows per block of the rolling vertical window
 
@@ -795,7 +916,8 @@ struct FastGeom {
     static constexpr int BH = PHP + 2 * R;       // staged rows of b^{n-1}
     static constexpr int SEGD = kFY / 2;         // statistics rows per wave
     static constexpr int NCH = (TS + 5) / 6;     // lookup chunks
-    static constexpr int smem_words = BH * kFWords + PHP * kPStride + UH * kFWords + BH * 2 + 16;
+    static constexpr int PS = PW;                // phi row stride (floats)
+    static constexpr int smem_words = BH * kFWords + PHP * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
 };
 
 template <int NCH>
@@ -861,7 +983,7 @@ __device__ __forceinline__ int range_code(const uint32_t *row, int lo, int hi) {
 // Wave-uniform test: do rows [row0, row0 + n) all carry code c (0 or 1)?
 // Returns 1 (all ones), 0 (all zeros) or -1.  n <= 64.
 __device__ __forceinline__ int block_code(const int *codes, int row0, int n, int chunk) {
-    const int lane = threadIdx.x & 63;
+    const int lane = (int)threadIdx.x & 63;
     const int c = lane < n ? codes[(row0 + lane) * 2 + chunk] : -1;
     const unsigned long long full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     if (__ballot(c == 1) == full) return 1;
@@ -886,7 +1008,7 @@ __device__ __forceinline__ void stage_bits_fast(uint32_t *dst, const uint32_t *_
 // columns 0..63, chunk 1 = 64..95, each with its R halo.
 template <int R>
 __device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, int *codes) {
-    for (int i = threadIdx.x; i < nrows * 2; i += kThreads) {
+    for (int i = (int)threadIdx.x; i < nrows * 2; i += kThreads) {
         const int row = i >> 1, c = i & 1;
         codes[i] = c == 0 ? range_code(bn + row * kFWords, 32 - R, 96 + R)
                           : range_code(bn + row * kFWords, 96 - R, 128 + R);
@@ -905,7 +1027,8 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
                                            const float *__restrict__ cum, float (&acc)[NB], int &cnt) {
     using G = FastGeom<R, false>;
     static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int chunk = wave & 1, seg = wave >> 1;
     const int ox = chunk * 64 + lane;
     const int x = x0 + ox;
@@ -941,8 +1064,18 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
         int uni = -1;
         if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
         if (uni >= 0) {
+            // Uniform block: every pixel has the same sign.  Outside blocks
+            // contribute nothing (their image values are not needed); inside
+            // blocks add every pixel (rows are inside the image here).
+            if (uni == 1 && colok) {
 #pragma unroll
-            for (int j = 0; j < kSB; ++j) accumulate(rb + j, uni == 1);
+                for (int j = 0; j < kSB; ++j) {
+                    const Px<NB> p = load_px<NB>(img, (long long)(y0 + rb + j) * W + x);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+                }
+                cnt += kSB;
+            }
             have_win = false;
             continue;
         }
@@ -974,6 +1107,20 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
     }
 }
 
+// Tile of this workgroup.  Workgroup j runs on XCD j % 8 (the hardware
+// dispatches workgroups round-robin over the 8 XCDs); each XCD takes a
+// contiguous band of tile rows, so tiles that re-read each other's halo share
+// that XCD's L2.  The grid is the tile count rounded up to a multiple of 8;
+// returns -1 for the spare workgroups.
+__device__ __forceinline__ int tile_of(int ntiles) {
+    const int g = gridDim.x, j = blockIdx.x;
+    if ((g & 7) != 0) return j < ntiles ? j : -1;
+    const int xcd = j & 7, per = g >> 3;
+    const int lo = (int)((long long)ntiles * xcd / 8), hi = (int)((long long)ntiles * (xcd + 1) / 8);
+    const int t = lo + (j >> 3);
+    return (t < hi && (j >> 3) < per) ? t : -1;
+}
+
 template <int R, int NB, bool EDGE>
 __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
     using G = FastGeom<R, EDGE>;
@@ -983,8 +1130,27 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
     __shared__ float red[kThreads / 64 * 8];
     DevState *st = A.st;
     const int sl = A.n % 3;
-    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead_block = blockIdx.x == 0;
     const bool lead = lead_block && threadIdx.x == 0;
+    const int H = A.H, W = A.W;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = (W + kFX - 1) / kFX, nty = (H + kFY - 1) / kFY;
+    const int t = tile_of(ntx * nty);
+    const int x0 = (t >= 0 ? t % ntx : 0) * kFX, y0 = (t >= 0 ? t / ntx : 0) * kFY;
+    const int by0 = y0 - G::RU - 1 - R;  // image row of staged bit row 0
+    const int px0 = x0 - G::RU - 1, py0 = y0 - G::RU - 1;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
+    float *s_phi = smem + G::BH * kFWords;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PHP * G::PS);
+    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);    // [max(BH, UH)][2]
+    int *s_pcode = s_codes + G::BH * 2;                                  // [PHP][2]: phi row uniformity
+    uint32_t *s_const = reinterpret_cast<uint32_t *>(s_pcode + G::PHP * 2);  // all-ones / all-zeros rows
+
+    // A: b^{n-1} on the tile + 2R+1 halo.  Issued before the statistics
+    // loads so that the two memory round trips overlap.
+    if (t >= 0) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
     load_totals(st, sl, !EDGE, &tot);
     {
         int done = st->done | st->bad;
@@ -994,17 +1160,6 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
             return;
         }
     }
-    const int H = A.H, W = A.W;
-    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * kFY;
-    const int by0 = y0 - G::RU - 1 - R;              // image row of staged bit row 0
-    const int px0 = x0 - G::RU - 1, py0 = y0 - G::RU - 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
-    float *s_phi = smem + G::BH * kFWords;
-    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PHP * kPStride);
-    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);  // [max(BH, UH)][2]
-    uint32_t *s_const = reinterpret_cast<uint32_t *>(s_codes + G::BH * 2);  // all-ones / all-zeros rows
 
     int lut[G::NCH];
     load_luts<G::NCH>(A.taps, lut);
@@ -1012,9 +1167,6 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
 #pragma unroll
     for (int i = 0; i < TS; ++i) kk[i] = A.taps->k[i];
     const float *cum = A.taps->cum;
-
-    stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
-    if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
 
     float a[NB], m[NB], w = 0.f;
     float cp[NB], cm[NB], M = 0.f;
@@ -1031,18 +1183,11 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
             hi.v[0] = key_float(tot.imax_key[0]);
             M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
         } else {
-            M = __uint_as_float(tot.mbits);
+            M = __uint_as_float((unsigned int)(tot.mkey >> 32));
         }
         w = M > 0.f ? A.dt / M : 0.f;
     }
-    __syncthreads();
-    // Codes of the staged rows over each chunk's window span, and the LSF
-    // value of an all-ones / all-zeros window (same arithmetic as any pixel).
-    for (int i = tid; i < G::BH * 2; i += kThreads) {
-        const int row = i >> 1, c = i & 1;
-        s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, 95 - G::RU + R)
-                            : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
-    }
+    // LSF value of an all-ones / all-zeros window (same arithmetic as any pixel).
     float phi_one = 0.f, phi_zero = 0.f;
     {
         const float h1 = hconv_fast<R, G::NCH>(s_const, 64, 64, 1 << 30, false, lut, cum);
@@ -1053,154 +1198,208 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
             phi_zero = fmaf(kk[i], h0, phi_zero);
         }
     }
-    __syncthreads();
+    // U-row words of an all-ones binarised row (the two ballots' valid lanes).
+    const unsigned long long ones1 = (32 + 2 * G::RU >= 64) ? ~0ull : ((1ull << (32 + 2 * G::RU)) - 1ull);
 
-    // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
-    {
-        const int chunk = wave & 1, seg = wave >> 1;
-        const int p = chunk * 64 + lane;
-        const int x = px0 + p;
-        const int xb = x - x0 + 32;
-        const bool colok = p < G::PW && x >= 0 && x < W;
-        if (A.raw) {
-            for (int j = 0; j < G::SEG; ++j) {
-                const int q = seg * G::SEG + j, y = py0 + q;
-                float v = 0.f;
-                if (colok && y >= 0 && y < H) {
-                    const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
-                    v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+    if (t >= 0) {
+        // Codes of the staged rows over each chunk's window span.
+        for (int i = tid; i < G::BH * 2; i += kThreads) {
+            const int row = i >> 1, c = i & 1;
+            s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, 95 - G::RU + R)
+                                : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
+        }
+        __syncthreads();
+
+        // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
+        {
+            const int chunk = wave & 1, seg = wave >> 1;
+            const int p = chunk * 64 + lane;
+            const int x = px0 + p;
+            const int xb = x - x0 + 32;
+            const bool colok = p < G::PW && x >= 0 && x < W;
+            if (A.raw) {
+                for (int j = 0; j < G::SEG; ++j) {
+                    const int q = seg * G::SEG + j, y = py0 + q;
+                    float v = 0.f;
+                    if (colok && y >= 0 && y < H) {
+                        const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
+                        v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+                    }
+                    if (p < G::PW) s_phi[q * G::PS + p] = v;
+                    if (lane == 0) s_pcode[q * 2 + chunk] = 2;
                 }
-                s_phi[q * kPStride + p] = v;
-            }
-        } else {
-            constexpr int NW = 2 * R + kSB;
-            float win[NW];
-            const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
-            bool have_win = false;
+            } else {
+                constexpr int NW = 2 * R + kSB;
+                float win[NW];
+                const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
+                bool have_win = false;
 #pragma unroll 1
-            for (int blk = 0; blk < G::NBLK; ++blk) {
-                const int rb = brow0 + blk * kSB;
-                int uni = -1;
-                if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
-                    uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
-                if (uni >= 0) {
-                    const float v = uni ? phi_one : phi_zero;
+                for (int blk = 0; blk < G::NBLK; ++blk) {
+                    const int rb = brow0 + blk * kSB;
+                    int uni = -1;
+                    if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
+                        uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
+                    if (uni >= 0) {
+                        const float v = uni ? phi_one : phi_zero;
+#pragma unroll
+                        for (int j = 0; j < kSB; ++j) {
+                            const int q = rb + j;
+                            if (p < G::PW) s_phi[q * G::PS + p] = colok ? v : 0.f;
+                        }
+                        if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
+                        have_win = false;
+                        continue;
+                    }
+                    if (!have_win) {
+#pragma unroll
+                        for (int t2 = 0; t2 < 2 * R; ++t2) {
+                            const int y = by0 + rb + t2;
+                            const float v =
+                                hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, border, lut, cum);
+                            win[t2] = (y >= 0 && y < H) ? v : 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int t2 = 0; t2 < kSB; ++t2) {
+                        const int brow = rb + 2 * R + t2;
+                        const int y = by0 + brow;
+                        const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
+                        win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
+                    }
 #pragma unroll
                     for (int j = 0; j < kSB; ++j) {
-                        const int q = rb + j, y = py0 + q;
-                        s_phi[q * kPStride + p] = (colok && y >= 0 && y < H) ? v : 0.f;
+                        float ph = 0.f;
+#pragma unroll
+                        for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                        const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
+                        if (p < G::PW) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
                     }
-                    have_win = false;
-                    continue;
+                    if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
+#pragma unroll
+                    for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + kSB];
+                    have_win = true;
                 }
-                if (!have_win) {
-#pragma unroll
-                    for (int t = 0; t < 2 * R; ++t) {
-                        const int y = by0 + rb + t;
-                        const float v =
-                            hconv_fast<R, G::NCH>(s_bits + (rb + t) * kFWords, xb, x, W, border, lut, cum);
-                        win[t] = (y >= 0 && y < H) ? v : 0.f;
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kSB; ++t) {
-                    const int brow = rb + 2 * R + t;
-                    const int y = by0 + brow;
-                    const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
-                    win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
-                }
-#pragma unroll
-                for (int j = 0; j < kSB; ++j) {
-                    float ph = 0.f;
-#pragma unroll
-                    for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
-                    const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
-                    s_phi[q * kPStride + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
-                }
-#pragma unroll
-                for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
-                have_win = true;
             }
         }
-    }
-    __syncthreads();
-
-    // C: update eq. (18) and binarisation on U = tile + RU halo, one row per
-    // wave task, two 64-lane chunks per row; owned words go to global memory.
-    int flips = 0;
-    for (int uy = wave; uy < G::UH; uy += kThreads / 64) {
-        const int y = y0 - G::RU + uy;
-        const bool rowok = y >= 0 && y < H;
-        unsigned long long mk[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int xb = 32 - G::RU + c * 64 + lane;
-            const int x = x0 - 32 + xb;
-            bool pred = false;
-            if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
-                const int p = c * 64 + lane + 1;
-                const float *cc = s_phi + (uy + 1) * kPStride + p;
-                float gx, gy;
-                if (x == 0)
-                    gx = cc[1] - cc[0];
-                else if (x == W - 1)
-                    gx = cc[0] - cc[-1];
-                else
-                    gx = 0.5f * (cc[1] - cc[-1]);
-                if (y == 0)
-                    gy = cc[kPStride] - cc[0];
-                else if (y == H - 1)
-                    gy = cc[0] - cc[-kPStride];
-                else
-                    gy = 0.5f * (cc[kPStride] - cc[-kPStride]);
-                if (gx == 0.f && gy == 0.f) {
-                    pred = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                } else {
-                    const float gm = sqrtf(gx * gx + gy * gy);
-                    const long long pix = (long long)y * W + x;
-                    float coef;
-                    if constexpr (EDGE) {
-                        coef = A.dt * static_cast<const float *>(A.img)[pix];
-                    } else {
-                        coef = w * region_D<NB>(load_px<NB>(static_cast<const float *>(A.img), pix), a, m);
-                    }
-                    pred = fmaf(coef, gm, cc[0]) >= 0.f;
-                }
-            }
-            mk[c] = __ballot(pred);
-        }
-        if (lane < kFWords) {
-            const uint32_t word =
-                bits_extract(mk[0], 32 - G::RU, lane) | bits_extract(mk[1], 96 - G::RU, lane);
-            s_bn[uy * kFWords + lane] = word;
-            const int gw = (x0 >> 5) - 1 + lane;
-            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
-                const int xs = gw * 32;
-                const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
-                const uint32_t nw = word & valid;
-                const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
-                A.bits_out[(size_t)y * A.WW + gw] = nw;
-                flips += __popc(nw ^ ow);
-            }
-        }
-    }
-    __syncthreads();
-
-    float acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
-    int cnt = 0;
-    if constexpr (!EDGE) {
-        code_rows_owned<R>(s_bn, G::UH, s_codes);
         __syncthreads();
-        stats_fast<R, NB>(s_bn, s_codes, static_cast<const float *>(A.img), x0, y0, H, W, border, false, lut, kk,
-                          cum, acc, cnt);
-    }
-    TileSmem rs;
-    rs.red = red;
-    reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][block_linear_id() % kBins], A.fix, !EDGE);
 
+        // C: update eq. (18) and binarisation on U = tile + RU halo, in blocks
+        // of 8 rows per wave task; blocks whose phi rows are one uniform
+        // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
+        int flips = 0;
+        constexpr int NBC = (G::UH + kSB - 1) / kSB;
+#pragma unroll 1
+        for (int bi = wave; bi < NBC; bi += kThreads / 64) {
+            const int u0 = bi * kSB;
+            const int nr = min(kSB, G::UH - u0);
+            int rc = -1;
+            if (!border) {
+                const int ncode = (nr + 2) * 2;  // phi rows u0 .. u0 + nr + 1, both chunks
+                const int c = lane < ncode ? s_pcode[u0 * 2 + lane] : -1;
+                const unsigned long long full = (1ull << ncode) - 1ull;
+                if (__ballot(c == 1) == full)
+                    rc = 1;
+                else if (__ballot(c == 0) == full)
+                    rc = 0;
+            }
+            if (rc >= 0) {
+                if (lane < nr * kFWords) {
+                    const int r = lane / kFWords, k = lane - r * kFWords;
+                    const int uy = u0 + r, y = y0 - G::RU + uy;
+                    const uint32_t word = rc ? (bits_extract(~0ull, 32 - G::RU, k) |
+                                                bits_extract(ones1, 96 - G::RU, k))
+                                             : 0u;
+                    s_bn[uy * kFWords + k] = word;
+                    const int gw = (x0 >> 5) - 1 + k;
+                    if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + kFY && y < H && gw < A.WW) {
+                        const int xs = gw * 32;
+                        const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                        const uint32_t nw = word & valid;
+                        const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + k] & valid;
+                        A.bits_out[(size_t)y * A.WW + gw] = nw;
+                        flips += __popc(nw ^ ow);
+                    }
+                }
+                continue;
+            }
+#pragma unroll 1
+            for (int r = 0; r < nr; ++r) {
+                const int uy = u0 + r;
+                const int y = y0 - G::RU + uy;
+                const bool rowok = y >= 0 && y < H;
+                unsigned long long mk[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int xb = 32 - G::RU + c * 64 + lane;
+                    const int x = x0 - 32 + xb;
+                    bool pred = false;
+                    if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
+                        const int p = c * 64 + lane + 1;
+                        const float *cc = s_phi + (uy + 1) * G::PS + p;
+                        float gx, gy;
+                        if (x == 0)
+                            gx = cc[1] - cc[0];
+                        else if (x == W - 1)
+                            gx = cc[0] - cc[-1];
+                        else
+                            gx = 0.5f * (cc[1] - cc[-1]);
+                        if (y == 0)
+                            gy = cc[G::PS] - cc[0];
+                        else if (y == H - 1)
+                            gy = cc[0] - cc[-G::PS];
+                        else
+                            gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
+                        if (gx == 0.f && gy == 0.f) {
+                            pred = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                        } else {
+                            const float gm = sqrtf(gx * gx + gy * gy);
+                            const long long pix = (long long)y * W + x;
+                            float coef;
+                            if constexpr (EDGE) {
+                                coef = A.dt * static_cast<const float *>(A.img)[pix];
+                            } else {
+                                coef = w * region_D<NB>(load_px<NB>(static_cast<const float *>(A.img), pix), a, m);
+                            }
+                            pred = fmaf(coef, gm, cc[0]) >= 0.f;
+                        }
+                    }
+                    mk[c] = __ballot(pred);
+                }
+                if (lane < kFWords) {
+                    const uint32_t word =
+                        bits_extract(mk[0], 32 - G::RU, lane) | bits_extract(mk[1], 96 - G::RU, lane);
+                    s_bn[uy * kFWords + lane] = word;
+                    const int gw = (x0 >> 5) - 1 + lane;
+                    if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                        const int xs = gw * 32;
+                        const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                        const uint32_t nw = word & valid;
+                        const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                        A.bits_out[(size_t)y * A.WW + gw] = nw;
+                        flips += __popc(nw ^ ow);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        float acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+        int cnt = 0;
+        if constexpr (!EDGE) {
+            // D: statistics of phi^{n+1} = G * b^n for the next iteration.
+            code_rows_owned<R>(s_bn, G::UH, s_codes);
+            __syncthreads();
+            stats_fast<R, NB>(s_bn, s_codes, static_cast<const float *>(A.img), x0, y0, H, W, border, false, lut,
+                              kk, cum, acc, cnt);
+        }
+        TileSmem rs;
+        rs.red = red;
+        reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][blockIdx.x % kBins], A.fix, !EDGE);
+    }
     if (lead_block) {
+        // Clear the slot of iteration n + 2 (nobody reads or writes it now).
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
     }
@@ -1389,11 +1588,19 @@ hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, in
     return hipGetLastError();
 }
 
+hipError_t launch_mbox(const float *img, int H, int W, int NB, float *boxes, hipStream_t s) {
+    const unsigned nblk = (unsigned)(((W + kMBX - 1) / kMBX) * ((H + kMBY - 1) / kMBY));
+    switch (NB) {
+        case 2: hipLaunchKernelGGL(mbox_kernel<2>, dim3(nblk), dim3(kThreads), 0, s, img, H, W, boxes); break;
+        case 4: hipLaunchKernelGGL(mbox_kernel<4>, dim3(nblk), dim3(kThreads), 0, s, img, H, W, boxes); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s) {
-    long long nb = (a.hw + (long long)kThreads * 16 - 1) / ((long long)kThreads * 16);
-    if (nb > 2048) nb = 2048;
-    if (nb < 1) nb = 1;
-    const dim3 grid((unsigned)nb), block(kThreads);
+    const long long nblk = (long long)((a.W + kMBX - 1) / kMBX) * ((a.H + kMBY - 1) / kMBY);
+    const dim3 grid((unsigned)((nblk + kMBlocksPerWG - 1) / kMBlocksPerWG)), block(kThreads);
     switch (NB) {
         case 2: hipLaunchKernelGGL(mpass_kernel<2>, grid, block, 0, s, a); break;
         case 4: hipLaunchKernelGGL(mpass_kernel<4>, grid, block, 0, s, a); break;
@@ -1407,8 +1614,11 @@ static hipError_t launch_step_fast_t(const StepArgs &a, hipStream_t s) {
     const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
     const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE>, sm);
     if (e != hipSuccess) return e;
-    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFY - 1) / kFY);
-    hipLaunchKernelGGL((step_fast_kernel<R, NB, EDGE>), grid, dim3(kThreads), sm, s, a);
+    // One workgroup per tile, rounded up to a multiple of 8 (one band of
+    // tiles per XCD, see tile_of).
+    const long long ntiles = (long long)((a.W + kFX - 1) / kFX) * ((a.H + kFY - 1) / kFY);
+    const long long g = (ntiles + 7) & ~7ll;
+    hipLaunchKernelGGL((step_fast_kernel<R, NB, EDGE>), dim3((unsigned)g), dim3(kThreads), sm, s, a);
     return hipGetLastError();
 }
 

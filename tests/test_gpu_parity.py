@@ -64,6 +64,29 @@ def one_step(job, img64, *, term="region", dt=15.0, sigma=1.0, ts=7, g=None):
     return err, int(amb.sum()), ref
 
 
+def check_normaliser(st, img64, ref_M):
+    """The normaliser of eq. (17) must be the maximum of |D| over every pixel.
+    Recompute that maximum in FP64 from the GPU's own FP32 means; the GPU's
+    value (a pruned block scan for B > 1) may differ only by the FP32
+    rounding of D, bounded by 12 u * sum_b |a_b| (2 max|I_b| + |m_b|).  The
+    oracle's M (FP64 means) must agree within the effect of rounding the means
+    themselves to FP32 on that same scale."""
+    nb = img64.shape[2]
+    cp = np.array(st["c_plus"][:nb], np.float32)
+    cm = np.array(st["c_minus"][:nb], np.float32)
+    a32 = (cp - cm).astype(np.float64)
+    m32 = (cp + cm).astype(np.float64)
+    D = np.zeros(img64.shape[:2])
+    for b in range(nb):
+        D += a32[b] * (2.0 * img64[:, :, b] - m32[b])
+    M64 = float(np.abs(D).max())
+    amax = np.abs(img64).reshape(-1, nb).max(0)
+    scale = float(np.sum(np.abs(a32) * (2.0 * amax + np.abs(m32))))
+    assert abs(st["M"] - M64) <= 12 * 2.0 ** -24 * scale + 1e-30, (st["M"], M64, scale)
+    cscale = float(np.sum((np.abs(cp) + np.abs(cm)) * (2.0 * amax + np.abs(m32))))
+    assert abs(st["M"] - ref_M) <= 12 * 2.0 ** -24 * (scale + cscale), (st["M"], ref_M)
+
+
 def mask_disagreement(a, b):
     return float(np.mean(a.astype(bool) != b.astype(bool)))
 
@@ -95,8 +118,10 @@ def test_multiband_ragged_one_step_parity(dev, bands, h, w, ts, sigma):
     img, img64 = _as_gpu(sc.image, dev)
     job = _make(dev, img, sc.init_region, sigma=sigma, ksize=ts)
     for it in range(6):
-        err, amb, _ = one_step(job, img64, sigma=sigma, ts=ts)
+        err, amb, ref = one_step(job, img64, sigma=sigma, ts=ts)
         assert err <= LSF_TOL, (it, err)
+        # the normaliser of eq. (17) (pruned block scan for B > 1) is the full max
+        check_normaliser(job.stats(), img64, ref.M)
 
 
 @pytest.mark.parametrize("h,w,ts", [(2, 2, 3), (3, 5, 3), (5, 7, 31), (2, 100, 11), (40, 33, 7), (33, 65, 9),
@@ -255,5 +280,10 @@ def test_large_multiband_one_step_parity(dev, term):
     job = _make(dev, img, mask, term=term, sigma=1.5, ksize=11)
     job.run(5)
     g = oracle.edge_map(img64, 1.0, 9, 255.0) if term == "edge" else None
-    err, amb, _ = one_step(job, img64, term=term, sigma=1.5, ts=11, g=g)
+    err, amb, ref = one_step(job, img64, term=term, sigma=1.5, ts=11, g=g)
     assert err <= LSF_TOL
+    if term == "region":
+        st = job.stats()
+        check_normaliser(st, img64, ref.M)
+        np.testing.assert_allclose(st["c_plus"], ref.c_plus, rtol=2e-6)
+        np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6)

@@ -101,13 +101,19 @@ typedef struct {
     float pad[3];
 } lse_stats_t;
 
-/* Kernel time accumulated while profiling is enabled (see lse_profile). */
+/* Totals accumulated while profiling is enabled (see lse_profile). */
 typedef struct {
     double step_ms;      /* fused update/binarise/smooth/statistics kernel    */
     double mpass_ms;     /* normaliser pass of eq. (17) (B > 1)               */
     int64_t step_launches;
     int64_t mpass_launches;
+    int64_t needed_pixels; /* LSE_PROFILE_COUNT: pixels whose image (region) or
+                              edge-map (edge) value the counted steps read    */
+    int64_t counted_steps;
 } lse_profile_t;
+
+/* lse_profile flags. */
+enum { LSE_PROFILE_TIMING = 1, LSE_PROFILE_COUNT = 2 };
 
 typedef struct lse_ctx lse_ctx; /* opaque, host-side */
 
@@ -157,9 +163,13 @@ lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream);
  * LSE_ERR_DEVICE on a pending device error, LSE_OK otherwise. */
 lse_status lse_check(const lse_ctx *c, void *stream);
 
-/* Enable (1) / disable (0) HIP-event timing of every kernel launch of this
- * context; enabling resets the totals. */
-lse_status lse_profile(lse_ctx *c, int32_t enable);
+/* Profiling of this context; `flags` (0 = off) resets the totals.
+ * LSE_PROFILE_TIMING: HIP events around every kernel launch.
+ * LSE_PROFILE_COUNT: after every step, an extra kernel counts the pixels whose
+ *   image value that step needed (the + side of the new LSF for the region
+ *   sums, and pixels with |grad phi| != 0 for the update) -- the algorithmic
+ *   bytes of the step.  It slows the run; do not time with it. */
+lse_status lse_profile(lse_ctx *c, int32_t flags);
 
 /* Totals since profiling was enabled; synchronises the stream last used. */
 lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out);

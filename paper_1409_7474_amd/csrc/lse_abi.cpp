@@ -198,7 +198,7 @@ StepArgs step_args(const lse_ctx *c) {
 lse_status dev_status(hipError_t e) { return e == hipSuccess ? LSE_OK : LSE_ERR_DEVICE; }
 
 void prof_begin(lse_ctx *c, int kind, hipStream_t s, lse_ctx::Ev *ev) {
-    if (!c->prof) return;
+    if (!(c->prof & LSE_PROFILE_TIMING)) return;
     if (c->pool.empty()) {
         lse_ctx::Ev e;
         if (hipEventCreate(&e.a) != hipSuccess) return;
@@ -215,7 +215,7 @@ void prof_begin(lse_ctx *c, int kind, hipStream_t s, lse_ctx::Ev *ev) {
 }
 
 void prof_end(lse_ctx *c, hipStream_t s, lse_ctx::Ev *ev) {
-    if (!c->prof || ev->kind < 0) return;
+    if (!(c->prof & LSE_PROFILE_TIMING) || ev->kind < 0) return;
     (void)hipEventRecord(ev->b, s);
     c->pending.push_back(*ev);
 }
@@ -237,6 +237,9 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     e = launch_step(a, c->NB, region ? 0 : 1, s);
     prof_end(c, s, &ev);
     if (e != hipSuccess) return LSE_ERR_DEVICE;
+    if (c->prof & LSE_PROFILE_COUNT) {
+        if (launch_count_needed(a, a.raw, region ? 0 : 1, s) != hipSuccess) return LSE_ERR_DEVICE;
+    }
     c->n += 1;
     c->raw_next = 0;
     c->last_stream = s;
@@ -421,15 +424,16 @@ lse_status lse_check(const lse_ctx *c, void *stream) {
     return st.bad_value ? LSE_ERR_BAD_VALUE : LSE_OK;
 }
 
-lse_status lse_profile(lse_ctx *c, int32_t enable) {
-    if (!c) return LSE_ERR_INVALID_ARG;
-    if (enable) {
+lse_status lse_profile(lse_ctx *c, int32_t flags) {
+    if (!c || (flags & ~(LSE_PROFILE_TIMING | LSE_PROFILE_COUNT))) return LSE_ERR_INVALID_ARG;
+    if (flags) {
         for (auto &e : c->pending) c->pool.push_back(e);
         c->pending.clear();
         c->prof_ms[0] = c->prof_ms[1] = 0.0;
         c->prof_n[0] = c->prof_n[1] = 0;
+        if (launch_reset_profile(c->st, c->last_stream) != hipSuccess) return LSE_ERR_DEVICE;
     }
-    c->prof = enable ? 1 : 0;
+    c->prof = flags;
     return LSE_OK;
 }
 
@@ -445,6 +449,10 @@ lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out) {
         c->pool.push_back(e);
     }
     c->pending.clear();
+    unsigned long long acc[2] = {0, 0};
+    if (hipMemcpy(acc, &c->st->acc_needed, sizeof(acc), hipMemcpyDeviceToHost) != hipSuccess) return LSE_ERR_DEVICE;
+    host_out->needed_pixels = (int64_t)acc[0];
+    host_out->counted_steps = (int64_t)acc[1];
     host_out->step_ms = c->prof_ms[0];
     host_out->mpass_ms = c->prof_ms[1];
     host_out->step_launches = c->prof_n[0];

@@ -57,6 +57,8 @@ struct DevState {
     float last_cp[4], last_cm[4];
     float last_M;
     int pad1[3];
+    unsigned long long acc_needed;  // profiling: pixels whose image value the steps needed
+    unsigned long long acc_steps;   // profiling: steps counted into acc_needed
 };
 
 // Constant tables, copied once into the workspace.
@@ -104,5 +106,7 @@ hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, ui
                            int WW, hipStream_t s);
 hipError_t launch_lsf_out(const StepArgs &a, const uint32_t *const bits[2], int raw, float *out,
                           hipStream_t s);
+hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, hipStream_t s);
+hipError_t launch_reset_profile(DevState *st, hipStream_t s);
 
 }  // namespace lse

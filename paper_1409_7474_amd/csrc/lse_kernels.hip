@@ -1495,6 +1495,104 @@ __global__ __launch_bounds__(kThreads) void lsf_out_kernel(StepArgs A, const uin
     }
 }
 
+// ---------------------------------------------------------- profiling count
+
+// Pixels whose image (or edge-map) value one iteration needed, for roofline
+// accounting: pixels on the + side of phi^{n+1} (read for the region sums) and
+// pixels where |grad phi^n| != 0 (read for the data term of the update).
+// Recomputes phi^n from b^{n-1} (bits_in) and phi^{n+1} from b^n (bits_out)
+// with the step's own arithmetic, so the decisions match the step kernel's.
+// Profiling only; not part of any timed path.
+__global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int raw, int edge) {
+    extern __shared__ float smem[];
+    __shared__ int part[kThreads / 64];
+    if (A.st->done || A.st->bad) return;  // the step did not run
+    const int r = A.r, ts = A.ts, nch = A.nch, H = A.H, W = A.W;
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    // carve: tables, prev bits (TY + 2 + 2r rows), cur bits (TY + 2r rows), h, phi (TY + 2) x (TX + 2)
+    float *lut = smem, *cum = lut + nch * 64, *k = cum + 36;
+    uint32_t *bp = reinterpret_cast<uint32_t *>(k + 32);
+    const int BPR = kTileY + 2 + 2 * r, BCR = kTileY + 2 * r;
+    uint32_t *bc = bp + BPR * kRowWords;
+    float *h = reinterpret_cast<float *>(bc + BCR * kRowWords);  // BPR x (TX + 2), reused for BCR x TX
+    float *phi = h + BPR * (kTileX + 2);                            // (TY + 2) x (TX + 2)
+    for (int i = threadIdx.x; i < nch * 64; i += kThreads) lut[i] = (&A.taps->lut[0][0])[i];
+    for (int i = threadIdx.x; i <= ts; i += kThreads) cum[i] = A.taps->cum[i];
+    for (int i = threadIdx.x; i < ts; i += kThreads) k[i] = A.taps->k[i];
+    stage_bits(bp, A.bits_in, y0 - 1 - r, BPR, x0, H, A.WW);
+    stage_bits(bc, A.bits_out, y0 - r, BCR, x0, H, A.WW);
+    __syncthreads();
+    const int PWc = kTileX + 2;
+    // phi^n on rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
+    if (raw) {
+        for (int i = threadIdx.x; i < (kTileY + 2) * PWc; i += kThreads) {
+            const int q = i / PWc, p = i - q * PWc, y = y0 - 1 + q, x = x0 - 1 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                const uint32_t wd = bp[(q + r) * kRowWords + ((x - x0 + 32) >> 5)];
+                v = ((wd >> ((x - x0 + 32) & 31)) & 1u) ? 1.f : -1.f;
+            }
+            phi[i] = v;
+        }
+    } else {
+        for (int i = threadIdx.x; i < BPR * PWc; i += kThreads) {
+            const int row = i / PWc, p = i - row * PWc, y = y0 - 1 - r + row, x = x0 - 1 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                v = hconv_bits(bp + row * kRowWords, x - x0 + 32, x, W, r, ts, nch, lut, cum);
+            h[i] = v;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < (kTileY + 2) * PWc; i += kThreads) {
+            const int q = i / PWc, p = i - q * PWc, y = y0 - 1 + q, x = x0 - 1 + p;
+            phi[i] = (y >= 0 && y < H && x >= 0 && x < W) ? vconv(h + q * PWc + p, PWc, k, ts) : 0.f;
+        }
+    }
+    __syncthreads();
+    // h of b^n for the owned columns (region term)
+    if (!edge) {
+        for (int i = threadIdx.x; i < BCR * kTileX; i += kThreads) {
+            const int row = i / kTileX, ox = i - row * kTileX, y = y0 - r + row, x = x0 + ox;
+            float v = 0.f;
+            if (y >= 0 && y < H && x < W) v = hconv_bits(bc + row * kRowWords, ox + 32, x, W, r, ts, nch, lut, cum);
+            h[i] = v;
+        }
+        __syncthreads();
+    }
+    int cnt = 0;
+    for (int i = threadIdx.x; i < kTileY * kTileX; i += kThreads) {
+        const int oy = i / kTileX, ox = i - oy * kTileX, y = y0 + oy, x = x0 + ox;
+        if (y >= H || x >= W) continue;
+        const float *c = phi + (oy + 1) * PWc + (ox + 1);
+        float gx, gy;
+        if (x == 0) gx = c[1] - c[0];
+        else if (x == W - 1) gx = c[0] - c[-1];
+        else gx = 0.5f * (c[1] - c[-1]);
+        if (y == 0) gy = c[PWc] - c[0];
+        else if (y == H - 1) gy = c[0] - c[-PWc];
+        else gy = 0.5f * (c[PWc] - c[-PWc]);
+        bool need = !(gx == 0.f && gy == 0.f);
+        if (!edge) need = need || vconv(h + oy * kTileX + ox, kTileX, k, ts) >= 0.f;
+        cnt += need ? 1 : 0;
+    }
+    cnt = wave_sum_i(cnt);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kThreads / 64; ++w) tot += part[w];
+        atomicAdd(&A.st->acc_needed, (unsigned long long)tot);
+        if (blockIdx.x == 0 && blockIdx.y == 0) atomicAdd(&A.st->acc_steps, 1ull);
+    }
+}
+
+__global__ void reset_profile_kernel(DevState *st) {
+    if (threadIdx.x == 0) {
+        st->acc_needed = 0;
+        st->acc_steps = 0;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 // Workgroups may use more than 64 KB of LDS (gfx950 has 160 KB per CU) for
@@ -1710,6 +1808,21 @@ hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, ui
     const long long n = (long long)H * W;
     hipLaunchKernelGGL(mask_out_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bits[0], bits[1], st,
                        mask, H, W, WW);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, hipStream_t s) {
+    const int BPR = kTileY + 2 + 2 * a.r, BCR = kTileY + 2 * a.r;
+    const size_t words = (size_t)a.nch * 64 + 36 + 32 + (size_t)(BPR + BCR) * kRowWords +
+                         (size_t)BPR * (kTileX + 2) + (size_t)(kTileY + 2) * (kTileX + 2);
+    const hipError_t e = ensure_lds(count_needed_kernel, words * 4);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_needed_kernel, tile_grid(a.H, a.W), dim3(kThreads), words * 4, s, a, raw, edge);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_profile(DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(reset_profile_kernel, dim3(1), dim3(64), 0, s, st);
     return hipGetLastError();
 }
 

@@ -59,7 +59,12 @@ class lse_profile_t(ctypes.Structure):
     _fields_ = [
         ("step_ms", ctypes.c_double), ("mpass_ms", ctypes.c_double),
         ("step_launches", ctypes.c_int64), ("mpass_launches", ctypes.c_int64),
+        ("needed_pixels", ctypes.c_int64), ("counted_steps", ctypes.c_int64),
     ]
+
+
+PROFILE_TIMING = 1
+PROFILE_COUNT = 2
 
 
 class LSEError(RuntimeError):
@@ -176,8 +181,9 @@ def lse_check(ctx, stream: int = 0) -> int:
     return int(load().lse_check(ctx, stream))
 
 
-def lse_profile(ctx, enable: bool) -> None:
-    _check(load().lse_profile(ctx, int(bool(enable))), "lse_profile")
+def lse_profile(ctx, flags: int) -> None:
+    """flags: 0 off, PROFILE_TIMING (1), PROFILE_COUNT (2), or both."""
+    _check(load().lse_profile(ctx, int(flags)), "lse_profile")
 
 
 def lse_profile_read(ctx) -> lse_profile_t:
@@ -310,13 +316,14 @@ class LSE:
     def check(self) -> int:
         return lse_check(self.ctx, self._s())
 
-    def profile(self, enable: bool) -> None:
-        lse_profile(self.ctx, enable)
+    def profile(self, flags: int = PROFILE_TIMING) -> None:
+        lse_profile(self.ctx, flags)
 
     def profile_read(self) -> dict:
         p = lse_profile_read(self.ctx)
         return {"step_ms": p.step_ms, "mpass_ms": p.mpass_ms, "step_launches": int(p.step_launches),
-                "mpass_launches": int(p.mpass_launches)}
+                "mpass_launches": int(p.mpass_launches), "needed_pixels": int(p.needed_pixels),
+                "counted_steps": int(p.counted_steps)}
 
     def step_bytes_per_pixel(self) -> float:
         return lse_step_bytes_per_pixel(self.ctx)

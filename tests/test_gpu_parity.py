@@ -287,3 +287,29 @@ def test_large_multiband_one_step_parity(dev, term):
         check_normaliser(st, img64, ref.M)
         np.testing.assert_allclose(st["c_plus"], ref.c_plus, rtol=2e-6)
         np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6)
+
+
+def test_profile_counts_needed_pixels(dev):
+    """The algorithmic-bytes count used for roofline figures: per step, the
+    pixels on the + side of the new LSF (read for the region sums) or with
+    |grad phi| != 0 (read for the update), recomputed here from the exported
+    LSFs."""
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_multiband(9, size=200, bands=4, n_roofs=6, n_roads=1)
+    img, _ = _as_gpu(sc.image, dev)
+    for term, mask in (("region", sc.init_region), ("edge", sc.init_edge)):
+        job = _make(dev, img, mask, term=term, sigma=1.5, ksize=11)
+        job.run(2)
+        job.profile(lse.PROFILE_COUNT)
+        expect = 0
+        for _ in range(3):
+            phi_n = job.lsf().cpu().double().numpy()
+            job.step()
+            phi_n1 = job.lsf().cpu().double().numpy()
+            gx, gy = oracle.gradient(phi_n)
+            need = (gx != 0) | (gy != 0)
+            if term == "region":
+                need |= phi_n1 >= 0
+            expect += int(need.sum())
+        p = job.profile_read()
+        assert p["counted_steps"] == 3 and p["needed_pixels"] == expect, (term, p, expect)

@@ -65,7 +65,8 @@ typedef enum { LSE_F32 = 0, LSE_F16 = 1, LSE_BF16 = 2 } lse_dtype;
 typedef enum { LSE_ORDER_TABLE1 = 0, LSE_ORDER_LISTING = 1 } lse_order;
 
 typedef struct {
-    int32_t height, width; /* H, W >= 2, H * W < 2^31                         */
+    int32_t height, width; /* H, W >= 2; H * W * (bands, 3 counted as 4) * 4 bytes
+                              below 4 GiB - 1 MiB (edge term: H * W * 4)      */
     int32_t bands;         /* B in 1..4                                       */
     int32_t term;          /* lse_term                                        */
     int32_t order;         /* lse_order (this build: TABLE1)                  */

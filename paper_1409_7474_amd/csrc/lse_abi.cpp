@@ -60,6 +60,12 @@ lse_status validate(const lse_params *p) {
     if (p->height < 2 || p->width < 2) return LSE_ERR_INVALID_ARG;
     if ((long long)p->height * (long long)p->width >= (1ll << 31)) return LSE_ERR_INVALID_ARG;
     if (p->bands < 1 || p->bands > 4) return LSE_ERR_INVALID_ARG;
+    {
+        // The device image copy (region: bands padded to 1, 2 or 4 floats;
+        // edge: one float) is addressed with 32-bit byte offsets.
+        const unsigned long long nb = p->term == LSE_TERM_EDGE ? 1 : (p->bands == 3 ? 4 : p->bands);
+        if ((unsigned long long)p->height * p->width * nb * 4ull >= 0xfff00000ull) return LSE_ERR_INVALID_ARG;
+    }
     if (p->term != LSE_TERM_REGION && p->term != LSE_TERM_EDGE) return LSE_ERR_INVALID_ARG;
     if (p->order != LSE_ORDER_TABLE1 && p->order != LSE_ORDER_LISTING) return LSE_ERR_INVALID_ARG;
     if (p->image_dtype != LSE_F32 && p->image_dtype != LSE_F16 && p->image_dtype != LSE_BF16)

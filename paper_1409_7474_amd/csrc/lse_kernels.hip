@@ -103,6 +103,7 @@ __device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x
 struct Totals {
     long long sum[4];
     unsigned long long nplus, flips, mkey;
+    int done, bad;
     long long total[4];
     unsigned int imin_key[4], imax_key[4];
 };
@@ -123,6 +124,11 @@ __device__ __forceinline__ void load_totals(const DevState *st, int sl, bool wan
             t->nplus = (unsigned long long)np;
             t->flips = (unsigned long long)fl;
             t->mkey = mk;
+        }
+    } else if (wave == 2) {
+        if (lane == 0) {
+            t->done = st->done;
+            t->bad = st->bad;
         }
     } else if (wave == 1 && want_img) {
         const ImgBin &b = st->img[lane];
@@ -166,6 +172,34 @@ __device__ __forceinline__ Px<NB> load_px(const float *__restrict__ img, long lo
         p.v[1] = f.y;
     } else {
         p.v[0] = img[pix];
+    }
+    return p;
+}
+
+// Raw buffer loads.  The descriptor bounds the image in bytes; an offset past
+// it returns zeros without touching memory.  Lanes that do not need a value
+// get kNoLoad, so every load instruction is issued by the whole wave (no
+// branch around it) and the compiler can count outstanding loads statically,
+// which keeps several loads in flight; no bytes are read for those lanes.
+constexpr uint32_t kNoLoad = 0xfffffff0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int NB>
+__device__ __forceinline__ Px<NB> buffer_px(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    Px<NB> p;
+    if constexpr (NB == 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) p.v[b] = __int_as_float(v[b]);
+    } else if constexpr (NB == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+        p.v[0] = __int_as_float(v[0]);
+        p.v[1] = __int_as_float(v[1]);
+    } else {
+        p.v[0] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
     }
     return p;
 }
@@ -653,8 +687,21 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
         const unsigned long long k = wave_max_u64(st->slot[(A.n + 2) % 3][lane].mkey);
         if (lane == 0) prev_key = k;
     }
+    // This workgroup's block boxes (lane k < kMBlocksPerWG of wave 0) do not
+    // depend on the statistics: load them before the statistics barrier.
+    const int nbx = (A.W + kMBX - 1) / kMBX, nby = (A.H + kMBY - 1) / kMBY, nblk = nbx * nby;
+    const int myblk = blockIdx.x * kMBlocksPerWG + lane;
+    float blo[NB], bhi[NB];
+    if (wave == 0 && lane < kMBlocksPerWG && myblk < nblk) {
+        const float *bx = A.boxes + (size_t)myblk * 2 * NB;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            blo[b] = bx[b];
+            bhi[b] = bx[NB + b];
+        }
+    }
     load_totals(st, sl, true, &tot);
-    if (st->done || st->bad || (A.stop && tot.flips == 0)) return;
+    if (tot.done || tot.bad || (A.stop && tot.flips == 0)) return;
     float cp[NB], cm[NB], a[NB], m[NB];
     slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
 #pragma unroll
@@ -666,16 +713,14 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(StepArgs A) {
     const unsigned int ppix = 0xffffffffu - (unsigned int)(prev_key & 0xffffffffu);
     const float lb = (long long)ppix < A.hw ? fabsf(region_D<NB>(load_px<NB>(img, ppix), a, m)) : 0.f;
 
-    const int nbx = (A.W + kMBX - 1) / kMBX, nby = (A.H + kMBY - 1) / kMBY, nblk = nbx * nby;
     if (wave == 0) {
-        const int blk = blockIdx.x * kMBlocksPerWG + lane;
+        const int blk = myblk;
         bool need = false;
         if (lane < kMBlocksPerWG && blk < nblk) {
-            const float *bx = A.boxes + (size_t)blk * 2 * NB;
             float dmax = 0.f, dmin = 0.f, scale = 0.f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float lo = bx[b], hi = bx[NB + b];
+                const float lo = blo[b], hi = bhi[b];
                 const float tl = a[b] * (2.f * lo - m[b]), th = a[b] * (2.f * hi - m[b]);
                 dmax += fmaxf(tl, th);
                 dmin += fminf(tl, th);
@@ -902,6 +947,7 @@ constexpr int kFY = 64;        // owned rows
 constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 - 1 .. x0/32 + 4
 
 constexpr int kSB = 8;         // rows per block of the rolling vertical window
+constexpr int kCG = 4;         // rows per group of data-term loads in the binarisation phase
 
 template <int R, bool EDGE>
 struct FastGeom {
@@ -1037,73 +1083,93 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
     for (int b = 0; b < NB; ++b) acc[b] = 0.f;
     cnt = 0;
     const int urow0 = seg * G::SEGD;  // U row of output row 0 of this segment's window
-    auto accumulate = [&](int oy, bool inside) {
-        const int y = y0 + oy;
-        if (colok && y < H) {
-            const Px<NB> p = load_px<NB>(img, (long long)y * W + x);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) acc[b] += inside ? p.v[b] : 0.f;
-            cnt += inside ? 1 : 0;
-        }
-    };
+    static_assert(G::SEGD <= 32, "inside flags of a segment fit one 32-bit mask");
+    // Pass 1: which output rows of this lane's column are on the + side.
+    uint32_t inmask = 0u;
     if (raw) {
         for (int j = 0; j < G::SEGD; ++j) {
-            const int oy = urow0 + j;
-            const uint32_t wd = bn[(oy + R) * kFWords + ((ox + 32) >> 5)];
-            accumulate(oy, (wd >> ((ox + 32) & 31)) & 1u);
+            const uint32_t wd = bn[(urow0 + j + R) * kFWords + ((ox + 32) >> 5)];
+            inmask |= ((wd >> ((ox + 32) & 31)) & 1u) << j;
         }
-        return;
-    }
-    constexpr int NW = 2 * R + kSB;
-    float win[NW];
-    bool have_win = false;  // win[0 .. 2R) holds rows rb .. rb + 2R of the current block
+    } else {
+        constexpr int NW = 2 * R + kSB;
+        float win[NW];
+        bool have_win = false;  // win[0 .. 2R) holds rows rb .. rb + 2R of the current block
 #pragma unroll 1
-    for (int blk = 0; blk < G::SEGD / kSB; ++blk) {
-        const int rb = urow0 + blk * kSB;
-        const int yb = y0 - R + rb;  // image row of U row rb
-        int uni = -1;
-        if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
-        if (uni >= 0) {
-            // Uniform block: every pixel has the same sign.  Outside blocks
-            // contribute nothing (their image values are not needed); inside
-            // blocks add every pixel (rows are inside the image here).
-            if (uni == 1 && colok) {
+        for (int blk = 0; blk < G::SEGD / kSB; ++blk) {
+            const int rb = urow0 + blk * kSB;
+            const int yb = y0 - R + rb;  // image row of U row rb
+            int uni = -1;
+            if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
+            if (uni >= 0) {
+                // Uniform block: every pixel has the sign of the constant.
+                if (uni == 1) inmask |= ((1u << kSB) - 1u) << (blk * kSB);
+                have_win = false;
+                continue;
+            }
+            if (!have_win) {
 #pragma unroll
-                for (int j = 0; j < kSB; ++j) {
-                    const Px<NB> p = load_px<NB>(img, (long long)(y0 + rb + j) * W + x);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+                for (int t = 0; t < 2 * R; ++t) {
+                    const int y = yb + t;
+                    const float v = hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, x, W, border, lut, cum);
+                    win[t] = (y >= 0 && y < H) ? v : 0.f;
                 }
-                cnt += kSB;
             }
-            have_win = false;
-            continue;
-        }
-        if (!have_win) {
 #pragma unroll
-            for (int t = 0; t < 2 * R; ++t) {
-                const int y = yb + t;
-                const float v = hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, x, W, border, lut, cum);
-                win[t] = (y >= 0 && y < H) ? v : 0.f;
+            for (int t = 0; t < kSB; ++t) {
+                const int urow = rb + 2 * R + t;
+                const int y = y0 - R + urow;
+                const float v = hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, x, W, border, lut, cum);
+                win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
             }
+#pragma unroll
+            for (int j = 0; j < kSB; ++j) {
+                float ph = 0.f;
+#pragma unroll
+                for (int i = 0; i < 2 * R + 1; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                inmask |= (ph >= 0.f ? 1u : 0u) << (blk * kSB + j);
+            }
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
+            have_win = true;
         }
+    }
+    // Pass 2: add the image values of the + side rows in row order.  Loads
+    // of one group of rows are in flight while the previous group is added;
+    // only + side pixels are read (the others get kNoLoad).
+    if (!colok) inmask = 0u;
+    const int nrows = min(G::SEGD, H - (y0 + urow0));
+    if (nrows < G::SEGD) inmask &= nrows > 0 ? ((1u << nrows) - 1u) : 0u;
+    const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (uint32_t)((unsigned long long)H * W * NB * 4));
+    const uint32_t off0 = (uint32_t)(((y0 + urow0) * W + x) * NB * 4);
+    const uint32_t rstride = (uint32_t)(W * NB * 4);
+    constexpr int GR = 4;
+    Px<NB> ba[GR], bb[GR];
+    auto load_group = [&](Px<NB>(&buf)[GR], int g) {
 #pragma unroll
-        for (int t = 0; t < kSB; ++t) {
-            const int urow = rb + 2 * R + t;
-            const int y = y0 - R + urow;
-            const float v = hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, x, W, border, lut, cum);
-            win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
+        for (int i = 0; i < GR; ++i) {
+            const int j = g * GR + i;
+            buf[i] = buffer_px<NB>(rs, ((inmask >> j) & 1u) ? off0 + j * rstride : kNoLoad);
         }
+    };
+    auto add_group = [&](const Px<NB>(&buf)[GR], int g) {
 #pragma unroll
-        for (int j = 0; j < kSB; ++j) {
-            float ph = 0.f;
+        for (int i = 0; i < GR; ++i) {
+            const bool in = (inmask >> (g * GR + i)) & 1u;
 #pragma unroll
-            for (int i = 0; i < 2 * R + 1; ++i) ph = fmaf(kk[i], win[j + i], ph);
-            accumulate(rb + j, ph >= 0.f);
+            for (int b = 0; b < NB; ++b) acc[b] += in ? buf[i].v[b] : 0.f;
+            cnt += in ? 1 : 0;
         }
-#pragma unroll
-        for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
-        have_win = true;
+    };
+    constexpr int NG = G::SEGD / GR;
+    static_assert(NG % 2 == 0, "groups come in pairs");
+    load_group(ba, 0);
+#pragma unroll 1
+    for (int g = 0; g < NG; g += 2) {
+        load_group(bb, g + 1);
+        add_group(ba, g);
+        if (g + 2 < NG) load_group(ba, g + 2);
+        add_group(bb, g + 1);
     }
 }
 
@@ -1151,22 +1217,23 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
     // loads so that the two memory round trips overlap.
     if (t >= 0) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
     if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
-    load_totals(st, sl, !EDGE, &tot);
-    {
-        int done = st->done | st->bad;
-        if (!done && A.stop && tot.flips == 0) done = 1;
-        if (done) {
-            if (lead && !st->bad) st->done = 1;
-            return;
-        }
-    }
-
+    // Tables do not depend on the statistics either: load them before the
+    // statistics barrier (one memory round trip for the whole set-up).
     int lut[G::NCH];
     load_luts<G::NCH>(A.taps, lut);
     float kk[TS];
 #pragma unroll
     for (int i = 0; i < TS; ++i) kk[i] = A.taps->k[i];
     const float *cum = A.taps->cum;
+    load_totals(st, sl, !EDGE, &tot);
+    {
+        int done = tot.done | tot.bad;
+        if (!done && A.stop && tot.flips == 0) done = 1;
+        if (done) {
+            if (lead && !tot.bad) st->done = 1;
+            return;
+        }
+    }
 
     float a[NB], m[NB], w = 0.f;
     float cp[NB], cm[NB], M = 0.f;
@@ -1198,6 +1265,8 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
             phi_zero = fmaf(kk[i], h0, phi_zero);
         }
     }
+    const __amdgpu_buffer_rsrc_t img_rs =
+        image_rsrc(A.img, (uint32_t)((unsigned long long)H * W * (EDGE ? 1 : NB) * 4));
     // U-row words of an all-ones binarised row (the two ballots' valid lanes).
     const unsigned long long ones1 = (32 + 2 * G::RU >= 64) ? ~0ull : ((1ull << (32 + 2 * G::RU)) - 1ull);
 
@@ -1322,61 +1391,96 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(StepArgs A) {
                 }
                 continue;
             }
+            // Rows in groups of kCG: gradients first (LDS), then every data-term
+            // load of the group, then the updates, so that one memory round
+            // trip serves the whole group.
 #pragma unroll 1
-            for (int r = 0; r < nr; ++r) {
-                const int uy = u0 + r;
-                const int y = y0 - G::RU + uy;
-                const bool rowok = y >= 0 && y < H;
-                unsigned long long mk[2];
+            for (int r0 = 0; r0 < nr; r0 += kCG) {
+                float phv[kCG][2], gmv[kCG][2];
+                bool need[kCG][2], pred[kCG][2];
+                int pixv[kCG][2];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int xb = 32 - G::RU + c * 64 + lane;
-                    const int x = x0 - 32 + xb;
-                    bool pred = false;
-                    if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
-                        const int p = c * 64 + lane + 1;
-                        const float *cc = s_phi + (uy + 1) * G::PS + p;
-                        float gx, gy;
-                        if (x == 0)
-                            gx = cc[1] - cc[0];
-                        else if (x == W - 1)
-                            gx = cc[0] - cc[-1];
-                        else
-                            gx = 0.5f * (cc[1] - cc[-1]);
-                        if (y == 0)
-                            gy = cc[G::PS] - cc[0];
-                        else if (y == H - 1)
-                            gy = cc[0] - cc[-G::PS];
-                        else
-                            gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
-                        if (gx == 0.f && gy == 0.f) {
-                            pred = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                        } else {
-                            const float gm = sqrtf(gx * gx + gy * gy);
-                            const long long pix = (long long)y * W + x;
-                            float coef;
-                            if constexpr (EDGE) {
-                                coef = A.dt * static_cast<const float *>(A.img)[pix];
-                            } else {
-                                coef = w * region_D<NB>(load_px<NB>(static_cast<const float *>(A.img), pix), a, m);
+                for (int i = 0; i < kCG; ++i) {
+                    const int uy = u0 + r0 + i;
+                    const int y = y0 - G::RU + uy;
+                    const bool rowok = r0 + i < nr && y >= 0 && y < H;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int xb = 32 - G::RU + c * 64 + lane;
+                        const int x = x0 - 32 + xb;
+                        need[i][c] = false;
+                        pred[i][c] = false;
+                        phv[i][c] = 0.f;
+                        gmv[i][c] = 0.f;
+                        pixv[i][c] = 0;
+                        if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
+                            const int p = c * 64 + lane + 1;
+                            const float *cc = s_phi + (uy + 1) * G::PS + p;
+                            float gx, gy;
+                            if (x == 0)
+                                gx = cc[1] - cc[0];
+                            else if (x == W - 1)
+                                gx = cc[0] - cc[-1];
+                            else
+                                gx = 0.5f * (cc[1] - cc[-1]);
+                            if (y == 0)
+                                gy = cc[G::PS] - cc[0];
+                            else if (y == H - 1)
+                                gy = cc[0] - cc[-G::PS];
+                            else
+                                gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
+                            phv[i][c] = cc[0];
+                            pred[i][c] = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                            if (!(gx == 0.f && gy == 0.f)) {
+                                need[i][c] = true;
+                                gmv[i][c] = sqrtf(gx * gx + gy * gy);
+                                pixv[i][c] = y * W + x;
                             }
-                            pred = fmaf(coef, gm, cc[0]) >= 0.f;
                         }
                     }
-                    mk[c] = __ballot(pred);
                 }
-                if (lane < kFWords) {
-                    const uint32_t word =
-                        bits_extract(mk[0], 32 - G::RU, lane) | bits_extract(mk[1], 96 - G::RU, lane);
-                    s_bn[uy * kFWords + lane] = word;
-                    const int gw = (x0 >> 5) - 1 + lane;
-                    if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
-                        const int xs = gw * 32;
-                        const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
-                        const uint32_t nw = word & valid;
-                        const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
-                        A.bits_out[(size_t)y * A.WW + gw] = nw;
-                        flips += __popc(nw ^ ow);
+                float coef[kCG][2];
+                {
+                    constexpr int NV = EDGE ? 1 : NB;  // values per pixel: edge map or image bands
+                    Px<NV> v[kCG][2];
+#pragma unroll
+                    for (int i = 0; i < kCG; ++i)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            v[i][c] = buffer_px<NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * (NV * 4) : kNoLoad);
+#pragma unroll
+                    for (int i = 0; i < kCG; ++i)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            if constexpr (EDGE)
+                                coef[i][c] = A.dt * v[i][c].v[0];
+                            else
+                                coef[i][c] = w * region_D<NB>(v[i][c], a, m);
+                        }
+                }
+#pragma unroll
+                for (int i = 0; i < kCG; ++i) {
+                    if (r0 + i >= nr) break;
+                    const int uy = u0 + r0 + i;
+                    const int y = y0 - G::RU + uy;
+                    const bool rowok = y >= 0 && y < H;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
+                    const unsigned long long m0 = __ballot(pred[i][0]);
+                    const unsigned long long m1 = __ballot(pred[i][1]);
+                    if (lane < kFWords) {
+                        const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
+                        s_bn[uy * kFWords + lane] = word;
+                        const int gw = (x0 >> 5) - 1 + lane;
+                        if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                            const int xs = gw * 32;
+                            const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                            const uint32_t nw = word & valid;
+                            const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                            A.bits_out[(size_t)y * A.WW + gw] = nw;
+                            flips += __popc(nw ^ ow);
+                        }
                     }
                 }
             }

@@ -1,6 +1,7 @@
 """Throughput benchmark of the fast level set evolution on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
+                    [--sections batched,precision]
 
 One step = one whole job on the 4096 x 4096 x 4 multiband scene (40 roofs,
 6 roads, noise 0.03; sigma 1.5, 11 x 11 template, dt 15): lse_init + 200
@@ -11,7 +12,14 @@ the K timed steps (2 x 200 x 4096^2 per step).  The line also carries
     launch / its mean launch time (HIP events on the launch stream, over the
     timed region), against the MI355X HBM peak of 8 TB/s;
   * cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same job
-    (a few iterations of each term on the full image), on this host's cores.
+    (a few iterations of each term on the full image), on this host's cores;
+  * batched -- 64 uneven images (sides 512-2048, 4 bands, sigma 1 / 7 x 7,
+    150 iterations): one batched, graph-replayed launch sequence (FP32 and
+    FP16 storage) against the 64 images run one after another (plain FP32);
+  * precision -- 8192 x 8192 x 4 runway scene (sigma 2 / 13 x 13, 300
+    iterations) with the image / edge map stored in FP32, FP16 and BF16:
+    throughput, and agreement of the 16-bit runs with the FP32 run; and the
+    same generator at 1024 x 1024 against the FP64 oracle.
 """
 import argparse
 import json
@@ -40,6 +48,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sections", default="batched,precision",
+                    help="extra sections after the headline job: batched, precision (comma-separated; empty for none)")
+    ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations per term in the CPU sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="instead of the benchmark, run a plain device copy of this many MiB (reads and writes "
@@ -112,6 +123,144 @@ def cpu_baseline(scene, sigma, ksize, iters, terms):
             "kind": "oracle",
             "sample": f"{iters} iterations of each of {list(terms)} on the full {h}x{w}x{img.shape[2]} image "
                       f"(edge map precompute excluded), {t_total:.1f} s"}
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _agreement(mask_a, mask_b, lsf_a, lsf_b):
+    import numpy as np
+    a, b = mask_a.astype(bool), mask_b.astype(bool)
+    union = np.logical_or(a, b).sum()
+    return {"mask_disagreement": float(np.mean(a != b)),
+            "iou": 1.0 if union == 0 else float(np.logical_and(a, b).sum() / union),
+            "lsf_max_abs": float(np.abs(lsf_a.astype(np.float64) - lsf_b.astype(np.float64)).max())}
+
+
+def section_batched(args):
+    """64 uneven images advanced together vs one after another."""
+    import numpy as np
+    import torch
+
+    from paper_1409_7474_amd import lse, synth
+    dev = torch.device("cuda:0")
+    iters = 150
+    shapes = synth.batch_shapes(0, n=args.batch_images)
+    stream = torch.cuda.Stream(dev)
+    jobs = {}
+    with torch.cuda.stream(stream):
+        masks = []
+        imgs = []
+        for i, (h, w) in enumerate(shapes):
+            sc = synth.scene_batch_image(0, i, h, w)
+            imgs.append(torch.tensor(sc.image, dtype=torch.float32, device=dev))
+            masks.append(torch.tensor(sc.init_region, device=dev))
+        for st in ("f32", "f16"):
+            jobs[st] = [lse.LSE(im, m, sigma=1.0, ksize=7, storage=st, stream=stream) for im, m in zip(imgs, masks)]
+    npx = sum(h * w for h, w in shapes)
+
+    def reset(js):
+        for j, m in zip(js, masks):
+            j.set_mask(m, smoothed=False)
+        stream.synchronize()
+
+    def timed(fn, js, reps=3):
+        best = None
+        for _ in range(reps):
+            reset(js)
+            t0 = time.perf_counter()
+            fn()
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    def plain_all(js):
+        for j in js:
+            j.run(iters)
+
+    out = {"workload": f"{len(shapes)} images, sides U{{512..2048}} (non-square), 4 bands, region term, "
+                       f"sigma 1.0 / 7x7, dt 15, {iters} iterations, {npx / 1e6:.1f} Mpx in total",
+           "pixels": npx}
+    t_plain = timed(lambda: plain_all(jobs["f32"]), jobs["f32"])
+    ref_masks = [j.mask().cpu().numpy() for j in jobs["f32"]]
+    out["plain_f32"] = {"ms": round(t_plain * 1e3, 2), "value": round(npx * iters / t_plain / 1e6, 1)}
+    for st in ("f32", "f16"):
+        batch = lse.Batch(jobs[st], targets=[iters] * len(shapes), stream=stream)
+        for graph in (False, True):
+            reset(jobs[st])
+            batch.run(iters, graph=graph)  # warm-up (and graph capture)
+            t = timed(lambda: batch.run(iters, graph=graph), jobs[st])
+            key = f"batched_{st}" + ("_graph" if graph else "")
+            out[key] = {"ms": round(t * 1e3, 2), "value": round(npx * iters / t / 1e6, 1),
+                        "speedup_vs_plain_f32": round(t_plain / t, 3)}
+        masks_b = [j.mask().cpu().numpy() for j in jobs[st]]
+        dis = float(sum(np.sum(a != b) for a, b in zip(masks_b, ref_masks)) / npx)
+        out[f"batched_{st}"]["mask_disagreement_vs_plain_f32"] = dis
+        batch.close()
+    out["unit"] = "Mpixel-iter/s"
+    return out
+
+
+def section_precision(args):
+    """Storage precision on the 8192^2 x 4 runway scene (GPU, three storage
+    types, against the FP32-storage run) and on a 1024^2 window of it centred
+    on the runway (against the FP64 oracle)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1409_7474_amd import lse, synth
+    dev = torch.device("cuda:0")
+    iters, sigma, ts = 300, 2.0, 13
+    out = {"workload": f"8192x8192x4 runway + 200 roofs, sigma {sigma} / {ts}x{ts}, dt 15, {iters} iterations, "
+                       "region and edge terms; FP64 comparison on a 1024x1024 window centred on the runway "
+                       "(its own centred initial square; edge also after 100 iterations)"}
+    full = synth.scene_precision(0)
+    cy, cx = int(full.meta["runway"][0]), int(full.meta["runway"][1])
+    y0, x0 = min(max(cy - 512, 0), 8192 - 1024), min(max(cx - 512, 0), 8192 - 1024)
+    window = synth.crop_scene(full, y0, x0, 1024, 1024)
+    for sc, tag in ((full, "full"), (window, "window")):
+        size = sc.image.shape[0]
+        img = torch.tensor(sc.image, dtype=torch.float32, device=dev)
+        res = {}
+        cases = [("region", iters), ("edge", iters)] + ([("edge", 100)] if tag == "window" else [])
+        for term, n_it in cases:
+            init = torch.tensor(sc.init_region if term == "region" else sc.init_edge, device=dev)
+            runs = {}
+            for st in ("f32", "f16", "bf16"):
+                job = lse.LSE(img, init, term=term, sigma=sigma, ksize=ts, storage=st)
+                _sync()
+                t0 = time.perf_counter()
+                job.run(n_it)
+                _sync()
+                dt = time.perf_counter() - t0
+                runs[st] = (job.mask().cpu().numpy(), job.lsf().cpu().numpy(), dt)
+                job.close()
+                del job
+            r = {}
+            for st in ("f32", "f16", "bf16"):
+                r[st] = {"ms": round(runs[st][2] * 1e3, 2),
+                         "value": round(size * size * n_it / runs[st][2] / 1e6, 1),
+                         "inside_fraction": round(float(runs[st][0].mean()), 5)}
+                if st != "f32":
+                    r[st]["vs_f32_storage"] = _agreement(runs[st][0], runs["f32"][0], runs[st][1], runs["f32"][1])
+            if tag == "window":
+                x = np.asarray(sc.image, np.float32).astype(np.float64)
+                g = oracle.edge_map(x, 1.0, 9, 255.0) if term == "edge" else None
+                ref = oracle.run(x, sc.init_region if term == "region" else sc.init_edge, term=term, iters=n_it,
+                                 sigma=sigma, ts=ts, g=g)
+                for st in ("f32", "f16", "bf16"):
+                    r[st]["vs_fp64_oracle"] = _agreement(runs[st][0], (ref.b > 0).astype(np.uint8), runs[st][1],
+                                                         ref.phi)
+            res[f"{term}_{n_it}"] = r
+        out[tag] = res
+        del img
+        torch.cuda.empty_cache()
+    out["unit"] = "Mpixel-iter/s"
+    return out
 
 
 def main():
@@ -199,8 +348,8 @@ def main():
     step_ms = pr["step_ms"] / max(pr["step_n"], 1)
     alg = step_bytes(dom)
     achieved = alg / (step_ms * 1e-3) / 1e9
-    kname = f"lse::step_fast_kernel<{ksize // 2}, {4 if b == 3 else b if dom == 'region' else 1}, " \
-            f"{'false' if dom == 'region' else 'true'}>"
+    kname = f"lse::step_fast_kernel<{ksize // 2}, {(4 if b == 3 else b) if dom == 'region' else 1}, " \
+            f"{'false' if dom == 'region' else 'true'}, float>"
     traffic, traffic_src = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
@@ -233,6 +382,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, sigma, ksize, args.cpu_iters, terms)
+    sections = [x for x in args.sections.split(",") if x]
+    if "batched" in sections:
+        out["batched"] = section_batched(args)
+    if "precision" in sections:
+        out["precision"] = section_precision(args)
     print(json.dumps(out), flush=True)
 
 

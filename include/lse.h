@@ -71,7 +71,11 @@ typedef struct {
     int32_t term;          /* lse_term                                        */
     int32_t order;         /* lse_order (this build: TABLE1)                  */
     int32_t image_dtype;   /* lse_dtype of the caller's image buffer          */
-    int32_t storage;       /* lse_dtype of the device copy (this build: F32)  */
+    int32_t storage;       /* lse_dtype of the resident image (region) or edge
+                              map (edge); values are rounded to it once at
+                              init, all arithmetic stays FP32.  The LSF itself
+                              is kept as its binary function (1 bit per pixel)
+                              in every mode.                                  */
     float dt;              /* time step of eq. (18), finite, > 0 (paper: 15)  */
     float sigma;           /* LSF smoothing: sigma of (17) / sigma2 of (14)   */
     int32_t ksize;         /* its template side TS, odd 3..31; 0 = 2*ceil(3 sigma)+1 */
@@ -85,7 +89,8 @@ typedef struct {
 
 /* Fill *p with the defaults (region term, Table I order, dt 15, sigma 1,
  * TS 7, sigma1 1, TS1 9, edge scale 255, FP32 image and storage) for an
- * H x W x B image. */
+ * H x W x B image.  With 16-bit storage the H x W x B limit on height applies
+ * with 2 bytes per value instead of 4. */
 void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t bands);
 
 /* State after the last executed iteration (see lse_stats). */
@@ -182,6 +187,49 @@ double lse_step_bytes_per_pixel(const lse_ctx *c);
 
 /* Release the context (host memory only; the workspace stays the caller's). */
 void lse_destroy(lse_ctx *c);
+
+/* ------------------------------------------------------------------ batch
+ *
+ * Many contexts (uneven sizes, either term, any storage) advanced together:
+ * each iteration of the batch is one launch of the step kernel (plus one of
+ * the normaliser pass for B > 1 region images) per kernel family (term, B,
+ * template side, storage), covering the tiles of all images of that family.
+ * Every image keeps its own state and statistics, so its results are bit for
+ * bit those of lse_run on it alone.  Contexts need a template side TS in
+ * 7..15 (LSE_ERR_UNSUPPORTED otherwise).
+ *
+ * The batch table (argument copies and the workgroup -> (image, tile) maps)
+ * lives in caller-provided device memory of lse_batch_bytes() bytes, 256-byte
+ * aligned, that must stay alive and untouched until lse_batch_destroy().  The
+ * contexts must outlive the batch; while a batch exists its contexts may still
+ * be stepped alone (lse_step / lse_run) on the same stream.  lse_set_mask on a
+ * member context is allowed; targets count iterations since the last
+ * lse_init / lse_set_mask. */
+typedef struct lse_batch lse_batch; /* opaque, host-side */
+
+/* lse_batch_run flags. */
+enum { LSE_BATCH_GRAPH = 1 };
+
+/* Device bytes of the batch table for these n contexts; 0 if they cannot form
+ * a batch (null or repeated context, unsupported template side). */
+size_t lse_batch_bytes(lse_ctx *const *cs, int32_t n);
+
+/* Build a batch of n distinct contexts.  targets (n entries, or NULL for no
+ * limit): context i stops iterating once it has run targets[i] iterations
+ * since its lse_init / lse_set_mask.  The table is written on `stream`. */
+lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
+                            size_t table_bytes, void *stream, lse_batch **out);
+
+/* Up to `iters` iterations of every context of the batch (each stops at its
+ * target, and with stop_when_unchanged at its Step-5 fixed point), enqueued
+ * on `stream` without synchronising.  LSE_BATCH_GRAPH: the launch sequence is
+ * captured once into a HIP graph (re-captured when iters or the stop flag
+ * change) and launched as one graph; needs a non-default stream. */
+lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchanged, int32_t flags, void *stream);
+
+/* Release the batch (synchronises the stream of its last graph launch, if
+ * any).  The table memory and the contexts stay the caller's. */
+void lse_batch_destroy(lse_batch *b);
 
 /* Human-readable name of a status code. */
 const char *lse_status_str(lse_status s);

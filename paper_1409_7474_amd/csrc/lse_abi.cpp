@@ -4,7 +4,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "lse_internal.h"
@@ -14,6 +17,7 @@ using namespace lse;
 struct lse_ctx {
     lse_params p;
     int NB;             // stored bands (1, 2 or 4)
+    int esz;            // bytes of one stored value (storage type)
     int r, ts, nch;     // LSF smoothing
     int r1, ts1;        // edge term: image pre-smoothing
     int WW;             // bit words per row
@@ -23,7 +27,9 @@ struct lse_ctx {
     int raw_next;       // next iteration starts from the binary LSF itself
     DevState *st;
     Taps *taps;
-    float *img;         // region: storage image; edge: edge map g
+    ImgArgs *dargs;     // this image's step / normaliser arguments (device)
+    ImgArgs host_args;
+    void *img;          // region: storage image; edge: edge map g
     float *boxes;       // region, B > 1: per-block band min / max for the normaliser
     uint32_t *bits[2];
     float *tmp[2];
@@ -38,6 +44,29 @@ struct lse_ctx {
     std::vector<Ev> pending, pool;
     double prof_ms[2];
     long long prof_n[2];
+};
+
+// A set of contexts advanced together: one step launch (and, for B > 1, one
+// normaliser launch) per iteration per kernel family, over a device table of
+// ImgArgs and a workgroup map (image, tile).
+struct lse_batch {
+    struct Group {
+        int r, NB, edge, storage;     // kernel family
+        int first, count;             // ImgArgs index range
+        int step_bits, mpass_bits;    // unit bits of the map entries
+        size_t step_map, mpass_map;   // offsets (entries) into the map
+        unsigned step_grid, mpass_grid;
+    };
+    std::vector<lse_ctx *> cs;        // in table order
+    std::vector<int> target;
+    std::vector<Group> groups;
+    std::vector<ImgArgs> hargs;
+    std::vector<uint32_t> hmap;
+    ImgArgs *dargs;
+    uint32_t *dmap;
+    hipStream_t last_stream;
+    hipGraphExec_t exec;
+    int exec_iters, exec_stop;
 };
 
 namespace {
@@ -60,17 +89,18 @@ lse_status validate(const lse_params *p) {
     if (p->height < 2 || p->width < 2) return LSE_ERR_INVALID_ARG;
     if ((long long)p->height * (long long)p->width >= (1ll << 31)) return LSE_ERR_INVALID_ARG;
     if (p->bands < 1 || p->bands > 4) return LSE_ERR_INVALID_ARG;
-    {
-        // The device image copy (region: bands padded to 1, 2 or 4 floats;
-        // edge: one float) is addressed with 32-bit byte offsets.
-        const unsigned long long nb = p->term == LSE_TERM_EDGE ? 1 : (p->bands == 3 ? 4 : p->bands);
-        if ((unsigned long long)p->height * p->width * nb * 4ull >= 0xfff00000ull) return LSE_ERR_INVALID_ARG;
-    }
     if (p->term != LSE_TERM_REGION && p->term != LSE_TERM_EDGE) return LSE_ERR_INVALID_ARG;
     if (p->order != LSE_ORDER_TABLE1 && p->order != LSE_ORDER_LISTING) return LSE_ERR_INVALID_ARG;
     if (p->image_dtype != LSE_F32 && p->image_dtype != LSE_F16 && p->image_dtype != LSE_BF16)
         return LSE_ERR_INVALID_ARG;
     if (p->storage != LSE_F32 && p->storage != LSE_F16 && p->storage != LSE_BF16) return LSE_ERR_INVALID_ARG;
+    {
+        // The device image copy (region: bands padded to 1, 2 or 4 values;
+        // edge: one value) is addressed with 32-bit byte offsets.
+        const unsigned long long nb = p->term == LSE_TERM_EDGE ? 1 : (p->bands == 3 ? 4 : p->bands);
+        const unsigned long long es = p->storage == LSE_F32 ? 4 : 2;
+        if ((unsigned long long)p->height * p->width * nb * es >= 0xfff00000ull) return LSE_ERR_INVALID_ARG;
+    }
     if (!(isfinite(p->dt) && p->dt > 0.f)) return LSE_ERR_INVALID_ARG;
     if (!(isfinite(p->sigma) && p->sigma > 0.f)) return LSE_ERR_INVALID_ARG;
     if (p->ksize < 0 || !valid_ts(resolved_ksize(p->ksize, p->sigma))) return LSE_ERR_INVALID_ARG;
@@ -82,13 +112,12 @@ lse_status validate(const lse_params *p) {
     if (p->reinit_every < 0) return LSE_ERR_INVALID_ARG;
     // Valid requests that this build does not implement.
     if (p->order != LSE_ORDER_TABLE1) return LSE_ERR_UNSUPPORTED;
-    if (p->storage != LSE_F32) return LSE_ERR_UNSUPPORTED;
     if (p->reinit_every != 1) return LSE_ERR_UNSUPPORTED;
     return LSE_OK;
 }
 
 struct Layout {
-    size_t state, taps, img, boxes, bits0, bits1, tmp0, tmp1, total;
+    size_t state, taps, args, img, boxes, bits0, bits1, tmp0, tmp1, total;
 };
 
 Layout layout_of(const lse_params *p) {
@@ -101,8 +130,11 @@ Layout layout_of(const lse_params *p) {
     o = align_up(o + sizeof(DevState));
     L.taps = o;
     o = align_up(o + sizeof(Taps));
+    L.args = o;
+    o = align_up(o + sizeof(ImgArgs));
+    const size_t es = p->storage == LSE_F32 ? 4 : 2;
     L.img = o;
-    o = align_up(o + (p->term == LSE_TERM_REGION ? hw * NB * 4 : hw * 4));
+    o = align_up(o + (p->term == LSE_TERM_REGION ? hw * NB * es : hw * es));
     L.boxes = 0;
     if (p->term == LSE_TERM_REGION && NB > 1) {
         L.boxes = o;
@@ -227,20 +259,25 @@ void prof_end(lse_ctx *c, hipStream_t s, lse_ctx::Ev *ev) {
 }
 
 lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
-    StepArgs a = step_args(c);
-    a.stop = stop;
     hipError_t e = hipSuccess;
     const bool region = c->p.term == LSE_TERM_REGION;
+    const int storage = c->p.storage;
     if (region && c->NB > 1) {
         lse_ctx::Ev ev{nullptr, nullptr, -1};
         prof_begin(c, 1, s, &ev);
-        e = launch_mpass(a, c->NB, s);
+        e = launch_mpass(c->dargs, nullptr, 0, (unsigned)c->host_args.mgroups, c->n, stop, c->NB, storage, s);
         prof_end(c, s, &ev);
         if (e != hipSuccess) return LSE_ERR_DEVICE;
     }
+    StepArgs a = step_args(c);
+    a.stop = stop;
     lse_ctx::Ev ev{nullptr, nullptr, -1};
     prof_begin(c, 0, s, &ev);
-    e = launch_step(a, c->NB, region ? 0 : 1, s);
+    if (fast_radius(c->r))
+        e = launch_step(c->dargs, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
+                        region ? 0 : 1, storage, s);
+    else
+        e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
     prof_end(c, s, &ev);
     if (e != hipSuccess) return LSE_ERR_DEVICE;
     if (c->prof & LSE_PROFILE_COUNT) {
@@ -298,6 +335,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     if (!c) return LSE_ERR_INVALID_ARG;
     c->p = *p;
     c->NB = p->bands == 3 ? 4 : p->bands;
+    c->esz = p->storage == LSE_F32 ? 4 : 2;
     c->ts = resolved_ksize(p->ksize, p->sigma);
     c->r = c->ts / 2;
     c->nch = (c->ts + kChunkBits - 1) / kChunkBits;
@@ -313,7 +351,8 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     char *base = static_cast<char *>(workspace_dev);
     c->st = reinterpret_cast<DevState *>(base + L.state);
     c->taps = reinterpret_cast<Taps *>(base + L.taps);
-    c->img = reinterpret_cast<float *>(base + L.img);
+    c->dargs = reinterpret_cast<ImgArgs *>(base + L.args);
+    c->img = base + L.img;
     c->boxes = L.boxes ? reinterpret_cast<float *>(base + L.boxes) : nullptr;
     c->bits[0] = reinterpret_cast<uint32_t *>(base + L.bits0);
     c->bits[1] = reinterpret_cast<uint32_t *>(base + L.bits1);
@@ -323,27 +362,52 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     c->prof_ms[0] = c->prof_ms[1] = 0.0;
     c->prof_n[0] = c->prof_n[1] = 0;
     build_taps(c->host_taps, p->sigma, c->ts, p->sigma_img, c->ts1);
+    {
+        ImgArgs &A = c->host_args;
+        memset(&A, 0, sizeof(A));
+        A.img = c->img;
+        A.boxes = c->boxes;
+        A.bits[0] = c->bits[0];
+        A.bits[1] = c->bits[1];
+        A.st = c->st;
+        A.taps = c->taps;
+        A.H = p->height;
+        A.W = p->width;
+        A.WW = c->WW;
+        A.tiles = step_tiles(p->height, p->width);
+        A.dt = p->dt;
+        A.fix = c->fix;
+        A.inv_fix = c->inv_fix;
+        A.target = 0x7fffffff;
+        A.hw = c->hw;
+        A.n0 = 0;
+        A.mgroups = (p->term == LSE_TERM_REGION && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
+    }
 
     hipStream_t st = as_stream(stream);
     c->last_stream = st;
     hipError_t e = hipMemcpyAsync(c->taps, &c->host_taps, sizeof(Taps), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_init_state(c->st, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dargs, &c->host_args, sizeof(ImgArgs), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_init_state(c->st, 1, st);
     if (e == hipSuccess) {
         if (p->term == LSE_TERM_REGION) {
-            e = launch_init_image(image_dev, p->image_dtype, p->bands, c->NB, c->img, c->hw, c->st, c->fix, 0, 0.f, st);
-            if (e == hipSuccess && c->NB > 1) e = launch_mbox(c->img, p->height, p->width, c->NB, c->boxes, st);
+            e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st, c->fix,
+                                  0, 0.f, st);
+            if (e == hipSuccess && c->NB > 1)
+                e = launch_mbox(c->img, p->height, p->width, c->NB, p->storage, c->boxes, st);
         } else {
-            e = launch_init_image(image_dev, p->image_dtype, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
+            e = launch_init_image(image_dev, p->image_dtype, LSE_F32, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
                                   p->edge_scale, st);
             if (e == hipSuccess)
-                e = launch_edge_map(c->tmp[1], p->height, p->width, c->taps, c->r1, c->tmp[0], c->tmp[1], c->img, st);
+                e = launch_edge_map(c->tmp[1], p->height, p->width, c->taps, c->r1, c->tmp[0], c->tmp[1], c->img,
+                                    p->storage, st);
         }
     }
     if (e == hipSuccess) e = launch_pack_mask(init_mask_dev, c->bits[0], p->height, p->width, c->WW, st);
     if (e == hipSuccess && p->term == LSE_TERM_REGION) {
         StepArgs a = step_args(c);
         a.bits_in = c->bits[0];
-        e = launch_stats(a, c->NB, 1, 0, st);
+        e = launch_stats(a, c->NB, p->storage, 1, 0, st);
     }
     if (e != hipSuccess) {
         delete c;
@@ -384,14 +448,14 @@ lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream) {
 lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, void *stream) {
     if (!c || !mask_dev) return LSE_ERR_INVALID_ARG;
     const hipStream_t s = as_stream(stream);
-    hipError_t e = launch_reset_state(c->st, s);
+    hipError_t e = launch_reset_state(c->st, smoothed ? 0 : 1, s);
     if (e == hipSuccess) e = launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
     c->n = 0;
     c->raw_next = smoothed ? 0 : 1;
     if (e == hipSuccess && c->p.term == LSE_TERM_REGION) {
         StepArgs a = step_args(c);
         a.bits_in = c->bits[0];
-        e = launch_stats(a, c->NB, c->raw_next, 0, s);
+        e = launch_stats(a, c->NB, c->p.storage, c->raw_next, 0, s);
     }
     c->last_stream = s;
     return dev_status(e);
@@ -469,8 +533,8 @@ lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out) {
 double lse_step_bytes_per_pixel(const lse_ctx *c) {
     if (!c) return 0.0;
     const double state = 2.0 / 8.0;  // binary state: one bit read, one bit written
-    if (c->p.term == LSE_TERM_EDGE) return 4.0 + state;
-    return 4.0 * c->NB + state;
+    if (c->p.term == LSE_TERM_EDGE) return (double)c->esz + state;
+    return (double)c->esz * c->NB + state;
 }
 
 void lse_destroy(lse_ctx *c) {
@@ -496,6 +560,243 @@ const char *lse_status_str(lse_status s) {
     return "LSE_ERR_UNKNOWN";
 }
 
-int32_t lse_version(void) { return 100; }
+// ------------------------------------------------------------------ batch
+
+namespace {
+
+int bits_for(long long n) {  // smallest b >= 1 with n <= 2^b
+    int b = 1;
+    while ((1ll << b) < n) ++b;
+    return b;
+}
+
+// Plan the table of a batch: contexts grouped by kernel family, each group's
+// step map (XCD-banded over the concatenated tiles of its images, as tile_of
+// does for one image) and normaliser map.  Returns the device bytes, or 0 if
+// the contexts cannot form a batch.
+size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
+    if (!cs || n <= 0) return 0;
+    std::set<const lse_ctx *> seen;
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i) {
+        if (!cs[i] || !seen.insert(cs[i]).second) return 0;  // null or repeated context
+        if (!fast_radius(cs[i]->r)) return 0;
+        order.push_back(i);
+    }
+    auto key = [&](int i) {
+        const lse_ctx *c = cs[i];
+        const int edge = c->p.term == LSE_TERM_EDGE;
+        return std::make_tuple(edge, c->r, edge ? 1 : c->NB, (int)c->p.storage);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+    b->cs.clear();
+    b->groups.clear();
+    b->hmap.clear();
+    for (size_t j = 0; j < order.size();) {
+        size_t e = j;
+        while (e < order.size() && key(order[e]) == key(order[j])) ++e;
+        lse_batch::Group g;
+        g.edge = std::get<0>(key(order[j]));
+        g.r = std::get<1>(key(order[j]));
+        g.NB = std::get<2>(key(order[j]));
+        g.storage = std::get<3>(key(order[j]));
+        g.first = (int)b->cs.size();
+        g.count = (int)(e - j);
+        long long total = 0, maxt = 1, maxm = 1;
+        std::vector<long long> prefix(1, 0);
+        for (size_t q = j; q < e; ++q) {
+            const lse_ctx *c = cs[order[q]];
+            b->cs.push_back(cs[order[q]]);
+            total += c->host_args.tiles;
+            prefix.push_back(total);
+            maxt = std::max<long long>(maxt, c->host_args.tiles);
+            maxm = std::max<long long>(maxm, c->host_args.mgroups);
+        }
+        g.step_bits = bits_for(maxt);
+        g.mpass_bits = bits_for(maxm);
+        const int ubits = std::max(g.step_bits, g.mpass_bits);
+        if (ubits >= 31 || (long long)g.count >= (1ll << (32 - ubits)) - 1) return 0;
+        // Step map: workgroup w runs on XCD w % 8; XCD x takes the x-th
+        // eighth of the concatenated tiles.
+        const long long grid = (total + 7) & ~7ll;
+        if (grid > 0x7fffffffll) return 0;
+        g.step_map = b->hmap.size();
+        g.step_grid = (unsigned)grid;
+        b->hmap.resize(b->hmap.size() + grid, kNoTile);
+        const long long per = grid / 8;
+        for (long long w = 0; w < grid; ++w) {
+            const long long x = w & 7, slot = w >> 3;
+            const long long lo = total * x / 8, hi = total * (x + 1) / 8;
+            const long long t = lo + slot;
+            if (slot >= per || t >= hi) continue;
+            const long long im = std::upper_bound(prefix.begin(), prefix.end(), t) - prefix.begin() - 1;
+            b->hmap[g.step_map + w] = ((uint32_t)im << g.step_bits) | (uint32_t)(t - prefix[im]);
+        }
+        // Normaliser map (B > 1 region images): image-major block groups.
+        g.mpass_map = b->hmap.size();
+        g.mpass_grid = 0;
+        if (!g.edge && g.NB > 1) {
+            for (int q = 0; q < g.count; ++q) {
+                const int mg = b->cs[g.first + q]->host_args.mgroups;
+                for (int u = 0; u < mg; ++u) b->hmap.push_back(((uint32_t)q << g.mpass_bits) | (uint32_t)u);
+            }
+            g.mpass_grid = (unsigned)(b->hmap.size() - g.mpass_map);
+        }
+        b->groups.push_back(g);
+        j = e;
+    }
+    return align_up(b->cs.size() * sizeof(ImgArgs)) + align_up(b->hmap.size() * sizeof(uint32_t));
+}
+
+}  // namespace
+
+size_t lse_batch_bytes(lse_ctx *const *cs, int32_t n) {
+    lse_batch b;
+    return plan_batch(cs, n, &b);
+}
+
+lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
+                            size_t table_bytes, void *stream, lse_batch **out) {
+    if (!out) return LSE_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!cs || n <= 0) return LSE_ERR_INVALID_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!cs[i]) return LSE_ERR_INVALID_ARG;
+    if (targets)
+        for (int i = 0; i < n; ++i)
+            if (targets[i] < 0) return LSE_ERR_INVALID_ARG;
+    lse_batch *b = new (std::nothrow) lse_batch();
+    if (!b) return LSE_ERR_INVALID_ARG;
+    const size_t need = plan_batch(cs, n, b);
+    if (need == 0) {
+        // Repeated or null contexts are invalid; a radius without a compiled
+        // step variant is valid but not batched by this build.
+        std::set<const lse_ctx *> seen;
+        lse_status v = LSE_ERR_UNSUPPORTED;
+        for (int i = 0; i < n; ++i)
+            if (!seen.insert(cs[i]).second) v = LSE_ERR_INVALID_ARG;
+        delete b;
+        return v;
+    }
+    if (!table_dev || (reinterpret_cast<uintptr_t>(table_dev) % kAlign)) {
+        delete b;
+        return LSE_ERR_WORKSPACE;
+    }
+    if (table_bytes < need) {
+        delete b;
+        return LSE_ERR_WORKSPACE;
+    }
+    b->dargs = static_cast<ImgArgs *>(table_dev);
+    b->dmap = reinterpret_cast<uint32_t *>(static_cast<char *>(table_dev) + align_up(b->cs.size() * sizeof(ImgArgs)));
+    b->hargs.resize(b->cs.size());
+    b->target.resize(b->cs.size());
+    for (size_t i = 0; i < b->cs.size(); ++i) {
+        int t = 0x7fffffff;
+        if (targets) {
+            const lse_ctx *c = b->cs[i];
+            for (int j = 0; j < n; ++j)
+                if (cs[j] == c) t = targets[j];
+        }
+        b->hargs[i] = b->cs[i]->host_args;
+        b->hargs[i].target = t;
+        b->hargs[i].n0 = 0;
+        b->target[i] = t;
+    }
+    b->exec = nullptr;
+    b->exec_iters = -1;
+    b->exec_stop = -1;
+    const hipStream_t s = as_stream(stream);
+    b->last_stream = s;
+    hipError_t e = hipMemcpyAsync(b->dargs, b->hargs.data(), b->hargs.size() * sizeof(ImgArgs),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dmap, b->hmap.data(), b->hmap.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        delete b;
+        return LSE_ERR_DEVICE;
+    }
+    *out = b;
+    return LSE_OK;
+}
+
+namespace {
+
+hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
+    hipError_t e = launch_batch_prepare(b->dargs, (int)b->cs.size(), s);
+    for (int k = 0; k < iters && e == hipSuccess; ++k) {
+        for (const auto &g : b->groups) {
+            if (g.mpass_grid)
+                e = launch_mpass(b->dargs + g.first, b->dmap + g.mpass_map, g.mpass_bits, g.mpass_grid, k, stop, g.NB,
+                                 g.storage, s);
+            if (e == hipSuccess)
+                e = launch_step(b->dargs + g.first, b->dmap + g.step_map, g.step_bits, g.step_grid, k, stop, g.r,
+                                g.NB, g.edge, g.storage, s);
+            if (e != hipSuccess) break;
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
+lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchanged, int32_t flags, void *stream) {
+    if (!b || iters < 0 || (flags & ~LSE_BATCH_GRAPH)) return LSE_ERR_INVALID_ARG;
+    const hipStream_t s = as_stream(stream);
+    const int stop = stop_when_unchanged ? 1 : 0;
+    if (iters == 0) return LSE_OK;
+    hipError_t e = hipSuccess;
+    if (flags & LSE_BATCH_GRAPH) {
+        if (!s) return LSE_ERR_INVALID_ARG;  // the default stream cannot be captured
+        if (!b->exec || b->exec_iters != iters || b->exec_stop != stop) {
+            if (b->exec) {
+                if (hipStreamSynchronize(b->last_stream) != hipSuccess) return LSE_ERR_DEVICE;
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return LSE_ERR_DEVICE;
+            const hipError_t le = enqueue_batch(b, iters, stop, s);
+            e = hipStreamEndCapture(s, &graph);
+            if (le != hipSuccess || e != hipSuccess || !graph) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return LSE_ERR_DEVICE;
+            }
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return LSE_ERR_DEVICE;
+            }
+            b->exec_iters = iters;
+            b->exec_stop = stop;
+        }
+        e = hipGraphLaunch(b->exec, s);
+    } else {
+        e = enqueue_batch(b, iters, stop, s);
+    }
+    if (e != hipSuccess) return LSE_ERR_DEVICE;
+    for (size_t i = 0; i < b->cs.size(); ++i) {
+        lse_ctx *c = b->cs[i];
+        const long long left = (long long)b->target[i] - c->n;
+        const int ran = (int)std::max(0ll, std::min((long long)iters, left));
+        c->n += ran;
+        if (ran > 0) c->raw_next = 0;
+        c->last_stream = s;
+    }
+    b->last_stream = s;
+    return LSE_OK;
+}
+
+void lse_batch_destroy(lse_batch *b) {
+    if (!b) return;
+    if (b->exec) {
+        (void)hipStreamSynchronize(b->last_stream);
+        (void)hipGraphExecDestroy(b->exec);
+    }
+    delete b;
+}
+
+int32_t lse_version(void) { return 101; }
 
 }  // extern "C"

@@ -1,0 +1,754 @@
+// Device helpers shared by the HIP kernels of the fast level set evolution
+// (arXiv 1409.7474): wave reductions, statistics totals, pixel loads of the
+// three storage types, binary-window Gaussian sums and the tile geometry.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "lse_internal.h"
+
+namespace lse {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ unsigned int float_key(float f) {
+    unsigned int u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_float(unsigned int k) {
+    unsigned int u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_max_u(unsigned int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned int)__shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)v, m, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, (unsigned int)__shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+
+// Totals of one statistics slot and of the image lines, reduced over the
+// kBins accumulation lines: wave 0 takes the slot (line i in lane i), wave 1
+// the image lines.  Called by every thread of the workgroup.
+struct Totals {
+    long long sum[4];
+    unsigned long long nplus, flips, mkey;
+    int done, bad, raw;
+    long long total[4];
+    unsigned int imin_key[4], imax_key[4];
+};
+
+__device__ __forceinline__ void load_totals(const DevState *st, int sl, bool want_img, Totals *t) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        const Bin &b = st->slot[sl][lane];
+        long long v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = wave_sum_ll(b.sum[k]);
+        const long long np = wave_sum_ll((long long)b.nplus);
+        const long long fl = wave_sum_ll((long long)b.flips);
+        const unsigned long long mk = wave_max_u64(b.mkey);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t->sum[k] = v[k];
+            t->nplus = (unsigned long long)np;
+            t->flips = (unsigned long long)fl;
+            t->mkey = mk;
+        }
+    } else if (wave == 2) {
+        if (lane == 0) {
+            t->done = st->done;
+            t->bad = st->bad;
+            t->raw = st->raw;
+        }
+    } else if (wave == 1 && want_img) {
+        const ImgBin &b = st->img[lane];
+        long long v[4];
+        unsigned int lo[4], hi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = wave_sum_ll(b.total[k]);
+            lo[k] = wave_min_u(b.imin_key[k]);
+            hi[k] = wave_max_u(b.imax_key[k]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                t->total[k] = v[k];
+                t->imin_key[k] = lo[k];
+                t->imax_key[k] = hi[k];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int NB>
+struct Px {
+    float v[NB];
+};
+
+// Element types of the resident image: FP32, or 16-bit FP16 / BF16 halves of
+// a 32-bit word (low half = lower address).
+template <typename ST>
+__device__ __forceinline__ float half_lo(uint32_t w);
+template <typename ST>
+__device__ __forceinline__ float half_hi(uint32_t w);
+template <>
+__device__ __forceinline__ float half_lo<__half>(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+}
+template <>
+__device__ __forceinline__ float half_hi<__half>(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+}
+template <>
+__device__ __forceinline__ float half_lo<__hip_bfloat16>(uint32_t w) { return __uint_as_float(w << 16); }
+template <>
+__device__ __forceinline__ float half_hi<__hip_bfloat16>(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <typename ST>
+__device__ __forceinline__ float to_f32(ST v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+
+// Round to the storage type (to nearest, ties to even).
+template <typename ST>
+__device__ __forceinline__ ST from_f32(float v);
+template <>
+__device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
+template <>
+__device__ __forceinline__ __hip_bfloat16 from_f32<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+
+// Pixel `pix` of an image with NB interleaved bands of type ST.
+template <typename ST, int NB>
+__device__ __forceinline__ Px<NB> load_px(const ST *__restrict__ img, long long pix) {
+    Px<NB> p;
+    if constexpr (sizeof(ST) == 4) {
+        const float *f = reinterpret_cast<const float *>(img) + pix * NB;
+        if constexpr (NB == 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(f);
+            p.v[0] = v.x;
+            p.v[1] = v.y;
+            p.v[2] = v.z;
+            p.v[3] = v.w;
+        } else if constexpr (NB == 2) {
+            const float2 v = *reinterpret_cast<const float2 *>(f);
+            p.v[0] = v.x;
+            p.v[1] = v.y;
+        } else {
+            p.v[0] = f[0];
+        }
+    } else {
+        const unsigned short *h = reinterpret_cast<const unsigned short *>(img) + pix * NB;
+        if constexpr (NB == 4) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(h);
+            p.v[0] = half_lo<ST>(v.x);
+            p.v[1] = half_hi<ST>(v.x);
+            p.v[2] = half_lo<ST>(v.y);
+            p.v[3] = half_hi<ST>(v.y);
+        } else if constexpr (NB == 2) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(h);
+            p.v[0] = half_lo<ST>(v);
+            p.v[1] = half_hi<ST>(v);
+        } else {
+            p.v[0] = half_lo<ST>((uint32_t)h[0]);
+        }
+    }
+    return p;
+}
+
+// Raw buffer loads.  The descriptor bounds the image in bytes; an offset past
+// it returns zeros without touching memory.  Lanes that do not need a value
+// get kNoLoad, so every load instruction is issued by the whole wave (no
+// branch around it) and the compiler can count outstanding loads statically,
+// which keeps several loads in flight; no bytes are read for those lanes.
+constexpr uint32_t kNoLoad = 0xfffffff0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// One pixel (NB values of type ST) at byte offset byte_off.
+template <typename ST, int NB>
+__device__ __forceinline__ Px<NB> buffer_px(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    Px<NB> p;
+    if constexpr (sizeof(ST) == 4) {
+        if constexpr (NB == 4) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) p.v[b] = __int_as_float(v[b]);
+        } else if constexpr (NB == 2) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+            p.v[0] = __int_as_float(v[0]);
+            p.v[1] = __int_as_float(v[1]);
+        } else {
+            p.v[0] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+        }
+    } else {
+        if constexpr (NB == 4) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+            p.v[0] = half_lo<ST>((uint32_t)v[0]);
+            p.v[1] = half_hi<ST>((uint32_t)v[0]);
+            p.v[2] = half_lo<ST>((uint32_t)v[1]);
+            p.v[3] = half_hi<ST>((uint32_t)v[1]);
+        } else if constexpr (NB == 2) {
+            const uint32_t v = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+            p.v[0] = half_lo<ST>(v);
+            p.v[1] = half_hi<ST>(v);
+        } else {
+            p.v[0] = half_lo<ST>((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+        }
+    }
+    return p;
+}
+
+// Band means of eq. (15) from the fixed-point sums of one slot.
+template <int NB>
+__device__ __forceinline__ void slot_means(const Totals &t, long long hw, float inv_fix, float (&cp)[NB],
+                                           float (&cm)[NB]) {
+    const unsigned long long np = t.nplus;
+    const long long nm = hw - (long long)np;
+    const float fnp = (float)np, fnm = (float)nm;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const long long S = t.sum[b];
+        const long long T = t.total[b];
+        cp[b] = np > 0 ? ((float)S * inv_fix) / fnp : 0.f;
+        cm[b] = nm > 0 ? ((float)(T - S) * inv_fix) / fnm : 0.f;
+    }
+}
+
+// Numerator of eq. (17): D = sum_b (c+ - c-)(2 I_b - c+ - c-), with
+// a_b = c+ - c- and m_b = c+ + c-.  The same expression is used by every
+// kernel so that the normaliser pass and the update agree bit for bit.
+template <int NB>
+__device__ __forceinline__ float region_D(const Px<NB> &p, const float (&a)[NB], const float (&m)[NB]) {
+    float d = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) d = fmaf(a[b], fmaf(2.f, p.v[b], -m[b]), d);
+    return d;
+}
+
+// Horizontal Gaussian of a binary row at image column x (eq. (13) values
+// +1 / -1, zero outside the image).  `row` holds kRowWords bit words whose bit
+// 0 is image column x0 - 32; xb is the bit position of column x.
+__device__ __forceinline__ float hconv_bits(const uint32_t *row, int xb, int x, int W, int r, int ts,
+                                            int nch, const float *lut, const float *cum) {
+    const int ws = xb - r;
+    const int wi = ws >> 5;
+    const uint32_t lo = row[wi], hi = row[wi + 1];
+    const uint32_t full = (1u << ts) - 1u;
+    uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(ws & 31)) & full;
+    float corr = 0.f;
+    const int left = r - x;             // taps left of column 0
+    const int right = x + r - (W - 1);  // taps right of column W - 1
+    if (left > 0) {
+        win |= (1u << left) - 1u;
+        corr = cum[left];
+    }
+    if (right > 0) {
+        win |= full & ~((1u << (ts - right)) - 1u);
+        corr += cum[right];
+    }
+    float h = lut[win & 63u];
+    for (int c = 1; c < nch; ++c) h += lut[c * 64 + ((win >> (6 * c)) & 63u)];
+    return h - corr;
+}
+
+// Vertical Gaussian: acc = sum_j k[j] col[j * stride], j = 0 .. ts-1, in order.
+__device__ __forceinline__ float vconv(const float *col, int stride, const float *k, int ts) {
+    float acc = 0.f;
+    for (int j = 0; j < ts; ++j) acc = fmaf(k[j], col[j * stride], acc);
+    return acc;
+}
+
+// LDS carve-up shared by the tile kernels.
+struct TileSmem {
+    float *lut, *cum, *k, *h, *phi, *red;
+    uint32_t *bits, *bn;
+};
+
+__host__ __device__ inline int tile_ru(int edge, int r) { return edge ? 0 : r; }
+
+__host__ __device__ inline size_t tile_smem_words(int r, int nch, int edge) {
+    const int RU = tile_ru(edge, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    size_t hwords = (size_t)BH * PW;
+    if ((size_t)UH * kTileX > hwords) hwords = (size_t)UH * kTileX;
+    return (size_t)nch * 64 + 36 + 32 + (size_t)BH * kRowWords + (size_t)UH * kRowWords + hwords +
+           (size_t)PH * PW + 4 * 8;
+}
+
+__device__ __forceinline__ TileSmem carve(float *smem, int r, int nch, int edge) {
+    const int RU = tile_ru(edge, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    size_t hwords = (size_t)BH * PW;
+    if ((size_t)UH * kTileX > hwords) hwords = (size_t)UH * kTileX;
+    TileSmem t;
+    float *p = smem;
+    t.lut = p;
+    p += nch * 64;
+    t.cum = p;
+    p += 36;
+    t.k = p;
+    p += 32;
+    t.bits = reinterpret_cast<uint32_t *>(p);
+    p += BH * kRowWords;
+    t.bn = reinterpret_cast<uint32_t *>(p);
+    p += UH * kRowWords;
+    t.h = p;
+    p += hwords;
+    t.phi = p;
+    p += PH * PW;
+    t.red = p;
+    return t;
+}
+
+__device__ __forceinline__ void stage_tables(const TileSmem &s, const Taps *__restrict__ taps, int ts, int nch) {
+    for (int i = threadIdx.x; i < nch * 64; i += kThreads) s.lut[i] = (&taps->lut[0][0])[i];
+    for (int i = threadIdx.x; i <= ts; i += kThreads) s.cum[i] = taps->cum[i];
+    for (int i = threadIdx.x; i < ts; i += kThreads) s.k[i] = taps->k[i];
+}
+
+// Stage bit rows [row0, row0 + nrows) of the tile's 4-word window starting
+// at global word (x0 / 32) - 1; out-of-image rows and words read as 0.
+__device__ __forceinline__ void stage_bits(uint32_t *dst, const uint32_t *__restrict__ bits, int row0, int nrows,
+                                           int x0, int H, int WW) {
+    const int wb0 = (x0 >> 5) - 1;
+    for (int i = threadIdx.x; i < nrows * kRowWords; i += kThreads) {
+        const int row = i / kRowWords, wc = i - row * kRowWords;
+        const int y = row0 + row, gw = wb0 + wc;
+        uint32_t v = 0;
+        if (wc < 4 && y >= 0 && y < H && gw >= 0 && gw < WW) v = bits[(size_t)y * WW + gw];
+        dst[i] = v;
+    }
+}
+
+// Phase D: sign of G * b on the owned tile (b given in s.bn for rows
+// y0 - r .. y0 + kTileY + r), accumulated into per-thread sums.  When raw is
+// set the LSF is b itself.  Shared by the step kernel and the statistics
+// kernel so that both produce identical partial sums.
+template <int NB, typename ST>
+__device__ __forceinline__ void stats_tile(const TileSmem &s, const ST *__restrict__ img, int x0, int y0,
+                                           int H, int W, int r, int ts, int nch, int raw, float (&acc)[NB],
+                                           int &cnt) {
+    const int UH = kTileY + 2 * r;
+    if (!raw) {
+        for (int i = threadIdx.x; i < UH * kTileX; i += kThreads) {
+            const int uy = i / kTileX, ox = i - uy * kTileX;
+            const int y = y0 - r + uy, x = x0 + ox;
+            float h = 0.f;
+            if (y >= 0 && y < H && x < W) h = hconv_bits(s.bn + uy * kRowWords, ox + 32, x, W, r, ts, nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    cnt = 0;
+    for (int k = 0; k < (kTileX * kTileY) / kThreads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int oy = i / kTileX, ox = i - oy * kTileX;
+        const int y = y0 + oy, x = x0 + ox;
+        if (y < H && x < W) {
+            bool inside;
+            if (raw) {
+                const uint32_t w = s.bn[(oy + r) * kRowWords + ((ox + 32) >> 5)];
+                inside = (w >> ((ox + 32) & 31)) & 1u;
+            } else {
+                inside = vconv(s.h + oy * kTileX + ox, kTileX, s.k, ts) >= 0.f;
+            }
+            if (inside) {
+                const Px<NB> p = load_px<ST, NB>(img, (long long)y * W + x);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+                ++cnt;
+            }
+        }
+    }
+}
+
+// Workgroup reduction of (NB sums, count, flips) and one atomic per value.
+template <int NB>
+__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Bin *out,
+                                             float fix, bool with_sums) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (with_sums) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = wave_sum_f(acc[b]);
+        cnt = wave_sum_i(cnt);
+    }
+    flips = wave_sum_i(flips);
+    if (lane == 0) {
+        float *rw = s.red + wave * 8;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rw[b] = acc[b];
+        reinterpret_cast<int *>(rw)[6] = cnt;
+        reinterpret_cast<int *>(rw)[7] = flips;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float S[NB];
+        int C = 0, F = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) S[b] = 0.f;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            const float *rw = s.red + w * 8;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) S[b] += rw[b];
+            C += reinterpret_cast<const int *>(rw)[6];
+            F += reinterpret_cast<const int *>(rw)[7];
+        }
+        if (with_sums) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]),
+                          (unsigned long long)__float2ll_rn(S[b] * fix));
+            atomicAdd(&out->nplus, (unsigned long long)C);
+        }
+        if (F) atomicAdd(&out->flips, (unsigned long long)F);
+    }
+}
+
+
+constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 8;
+
+__device__ __forceinline__ unsigned long long mkey_of(float absd, unsigned int pix) {
+    return ((unsigned long long)__float_as_uint(absd) << 32) | (unsigned long long)(0xffffffffu - pix);
+}
+
+// ------------------------------------------------------------- fast step
+//
+// Same arithmetic as step_kernel, organised for throughput when the template
+// radius R is a compile-time constant: tiles of 96 owned columns x 64 owned
+// rows, lanes mapped to columns, each wave taking a vertical segment of rows
+// so that the vertical Gaussian runs over a register window (each horizontal
+// sum computed once per segment).  The 6-bit lookup tables live in one VGPR
+// per chunk and are read with ds_bpermute (a crossbar, no bank conflicts).
+
+constexpr int kFX = 96;        // owned columns (3 bit words)
+constexpr int kFY = 64;        // owned rows
+constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 - 1 .. x0/32 + 4
+
+constexpr int kSB = 8;         // rows per block of the rolling vertical window
+constexpr int kCG = 4;         // rows per group of data-term loads in the binarisation phase
+
+template <int R, bool EDGE>
+struct FastGeom {
+    static constexpr int TS = 2 * R + 1;
+    static constexpr int RU = EDGE ? 0 : R;      // halo of the binarised field
+    static constexpr int UH = kFY + 2 * RU;      // rows where b^n is computed
+    static constexpr int PH = UH + 2;            // rows of phi^n
+    static constexpr int PW = kFX + 2 * RU + 2;  // columns of phi^n (<= 128)
+    static constexpr int NBLK = (PH + 2 * kSB - 1) / (2 * kSB);  // window blocks per segment
+    static constexpr int SEG = NBLK * kSB;       // phi rows per wave (2 segments x 2 chunks)
+    static constexpr int PHP = 2 * SEG;          // phi rows allocated (>= PH)
+    static constexpr int BH = PHP + 2 * R;       // staged rows of b^{n-1}
+    static constexpr int SEGD = kFY / 2;         // statistics rows per wave
+    static constexpr int NCH = (TS + 5) / 6;     // lookup chunks
+    static constexpr int PS = PW;                // phi row stride (floats)
+    static constexpr int smem_words = BH * kFWords + PHP * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
+};
+
+template <int NCH>
+__device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, int (&lut)[NCH]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) lut[c] = __float_as_int(taps->lut[c][lane]);
+}
+
+// Horizontal Gaussian of a binary row, as hconv_bits; must be called with all
+// 64 lanes active (ds_bpermute).  `border` (uniform) enables the zero-padding
+// correction, needed only by tiles that touch the left or right image edge.
+template <int R, int NCH>
+__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, int x, int W, bool border,
+                                            const int (&lut)[NCH], const float *__restrict__ cum) {
+    constexpr int TS = 2 * R + 1;
+    constexpr uint32_t FULL = (1u << TS) - 1u;
+    const int ws = xb - R;
+    const int wi = ws >> 5;
+    uint32_t win = __builtin_amdgcn_alignbit(row[wi + 1], row[wi], (uint32_t)(ws & 31)) & FULL;
+    float corr = 0.f;
+    if (border) {
+        const int left = min(R - x, TS);
+        const int right = min(x + R - (W - 1), TS);
+        if (left > 0) {
+            win |= (1u << left) - 1u;
+            corr = cum[left];
+        }
+        if (right > 0) {
+            win |= FULL & ~((1u << (TS - right)) - 1u);
+            corr += cum[right];
+        }
+    }
+    float h = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int idx = (int)((win >> (6 * c)) & 63u);
+        h += __int_as_float(__builtin_amdgcn_ds_bpermute(idx << 2, lut[c]));
+    }
+    return h - corr;
+}
+
+__device__ __forceinline__ uint32_t bits_extract(unsigned long long m, int off, int k) {
+    const int d = 32 * k - off;  // right shift that brings word k of the row to bit 0
+    if (d >= 64 || d <= -32) return 0u;
+    return d >= 0 ? (uint32_t)(m >> d) : (uint32_t)(m << (-d));
+}
+
+// 0 if bits [lo, hi) of a staged row are all 0, 1 if all 1, 2 if mixed.
+__device__ __forceinline__ int range_code(const uint32_t *row, int lo, int hi) {
+    uint32_t any1 = 0u, any0 = 0u;
+    const int j0 = lo >> 5, j1 = (hi - 1) >> 5;
+    for (int j = j0; j <= j1; ++j) {
+        uint32_t m = ~0u;
+        if (j == j0) m &= ~0u << (lo & 31);
+        if (j == j1) m &= ~0u >> (31 - ((hi - 1) & 31));
+        any1 |= row[j] & m;
+        any0 |= ~row[j] & m;
+    }
+    return (any1 && any0) ? 2 : (any1 ? 1 : 0);
+}
+
+// Wave-uniform test: do rows [row0, row0 + n) all carry code c (0 or 1)?
+// Returns 1 (all ones), 0 (all zeros) or -1.  n <= 64.
+__device__ __forceinline__ int block_code(const int *codes, int row0, int n, int chunk) {
+    const int lane = (int)threadIdx.x & 63;
+    const int c = lane < n ? codes[(row0 + lane) * 2 + chunk] : -1;
+    const unsigned long long full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    if (__ballot(c == 1) == full) return 1;
+    if (__ballot(c == 0) == full) return 0;
+    return -1;
+}
+
+// Stage bit rows [row0, row0 + nrows) of global words x0/32 - 1 .. x0/32 + 4.
+__device__ __forceinline__ void stage_bits_fast(uint32_t *dst, const uint32_t *__restrict__ bits, int row0,
+                                                int nrows, int x0, int H, int WW) {
+    const int wb0 = (x0 >> 5) - 1;
+    for (int i = threadIdx.x; i < nrows * kFWords; i += kThreads) {
+        const int row = i / kFWords, wc = i - row * kFWords;
+        const int y = row0 + row, gw = wb0 + wc;
+        uint32_t v = 0;
+        if (wc < kFWords - 1 && y >= 0 && y < H && gw >= 0 && gw < WW) v = bits[(size_t)y * WW + gw];
+        dst[i] = v;
+    }
+}
+
+// Codes of the owned-column spans of the U rows (b^n): chunk 0 = owned
+// columns 0..63, chunk 1 = 64..95, each with its R halo.
+template <int R>
+__device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, int *codes) {
+    for (int i = (int)threadIdx.x; i < nrows * 2; i += kThreads) {
+        const int row = i >> 1, c = i & 1;
+        codes[i] = c == 0 ? range_code(bn + row * kFWords, 32 - R, 96 + R)
+                          : range_code(bn + row * kFWords, 96 - R, 128 + R);
+    }
+}
+
+// Statistics of phi^{n+1} = G * b on the owned 96 x 64 tile (b in `bn`, rows
+// y0 - R .. y0 + 64 + R, bit 0 of each row = column x0 - 32).  raw: phi = b.
+// Every owned pixel of the image is read once (dense streaming); blocks of
+// 8 rows whose whole bit window is uniform take the sign without the
+// Gaussian sums (their value would be the same constant in every pixel).
+template <int R, int NB, typename ST>
+__device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes, const ST *__restrict__ img,
+                                           int x0, int y0, int H, int W, bool border, bool raw,
+                                           const int (&lut)[FastGeom<R, false>::NCH], const float (&kk)[2 * R + 1],
+                                           const float *__restrict__ cum, float (&acc)[NB], int &cnt) {
+    using G = FastGeom<R, false>;
+    static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int chunk = wave & 1, seg = wave >> 1;
+    const int ox = chunk * 64 + lane;
+    const int x = x0 + ox;
+    const bool colok = ox < kFX && x < W;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    cnt = 0;
+    const int urow0 = seg * G::SEGD;  // U row of output row 0 of this segment's window
+    static_assert(G::SEGD <= 32, "inside flags of a segment fit one 32-bit mask");
+    // Pass 1: which output rows of this lane's column are on the + side.
+    uint32_t inmask = 0u;
+    if (raw) {
+        for (int j = 0; j < G::SEGD; ++j) {
+            const uint32_t wd = bn[(urow0 + j + R) * kFWords + ((ox + 32) >> 5)];
+            inmask |= ((wd >> ((ox + 32) & 31)) & 1u) << j;
+        }
+    } else {
+        constexpr int NW = 2 * R + kSB;
+        float win[NW];
+        bool have_win = false;  // win[0 .. 2R) holds rows rb .. rb + 2R of the current block
+#pragma unroll 1
+        for (int blk = 0; blk < G::SEGD / kSB; ++blk) {
+            const int rb = urow0 + blk * kSB;
+            const int yb = y0 - R + rb;  // image row of U row rb
+            int uni = -1;
+            if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
+            if (uni >= 0) {
+                // Uniform block: every pixel has the sign of the constant.
+                if (uni == 1) inmask |= ((1u << kSB) - 1u) << (blk * kSB);
+                have_win = false;
+                continue;
+            }
+            if (!have_win) {
+#pragma unroll
+                for (int t = 0; t < 2 * R; ++t) {
+                    const int y = yb + t;
+                    const float v = hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, x, W, border, lut, cum);
+                    win[t] = (y >= 0 && y < H) ? v : 0.f;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kSB; ++t) {
+                const int urow = rb + 2 * R + t;
+                const int y = y0 - R + urow;
+                const float v = hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, x, W, border, lut, cum);
+                win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < kSB; ++j) {
+                float ph = 0.f;
+#pragma unroll
+                for (int i = 0; i < 2 * R + 1; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                inmask |= (ph >= 0.f ? 1u : 0u) << (blk * kSB + j);
+            }
+#pragma unroll
+            for (int t = 0; t < 2 * R; ++t) win[t] = win[t + kSB];
+            have_win = true;
+        }
+    }
+    // Pass 2: add the image values of the + side rows in row order.  Loads
+    // of one group of rows are in flight while the previous group is added;
+    // only + side pixels are read (the others get kNoLoad).
+    if (!colok) inmask = 0u;
+    const int nrows = min(G::SEGD, H - (y0 + urow0));
+    if (nrows < G::SEGD) inmask &= nrows > 0 ? ((1u << nrows) - 1u) : 0u;
+    constexpr int PB = NB * (int)sizeof(ST);  // bytes per pixel
+    const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (uint32_t)((unsigned long long)H * W * PB));
+    const uint32_t off0 = (uint32_t)(((y0 + urow0) * W + x) * PB);
+    const uint32_t rstride = (uint32_t)(W * PB);
+    constexpr int GR = 4;
+    Px<NB> ba[GR], bb[GR];
+    auto load_group = [&](Px<NB>(&buf)[GR], int g) {
+#pragma unroll
+        for (int i = 0; i < GR; ++i) {
+            const int j = g * GR + i;
+            buf[i] = buffer_px<ST, NB>(rs, ((inmask >> j) & 1u) ? off0 + j * rstride : kNoLoad);
+        }
+    };
+    auto add_group = [&](const Px<NB>(&buf)[GR], int g) {
+#pragma unroll
+        for (int i = 0; i < GR; ++i) {
+            const bool in = (inmask >> (g * GR + i)) & 1u;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] += in ? buf[i].v[b] : 0.f;
+            cnt += in ? 1 : 0;
+        }
+    };
+    constexpr int NG = G::SEGD / GR;
+    static_assert(NG % 2 == 0, "groups come in pairs");
+    load_group(ba, 0);
+#pragma unroll 1
+    for (int g = 0; g < NG; g += 2) {
+        load_group(bb, g + 1);
+        add_group(ba, g);
+        if (g + 2 < NG) load_group(ba, g + 2);
+        add_group(bb, g + 1);
+    }
+}
+
+// Tile of this workgroup.  Workgroup j runs on XCD j % 8 (the hardware
+// dispatches workgroups round-robin over the 8 XCDs); each XCD takes a
+// contiguous band of tile rows, so tiles that re-read each other's halo share
+// that XCD's L2.  The grid is the tile count rounded up to a multiple of 8;
+// returns -1 for the spare workgroups.
+__device__ __forceinline__ int tile_of(int ntiles) {
+    const int g = gridDim.x, j = blockIdx.x;
+    if ((g & 7) != 0) return j < ntiles ? j : -1;
+    const int xcd = j & 7, per = g >> 3;
+    const int lo = (int)((long long)ntiles * xcd / 8), hi = (int)((long long)ntiles * (xcd + 1) / 8);
+    const int t = lo + (j >> 3);
+    return (t < hi && (j >> 3) < per) ? t : -1;
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Workgroups may use more than 64 KB of LDS (gfx950 has 160 KB per CU) for
+// large templates; raise the per-kernel limit when a launch needs it.
+template <typename K>
+static hipError_t ensure_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+static inline dim3 tile_grid(int H, int W) { return dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY); }
+
+static inline unsigned int stream_blocks(long long n, int per_thread = 1) {
+    long long b = (n + (long long)kThreads * per_thread - 1) / ((long long)kThreads * per_thread);
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (unsigned int)b;
+}
+}  // namespace lse

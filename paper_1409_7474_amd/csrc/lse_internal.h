@@ -53,7 +53,7 @@ struct DevState {
     int bad;                      // nonzero: bad value found by init
     int done;                     // sticky "stopped" flag (Step 5)
     int iters;                    // iterations executed since init / set_mask
-    int pad0;
+    int raw;                      // iteration 0 starts from the binary function itself (no smoothing)
     float last_cp[4], last_cm[4];
     float last_M;
     int pad1[3];
@@ -70,6 +70,9 @@ struct Taps {
     float pad[31];
 };
 
+// Arguments of one host-launched kernel on one image (initial statistics,
+// LSF export, profiling count, and the step for templates outside the
+// compile-time radius range).
 struct StepArgs {
     const void *img;          // storage image (NB interleaved bands) or edge map
     const float *boxes;       // region term, B > 1: per-block band min / max (normaliser pruning)
@@ -88,20 +91,70 @@ struct StepArgs {
     long long hw;
 };
 
-// Kernel launchers (lse_kernels.hip).  All return hipSuccess or the launch error.
+// Device-resident arguments of one image for the step and normaliser
+// kernels.  A single image keeps one in its workspace (n0 = 0: launch k is
+// iteration k); a batch keeps an array of them plus a workgroup map, so that
+// one launch advances every image of the batch by one iteration.
+struct alignas(16) ImgArgs {
+    const void *img;          // region: image (NB interleaved bands); edge: edge map g (storage type)
+    const float *boxes;       // region, B > 1: per-block band min / max
+    uint32_t *bits[2];        // iteration n reads bits[n & 1] and writes bits[(n + 1) & 1]
+    DevState *st;
+    const Taps *taps;
+    int H, W, WW;
+    int tiles;                // workgroup tiles of the step kernel
+    float dt, fix, inv_fix;
+    int target;               // iterations n >= target are not run
+    long long hw;
+    int n0;                   // iteration index of launch k = 0
+    int mgroups;              // workgroups of the normaliser pass (B > 1)
+};
+
+constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare workgroup
+
+// Kernels whose code depends on the storage type T of the resident image
+// (float, __half or __hip_bfloat16).  The member functions are defined in
+// lse_store.h and instantiated once per type (lse_store_*.hip).
+template <typename T>
+struct Store {
+    static hipError_t init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
+                                 DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s);
+    static hipError_t edge_g(const float *Is, void *g, int H, int W, hipStream_t s);
+    static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
+    static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
+    static hipError_t step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
+                           int r, int NB, int edge, hipStream_t s);
+    static hipError_t step_generic(const StepArgs &a, int NB, int edge, hipStream_t s);
+    static hipError_t mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
+                            int NB, hipStream_t s);
+};
+
+// Kernel launchers (lse_kernels.hip).  All return hipSuccess or the launch
+// error; `storage` is an lse_dtype.
 size_t tile_smem_bytes(int r, int nch, int edge);
-hipError_t launch_init_state(DevState *st, hipStream_t s);
-hipError_t launch_reset_state(DevState *st, hipStream_t s);
-hipError_t launch_init_image(const void *src, int src_dtype, int B, int NB, float *dst, long long npx,
+bool fast_radius(int r);                 // the step kernel has a compiled variant for radius r
+int step_tiles(int H, int W);            // workgroup tiles of the step kernel for an H x W image
+int mpass_groups(int H, int W);          // workgroups of the normaliser pass
+hipError_t launch_init_state(DevState *st, int raw, hipStream_t s);
+hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);
+hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
                              DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s);
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s);
-hipError_t launch_stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
+hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slot, hipStream_t s);
 hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
-                           float *g, hipStream_t s);
-hipError_t launch_mpass(const StepArgs &a, int NB, hipStream_t s);
+                           void *g, int storage, hipStream_t s);
 size_t mbox_floats(int H, int W, int NB);
-hipError_t launch_mbox(const float *img, int H, int W, int NB, float *boxes, hipStream_t s);
-hipError_t launch_step(const StepArgs &a, int NB, int edge, hipStream_t s);
+hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float *boxes, hipStream_t s);
+// Step / normaliser launches over ImgArgs: map == nullptr runs image args[0]
+// (grid = step_launch_grid / mpass_groups); else map[blockIdx.x] holds
+// (image << unit_bits) | unit, or kNoTile.
+unsigned step_launch_grid(int tiles);
+hipError_t launch_step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop, int r,
+                       int NB, int edge, int storage, hipStream_t s);
+hipError_t launch_step_generic(const StepArgs &a, int NB, int edge, int storage, hipStream_t s);
+hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
+                        int NB, int storage, hipStream_t s);
+hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s);
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W,
                            int WW, hipStream_t s);
 hipError_t launch_lsf_out(const StepArgs &a, const uint32_t *const bits[2], int raw, float *out,

@@ -1,0 +1,1028 @@
+// Kernels templated on the storage type of the resident image (FP32, FP16 or
+// BF16) and their launchers.  Included once per storage type by
+// lse_store_f32.hip, lse_store_f16.hip and lse_store_bf16.hip, each of which
+// instantiates Store<T> for its type, so that every kernel is compiled in
+// exactly one translation unit.
+#pragma once
+
+#include "lse_device.h"
+
+namespace lse {
+
+// Convert the caller's image to the interleaved storage of type ST (NB >= B
+// bands, extra bands zero), check values, and reduce per-band min / max and
+// totals of the stored (rounded) values, so that the statistics describe
+// exactly the image the iterations read.  want_gray: write the band mean
+// times gray_scale (FP32) instead, for the edge map.
+template <typename T, typename ST>
+__global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restrict__ src, int B, int NB,
+                                                              ST *__restrict__ dst, long long npx,
+                                                              DevState *st, float fix, int want_gray,
+                                                              float gray_scale) {
+    float sum[4] = {0.f, 0.f, 0.f, 0.f};
+    float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < npx; i += (long long)gridDim.x * kThreads) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b < B) {
+                v[b] = to_f32<T>(src[i * B + b]);
+                if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // also catches NaN / Inf
+            }
+        }
+        if (want_gray) {
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < B) s += v[b];
+            dst[i] = from_f32<ST>(gray_scale * (s / (float)B));
+        } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (b < NB) {
+                    const ST q = from_f32<ST>(v[b]);
+                    dst[i * NB + b] = q;
+                    v[b] = to_f32<ST>(q);
+                    if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // overflow of the storage type
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b < B) {
+                sum[b] += v[b];
+                mn[b] = fminf(mn[b], v[b]);
+                mx[b] = fmaxf(mx[b], v[b]);
+            }
+        }
+    }
+    __shared__ float red[kThreads / 64][4][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (bad) st->bad = 1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float s = wave_sum_f(sum[b]);
+        const float lo = wave_min_f(mn[b]);
+        const float hi = wave_max_f(mx[b]);
+        if (lane == 0) {
+            red[wave][b][0] = s;
+            red[wave][b][1] = lo;
+            red[wave][b][2] = hi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ImgBin &bin = st->img[blockIdx.x % kBins];
+        for (int b = 0; b < B; ++b) {
+            float s = 0.f, lo = INFINITY, hi = -INFINITY;
+            for (int w = 0; w < kThreads / 64; ++w) {
+                s += red[w][b][0];
+                lo = fminf(lo, red[w][b][1]);
+                hi = fmaxf(hi, red[w][b][2]);
+            }
+            if (!want_gray)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&bin.total[b]),
+                          (unsigned long long)__float2ll_rn(s * fix));
+            atomicMin(&bin.imin_key[b], float_key(lo));
+            atomicMax(&bin.imax_key[b], float_key(hi));
+        }
+    }
+}
+
+// Region statistics of the LSF given by `bits` (raw: phi = b; else phi = G * b).
+template <int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void stats_kernel(StepArgs A, int raw, int slot) {
+    extern __shared__ float smem[];
+    const TileSmem s = carve(smem, A.r, A.nch, 0);
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    stage_tables(s, A.taps, A.ts, A.nch);
+    stage_bits(s.bn, A.bits_in, y0 - A.r, kTileY + 2 * A.r, x0, A.H, A.WW);
+    __syncthreads();
+    float acc[NB];
+    int cnt;
+    stats_tile<NB, ST>(s, static_cast<const ST *>(A.img), x0, y0, A.H, A.W, A.r, A.ts, A.nch, raw, acc, cnt);
+    reduce_commit<NB>(s, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
+}
+
+// g = 1 / (1 + |grad Is|^2), eq. (14), stored as ST; central differences
+// inside, one-sided at the border.
+template <typename ST>
+__global__ void edge_g_kernel(const float *__restrict__ Is, ST *__restrict__ g, int H, int W) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * W) return;
+    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    const float *row = Is + (size_t)y * W;
+    float gx, gy;
+    if (x == 0)
+        gx = row[1] - row[0];
+    else if (x == W - 1)
+        gx = row[W - 1] - row[W - 2];
+    else
+        gx = 0.5f * (row[x + 1] - row[x - 1]);
+    if (y == 0)
+        gy = Is[(size_t)W + x] - Is[x];
+    else if (y == H - 1)
+        gy = Is[(size_t)(H - 1) * W + x] - Is[(size_t)(H - 2) * W + x];
+    else
+        gy = 0.5f * (Is[(size_t)(y + 1) * W + x] - Is[(size_t)(y - 1) * W + x]);
+    g[i] = from_f32<ST>(1.f / (1.f + (gx * gx + gy * gy)));
+}
+
+// ------------------------------------------------------------ normaliser
+
+// Normaliser M = max_x |D(x)| of eq. (17), for B > 1 (B = 1 uses the closed
+// form from the image min / max, since D is then monotone in I).
+//
+// Exact, with pruning: the image is cut into 64 x 32 blocks whose per-band
+// min / max are stored at init.  D is affine in the pixel value, so over a
+// block |D| is bounded by its value at the box corners; a rounding margin
+// makes the bound hold for the FP32 D of every pixel.  The previous
+// iteration's maximising pixel, evaluated with the current means, gives a
+// lower bound LB <= M; only blocks whose bound reaches LB can hold the
+// maximum, and only those are read.  With no previous pixel (LB = 0) every
+// block is read.  The result (value and pixel) equals a full scan bit for bit.
+template <int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void mbox_kernel(const ST *__restrict__ img, int H, int W,
+                                                         float *__restrict__ boxes) {
+    __shared__ float red[kThreads / 64][2 * NB];
+    const int nbx = (W + kMBX - 1) / kMBX;
+    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float lo[NB], hi[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        lo[b] = INFINITY;
+        hi[b] = -INFINITY;
+    }
+    const int x = bx * kMBX + lane;
+    for (int r = wave; r < kMBY; r += kThreads / 64) {
+        const int y = by * kMBY + r;
+        if (x < W && y < H) {
+            const Px<NB> p = load_px<ST, NB>(img, (long long)y * W + x);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                lo[b] = fminf(lo[b], p.v[b]);
+                hi[b] = fmaxf(hi[b], p.v[b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        lo[b] = wave_min_f(lo[b]);
+        hi[b] = wave_max_f(hi[b]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            red[wave][b] = lo[b];
+            red[wave][NB + b] = hi[b];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NB) {
+        const int k = threadIdx.x;
+        float v = red[0][k];
+        for (int w = 1; w < kThreads / 64; ++w) v = k < NB ? fminf(v, red[w][k]) : fmaxf(v, red[w][k]);
+        boxes[(size_t)blockIdx.x * 2 * NB + k] = v;
+    }
+}
+
+// Workgroup -> (image, unit) of a launch: single image (map == nullptr) or an
+// entry of a batch map, image index in the high bits, unit (tile or block
+// group) in the low `unit_bits` bits.  Returns false for a spare workgroup.
+__device__ __forceinline__ bool batch_unit(const uint32_t *__restrict__ map, int unit_bits, int &img, int &unit) {
+    if (!map) {
+        img = 0;
+        unit = (int)blockIdx.x;
+        return true;
+    }
+    const uint32_t v = map[blockIdx.x];
+    if (v == kNoTile) return false;
+    img = (int)(v >> unit_bits);
+    unit = (int)(v & ((1u << unit_bits) - 1u));
+    return true;
+}
+
+template <int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restrict__ args,
+                                                          const uint32_t *__restrict__ map, int unit_bits, int k,
+                                                          int stop) {
+    int ii, grp;
+    if (!batch_unit(map, unit_bits, ii, grp)) return;
+    const ImgArgs &A = args[ii];
+    const int n = A.n0 + k;
+    if (n >= A.target) return;
+    DevState *st = A.st;
+    const int sl = n % 3;
+    __shared__ Totals tot;
+    __shared__ unsigned long long prev_key, wkey[kThreads / 64];
+    __shared__ int scan_list[kMBlocksPerWG];
+    __shared__ int nscan;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 2) {  // previous iteration's maximum (slot n - 1 == (n + 2) % 3)
+        const unsigned long long pk = wave_max_u64(st->slot[(n + 2) % 3][lane].mkey);
+        if (lane == 0) prev_key = pk;
+    }
+    // This workgroup's block boxes (lane k < kMBlocksPerWG of wave 0) do not
+    // depend on the statistics: load them before the statistics barrier.
+    const int nbx = (A.W + kMBX - 1) / kMBX, nby = (A.H + kMBY - 1) / kMBY, nblk = nbx * nby;
+    const int myblk = grp * kMBlocksPerWG + lane;
+    float blo[NB], bhi[NB];
+    if (wave == 0 && lane < kMBlocksPerWG && myblk < nblk) {
+        const float *bx = A.boxes + (size_t)myblk * 2 * NB;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            blo[b] = bx[b];
+            bhi[b] = bx[NB + b];
+        }
+    }
+    load_totals(st, sl, true, &tot);
+    if (tot.done || tot.bad || (stop && tot.flips == 0)) return;
+    float cp[NB], cm[NB], a[NB], m[NB];
+    slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        a[b] = cp[b] - cm[b];
+        m[b] = cp[b] + cm[b];
+    }
+    const ST *img = static_cast<const ST *>(A.img);
+    const unsigned int ppix = 0xffffffffu - (unsigned int)(prev_key & 0xffffffffu);
+    const float lb = (long long)ppix < A.hw ? fabsf(region_D<NB>(load_px<ST, NB>(img, ppix), a, m)) : 0.f;
+
+    if (wave == 0) {
+        const int blk = myblk;
+        bool need = false;
+        if (lane < kMBlocksPerWG && blk < nblk) {
+            float dmax = 0.f, dmin = 0.f, scale = 0.f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float lo = blo[b], hi = bhi[b];
+                const float tl = a[b] * (2.f * lo - m[b]), th = a[b] * (2.f * hi - m[b]);
+                dmax += fmaxf(tl, th);
+                dmin += fminf(tl, th);
+                scale += fabsf(a[b]) * (2.f * fmaxf(fabsf(lo), fabsf(hi)) + fabsf(m[b]));
+            }
+            // |FP32 D - exact D| <= ~6 u scale at any pixel and for dmax/dmin;
+            // 2^-18 scale is a wide margin over both.
+            const float ub = fmaxf(fabsf(dmax), fabsf(dmin)) + scale * 3.814697265625e-06f;
+            need = ub >= lb;
+        }
+        const unsigned long long bal = __ballot(need);
+        if (lane == 0) nscan = __popcll(bal);
+        if (need) scan_list[__popcll(bal & ((1ull << lane) - 1ull))] = blk;
+    }
+    __syncthreads();
+    unsigned long long best = 0ull;
+    for (int q = 0; q < nscan; ++q) {
+        const int blk = scan_list[q];
+        const int bx = blk % nbx, by = blk / nbx;
+        const int x = bx * kMBX + lane;
+        for (int r = wave; r < kMBY; r += kThreads / 64) {
+            const int y = by * kMBY + r;
+            if (x < A.W && y < A.H) {
+                const unsigned int pix = (unsigned int)((long long)y * A.W + x);
+                const float d = fabsf(region_D<NB>(load_px<ST, NB>(img, pix), a, m));
+                const unsigned long long key = mkey_of(d, pix);
+                best = key > best ? key : best;
+            }
+        }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) wkey[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) best = wkey[w] > best ? wkey[w] : best;
+        if (best) atomicMax(&st->slot[sl][blockIdx.x % kBins].mkey, best);
+    }
+}
+
+// ------------------------------------------------------------------- step
+
+template <int NB, bool EDGE, typename ST>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
+    extern __shared__ float smem[];
+    __shared__ Totals tot;
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
+    load_totals(st, sl, !EDGE, &tot);
+    {
+        int done = st->done | st->bad;
+        if (!done && A.stop && tot.flips == 0) done = 1;
+        if (done) {
+            if (lead && !st->bad) st->done = 1;
+            return;
+        }
+    }
+    const int r = A.r, ts = A.ts, nch = A.nch, H = A.H, W = A.W;
+    const int RU = tile_ru(EDGE, r);
+    const int UH = kTileY + 2 * RU;
+    const int PH = UH + 2, PW = kTileX + 2 * RU + 2;
+    const int BH = PH + 2 * r;
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    const int by0 = y0 - RU - 1 - r;      // image row of staged bit row 0
+    const int px0 = x0 - RU - 1, py0 = y0 - RU - 1;  // image coords of phi(0, 0)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const TileSmem s = carve(smem, r, nch, EDGE);
+
+    // A: tables and b^{n-1}
+    stage_tables(s, A.taps, ts, nch);
+    stage_bits(s.bits, A.bits_in, by0, BH, x0, H, A.WW);
+    __syncthreads();
+
+    // Data-term coefficients (identical in every workgroup).
+    float a[NB], m[NB], w = 0.f;
+    float cp[NB], cm[NB], M = 0.f;
+    if constexpr (!EDGE) {
+        slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            a[b] = cp[b] - cm[b];
+            m[b] = cp[b] + cm[b];
+        }
+        if constexpr (NB == 1) {
+            Px<1> lo, hi;
+            lo.v[0] = key_float(tot.imin_key[0]);
+            hi.v[0] = key_float(tot.imax_key[0]);
+            M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
+        } else {
+            M = __uint_as_float((unsigned int)(tot.mkey >> 32));
+        }
+        w = M > 0.f ? A.dt / M : 0.f;
+    }
+
+    // B: phi^n on the tile + (RU + 1) halo.
+    if (A.raw) {
+        for (int i = tid; i < PH * PW; i += kThreads) {
+            const int q = i / PW, p = i - q * PW;
+            const int y = py0 + q, x = px0 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                const int xb = x - x0 + 32;
+                const uint32_t wd = s.bits[(q + r) * kRowWords + (xb >> 5)];
+                v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+            }
+            s.phi[i] = v;
+        }
+    } else {
+        for (int i = tid; i < BH * PW; i += kThreads) {
+            const int row = i / PW, p = i - row * PW;
+            const int y = by0 + row, x = px0 + p;
+            float h = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                h = hconv_bits(s.bits + row * kRowWords, x - x0 + 32, x, W, r, ts, nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+        for (int i = tid; i < PH * PW; i += kThreads) {
+            const int q = i / PW, p = i - q * PW;
+            const int y = py0 + q, x = px0 + p;
+            float v = 0.f;
+            if (y >= 0 && y < H && x >= 0 && x < W) v = vconv(s.h + q * PW + p, PW, s.k, ts);
+            s.phi[i] = v;
+        }
+    }
+    __syncthreads();
+
+    // C: update eq. (18) and binarisation on the tile + RU halo.
+    for (int t = wave; t < UH * 2; t += kThreads / 64) {
+        const int uy = t >> 1, half = t & 1;
+        const int xb = half * 64 + lane;
+        const int x = x0 - 32 + xb, y = y0 - RU + uy;
+        bool pred = false;
+        if (xb >= 32 - RU && xb < 96 + RU && x >= 0 && x < W && y >= 0 && y < H) {
+            const int q = uy + 1, p = x - px0;
+            const float *c = s.phi + q * PW + p;
+            float gx, gy;
+            if (x == 0)
+                gx = c[1] - c[0];
+            else if (x == W - 1)
+                gx = c[0] - c[-1];
+            else
+                gx = 0.5f * (c[1] - c[-1]);
+            if (y == 0)
+                gy = c[PW] - c[0];
+            else if (y == H - 1)
+                gy = c[0] - c[-PW];
+            else
+                gy = 0.5f * (c[PW] - c[-PW]);
+            const float gm = sqrtf(gx * gx + gy * gy);
+            const long long pix = (long long)y * W + x;
+            float coef;
+            if constexpr (EDGE) {
+                coef = A.dt * to_f32<ST>(static_cast<const ST *>(A.img)[pix]);
+            } else {
+                coef = w * region_D<NB>(load_px<ST, NB>(static_cast<const ST *>(A.img), pix), a, m);
+            }
+            pred = fmaf(coef, gm, c[0]) >= 0.f;
+        }
+        const unsigned long long bal = __ballot(pred);
+        if (lane == 0) {
+            s.bn[uy * kRowWords + 2 * half] = (uint32_t)bal;
+            s.bn[uy * kRowWords + 2 * half + 1] = (uint32_t)(bal >> 32);
+            if (half) s.bn[uy * kRowWords + 4] = 0u;
+        }
+    }
+    __syncthreads();
+
+    // Owned words of b^n to global memory, and flips against b^{n-1}.
+    int flips = 0;
+    if (tid < kTileY * 2) {
+        const int row = tid >> 1, wsel = tid & 1;
+        const int y = y0 + row, gw = (x0 >> 5) + wsel;
+        if (y < H && gw < A.WW) {
+            const int xs = gw * 32;
+            const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+            const uint32_t nw = s.bn[(row + RU) * kRowWords + 1 + wsel] & valid;
+            const uint32_t ow = s.bits[(row + RU + 1 + r) * kRowWords + 1 + wsel] & valid;
+            A.bits_out[(size_t)y * A.WW + gw] = nw;
+            flips = __popc(nw ^ ow);
+        }
+    }
+
+    Bin *out = &st->slot[(A.n + 1) % 3][block_linear_id() % kBins];
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    int cnt = 0;
+    if constexpr (!EDGE) {
+        // D: statistics of phi^{n+1} = G * b^n for the next iteration.
+        stats_tile<NB, ST>(s, static_cast<const ST *>(A.img), x0, y0, H, W, r, ts, nch, 0, acc, cnt);
+    }
+    reduce_commit<NB>(s, acc, cnt, flips, out, A.fix, !EDGE);
+
+    if (lead_block) {
+        // Clear the slot of iteration n + 2 (nobody reads or writes it now).
+        unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
+        for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+    }
+    if (lead) {
+        st->iters += 1;
+        if constexpr (!EDGE) {
+            for (int b = 0; b < NB; ++b) {
+                st->last_cp[b] = cp[b];
+                st->last_cm[b] = cm[b];
+            }
+            st->last_M = M;
+        }
+    }
+}
+
+// One iteration (Table I steps 2-4, plus the statistics of step 2.1 for the
+// next iteration) on one 96 x 64 tile of one image.  Launch k runs iteration
+// n = n0 + k of every image it covers (one image when map is null; else the
+// workgroup map names image and tile).
+template <int R, int NB, bool EDGE, typename ST>
+__global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__restrict__ args,
+                                                              const uint32_t *__restrict__ map, int unit_bits, int k,
+                                                              int stop) {
+    using G = FastGeom<R, EDGE>;
+    constexpr int TS = G::TS;
+    extern __shared__ float smem[];
+    __shared__ Totals tot;
+    __shared__ float red[kThreads / 64 * 8];
+    int ii, t;
+    if (!batch_unit(map, unit_bits, ii, t)) return;
+    const ImgArgs &E = args[ii];
+    if (!map) t = tile_of(E.tiles);
+    const int n = E.n0 + k;
+    if (t < 0 || n >= E.target) return;
+    StepArgs A;
+    A.img = E.img;
+    A.bits_in = E.bits[n & 1];
+    A.bits_out = E.bits[(n + 1) & 1];
+    A.st = E.st;
+    A.taps = E.taps;
+    A.H = E.H;
+    A.W = E.W;
+    A.WW = E.WW;
+    A.dt = E.dt;
+    A.n = n;
+    A.stop = stop;
+    A.fix = E.fix;
+    A.inv_fix = E.inv_fix;
+    A.hw = E.hw;
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    const bool lead_block = t == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
+    const int H = A.H, W = A.W;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = (W + kFX - 1) / kFX;
+    const int x0 = (t >= 0 ? t % ntx : 0) * kFX, y0 = (t >= 0 ? t / ntx : 0) * kFY;
+    const int by0 = y0 - G::RU - 1 - R;  // image row of staged bit row 0
+    const int px0 = x0 - G::RU - 1, py0 = y0 - G::RU - 1;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
+    float *s_phi = smem + G::BH * kFWords;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PHP * G::PS);
+    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);    // [max(BH, UH)][2]
+    int *s_pcode = s_codes + G::BH * 2;                                  // [PHP][2]: phi row uniformity
+    uint32_t *s_const = reinterpret_cast<uint32_t *>(s_pcode + G::PHP * 2);  // all-ones / all-zeros rows
+
+    // A: b^{n-1} on the tile + 2R+1 halo.  Issued before the statistics
+    // loads so that the two memory round trips overlap.
+    if (t >= 0) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
+    // Tables do not depend on the statistics either: load them before the
+    // statistics barrier (one memory round trip for the whole set-up).
+    int lut[G::NCH];
+    load_luts<G::NCH>(A.taps, lut);
+    float kk[TS];
+#pragma unroll
+    for (int i = 0; i < TS; ++i) kk[i] = A.taps->k[i];
+    const float *cum = A.taps->cum;
+    load_totals(st, sl, !EDGE, &tot);
+    {
+        int done = tot.done | tot.bad;
+        if (!done && A.stop && tot.flips == 0) done = 1;
+        if (done) {
+            if (lead && !tot.bad) st->done = 1;
+            return;
+        }
+    }
+    const bool raw = tot.raw && n == 0;
+
+    float a[NB], m[NB], w = 0.f;
+    float cp[NB], cm[NB], M = 0.f;
+    if constexpr (!EDGE) {
+        slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            a[b] = cp[b] - cm[b];
+            m[b] = cp[b] + cm[b];
+        }
+        if constexpr (NB == 1) {
+            Px<1> lo, hi;
+            lo.v[0] = key_float(tot.imin_key[0]);
+            hi.v[0] = key_float(tot.imax_key[0]);
+            M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
+        } else {
+            M = __uint_as_float((unsigned int)(tot.mkey >> 32));
+        }
+        w = M > 0.f ? A.dt / M : 0.f;
+    }
+    // LSF value of an all-ones / all-zeros window (same arithmetic as any pixel).
+    float phi_one = 0.f, phi_zero = 0.f;
+    {
+        const float h1 = hconv_fast<R, G::NCH>(s_const, 64, 64, 1 << 30, false, lut, cum);
+        const float h0 = hconv_fast<R, G::NCH>(s_const + 8, 64, 64, 1 << 30, false, lut, cum);
+#pragma unroll
+        for (int i = 0; i < TS; ++i) {
+            phi_one = fmaf(kk[i], h1, phi_one);
+            phi_zero = fmaf(kk[i], h0, phi_zero);
+        }
+    }
+    constexpr int NV = EDGE ? 1 : NB;               // values per pixel: edge map or image bands
+    constexpr int PB = NV * (int)sizeof(ST);        // bytes per pixel
+    const __amdgpu_buffer_rsrc_t img_rs = image_rsrc(A.img, (uint32_t)((unsigned long long)H * W * PB));
+    // U-row words of an all-ones binarised row (the two ballots' valid lanes).
+    const unsigned long long ones1 = (32 + 2 * G::RU >= 64) ? ~0ull : ((1ull << (32 + 2 * G::RU)) - 1ull);
+
+    if (t >= 0) {
+        // Codes of the staged rows over each chunk's window span.
+        for (int i = tid; i < G::BH * 2; i += kThreads) {
+            const int row = i >> 1, c = i & 1;
+            s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, 95 - G::RU + R)
+                                : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
+        }
+        __syncthreads();
+
+        // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
+        {
+            const int chunk = wave & 1, seg = wave >> 1;
+            const int p = chunk * 64 + lane;
+            const int x = px0 + p;
+            const int xb = x - x0 + 32;
+            const bool colok = p < G::PW && x >= 0 && x < W;
+            if (raw) {
+                for (int j = 0; j < G::SEG; ++j) {
+                    const int q = seg * G::SEG + j, y = py0 + q;
+                    float v = 0.f;
+                    if (colok && y >= 0 && y < H) {
+                        const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
+                        v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+                    }
+                    if (p < G::PW) s_phi[q * G::PS + p] = v;
+                    if (lane == 0) s_pcode[q * 2 + chunk] = 2;
+                }
+            } else {
+                constexpr int NW = 2 * R + kSB;
+                float win[NW];
+                const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
+                bool have_win = false;
+#pragma unroll 1
+                for (int blk = 0; blk < G::NBLK; ++blk) {
+                    const int rb = brow0 + blk * kSB;
+                    int uni = -1;
+                    if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
+                        uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
+                    if (uni >= 0) {
+                        const float v = uni ? phi_one : phi_zero;
+#pragma unroll
+                        for (int j = 0; j < kSB; ++j) {
+                            const int q = rb + j;
+                            if (p < G::PW) s_phi[q * G::PS + p] = colok ? v : 0.f;
+                        }
+                        if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
+                        have_win = false;
+                        continue;
+                    }
+                    if (!have_win) {
+#pragma unroll
+                        for (int t2 = 0; t2 < 2 * R; ++t2) {
+                            const int y = by0 + rb + t2;
+                            const float v =
+                                hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, border, lut, cum);
+                            win[t2] = (y >= 0 && y < H) ? v : 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int t2 = 0; t2 < kSB; ++t2) {
+                        const int brow = rb + 2 * R + t2;
+                        const int y = by0 + brow;
+                        const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
+                        win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kSB; ++j) {
+                        float ph = 0.f;
+#pragma unroll
+                        for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                        const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
+                        if (p < G::PW) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
+                    }
+                    if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
+#pragma unroll
+                    for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + kSB];
+                    have_win = true;
+                }
+            }
+        }
+        __syncthreads();
+
+        // C: update eq. (18) and binarisation on U = tile + RU halo, in blocks
+        // of 8 rows per wave task; blocks whose phi rows are one uniform
+        // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
+        int flips = 0;
+        constexpr int NBC = (G::UH + kSB - 1) / kSB;
+#pragma unroll 1
+        for (int bi = wave; bi < NBC; bi += kThreads / 64) {
+            const int u0 = bi * kSB;
+            const int nr = min(kSB, G::UH - u0);
+            int rc = -1;
+            if (!border) {
+                const int ncode = (nr + 2) * 2;  // phi rows u0 .. u0 + nr + 1, both chunks
+                const int c = lane < ncode ? s_pcode[u0 * 2 + lane] : -1;
+                const unsigned long long full = (1ull << ncode) - 1ull;
+                if (__ballot(c == 1) == full)
+                    rc = 1;
+                else if (__ballot(c == 0) == full)
+                    rc = 0;
+            }
+            if (rc >= 0) {
+                if (lane < nr * kFWords) {
+                    const int r = lane / kFWords, k = lane - r * kFWords;
+                    const int uy = u0 + r, y = y0 - G::RU + uy;
+                    const uint32_t word = rc ? (bits_extract(~0ull, 32 - G::RU, k) |
+                                                bits_extract(ones1, 96 - G::RU, k))
+                                             : 0u;
+                    s_bn[uy * kFWords + k] = word;
+                    const int gw = (x0 >> 5) - 1 + k;
+                    if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + kFY && y < H && gw < A.WW) {
+                        const int xs = gw * 32;
+                        const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                        const uint32_t nw = word & valid;
+                        const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + k] & valid;
+                        A.bits_out[(size_t)y * A.WW + gw] = nw;
+                        flips += __popc(nw ^ ow);
+                    }
+                }
+                continue;
+            }
+            // Rows in groups of kCG: gradients first (LDS), then every data-term
+            // load of the group, then the updates, so that one memory round
+            // trip serves the whole group.
+#pragma unroll 1
+            for (int r0 = 0; r0 < nr; r0 += kCG) {
+                float phv[kCG][2], gmv[kCG][2];
+                bool need[kCG][2], pred[kCG][2];
+                int pixv[kCG][2];
+#pragma unroll
+                for (int i = 0; i < kCG; ++i) {
+                    const int uy = u0 + r0 + i;
+                    const int y = y0 - G::RU + uy;
+                    const bool rowok = r0 + i < nr && y >= 0 && y < H;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int xb = 32 - G::RU + c * 64 + lane;
+                        const int x = x0 - 32 + xb;
+                        need[i][c] = false;
+                        pred[i][c] = false;
+                        phv[i][c] = 0.f;
+                        gmv[i][c] = 0.f;
+                        pixv[i][c] = 0;
+                        if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
+                            const int p = c * 64 + lane + 1;
+                            const float *cc = s_phi + (uy + 1) * G::PS + p;
+                            float gx, gy;
+                            if (x == 0)
+                                gx = cc[1] - cc[0];
+                            else if (x == W - 1)
+                                gx = cc[0] - cc[-1];
+                            else
+                                gx = 0.5f * (cc[1] - cc[-1]);
+                            if (y == 0)
+                                gy = cc[G::PS] - cc[0];
+                            else if (y == H - 1)
+                                gy = cc[0] - cc[-G::PS];
+                            else
+                                gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
+                            phv[i][c] = cc[0];
+                            pred[i][c] = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                            if (!(gx == 0.f && gy == 0.f)) {
+                                need[i][c] = true;
+                                gmv[i][c] = sqrtf(gx * gx + gy * gy);
+                                pixv[i][c] = y * W + x;
+                            }
+                        }
+                    }
+                }
+                float coef[kCG][2];
+                {
+                    Px<NV> v[kCG][2];
+#pragma unroll
+                    for (int i = 0; i < kCG; ++i)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
+#pragma unroll
+                    for (int i = 0; i < kCG; ++i)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            if constexpr (EDGE)
+                                coef[i][c] = A.dt * v[i][c].v[0];
+                            else
+                                coef[i][c] = w * region_D<NB>(v[i][c], a, m);
+                        }
+                }
+#pragma unroll
+                for (int i = 0; i < kCG; ++i) {
+                    if (r0 + i >= nr) break;
+                    const int uy = u0 + r0 + i;
+                    const int y = y0 - G::RU + uy;
+                    const bool rowok = y >= 0 && y < H;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
+                    const unsigned long long m0 = __ballot(pred[i][0]);
+                    const unsigned long long m1 = __ballot(pred[i][1]);
+                    if (lane < kFWords) {
+                        const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
+                        s_bn[uy * kFWords + lane] = word;
+                        const int gw = (x0 >> 5) - 1 + lane;
+                        if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                            const int xs = gw * 32;
+                            const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                            const uint32_t nw = word & valid;
+                            const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                            A.bits_out[(size_t)y * A.WW + gw] = nw;
+                            flips += __popc(nw ^ ow);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        float acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+        int cnt = 0;
+        if constexpr (!EDGE) {
+            // D: statistics of phi^{n+1} = G * b^n for the next iteration.
+            code_rows_owned<R>(s_bn, G::UH, s_codes);
+            __syncthreads();
+            stats_fast<R, NB, ST>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, H, W, border, false,
+                                  lut, kk, cum, acc, cnt);
+        }
+        TileSmem rs;
+        rs.red = red;
+        reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][blockIdx.x % kBins], A.fix, !EDGE);
+    }
+    if (lead_block) {
+        // Clear the slot of iteration n + 2 (nobody reads or writes it now).
+        unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
+        for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+    }
+    if (lead) {
+        st->iters += 1;
+        if constexpr (!EDGE) {
+            for (int b = 0; b < NB; ++b) {
+                st->last_cp[b] = cp[b];
+                st->last_cm[b] = cm[b];
+            }
+            st->last_M = M;
+        }
+    }
+}
+
+// Region statistics on the fast tiling (used at init and by set_mask so that
+// its partial sums equal the step kernel's bit for bit).
+template <int R, int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int raw, int slot) {
+    extern __shared__ float smem[];
+    __shared__ float red[kThreads / 64 * 8];
+    using G = FastGeom<R, false>;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
+    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * kFY;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > A.W;
+    int lut[G::NCH];
+    load_luts<G::NCH>(A.taps, lut);
+    float kk[2 * R + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * R + 1; ++i) kk[i] = A.taps->k[i];
+    int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);
+    stage_bits_fast(s_bn, A.bits_in, y0 - R, G::UH, x0, A.H, A.WW);
+    __syncthreads();
+    code_rows_owned<R>(s_bn, G::UH, s_codes);
+    __syncthreads();
+    float acc[NB];
+    int cnt;
+    stats_fast<R, NB, ST>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, A.H, A.W, border, raw != 0,
+                          lut, kk, A.taps->cum, acc, cnt);
+    TileSmem rs;
+    rs.red = red;
+    reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int R, int NB, bool EDGE, typename ST>
+static hipError_t launch_step_fast_t(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k,
+                                     int stop, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
+    const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE, ST>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((step_fast_kernel<R, NB, EDGE, ST>), dim3(grid), dim3(kThreads), sm, s, args, map, unit_bits,
+                       k, stop);
+    return hipGetLastError();
+}
+
+template <int R, typename ST>
+static hipError_t launch_step_fast_r(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k,
+                                     int stop, int NB, int edge, hipStream_t s) {
+    if (edge) return launch_step_fast_t<R, 1, true, ST>(args, map, unit_bits, grid, k, stop, s);
+    switch (NB) {
+        case 1: return launch_step_fast_t<R, 1, false, ST>(args, map, unit_bits, grid, k, stop, s);
+        case 2: return launch_step_fast_t<R, 2, false, ST>(args, map, unit_bits, grid, k, stop, s);
+        case 4: return launch_step_fast_t<R, 4, false, ST>(args, map, unit_bits, grid, k, stop, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int R, int NB, typename ST>
+static hipError_t launch_stats_fast_t(const StepArgs &a, int raw, int slot, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, false>::UH * (kFWords + 2) * 4;
+    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFY - 1) / kFY);
+    hipLaunchKernelGGL((stats_fast_kernel<R, NB, ST>), grid, dim3(kThreads), sm, s, a, raw, slot);
+    return hipGetLastError();
+}
+
+template <int R, typename ST>
+static hipError_t launch_stats_fast_r(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+    switch (NB) {
+        case 1: return launch_stats_fast_t<R, 1, ST>(a, raw, slot, s);
+        case 2: return launch_stats_fast_t<R, 2, ST>(a, raw, slot, s);
+        case 4: return launch_stats_fast_t<R, 4, ST>(a, raw, slot, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int NB, typename ST>
+static hipError_t launch_stats_generic_t(const StepArgs &a, int raw, int slot, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, 0);
+    const hipError_t e = ensure_lds(stats_kernel<NB, ST>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((stats_kernel<NB, ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a, raw, slot);
+    return hipGetLastError();
+}
+
+template <int NB, bool EDGE, typename ST>
+static hipError_t launch_step_generic_t(const StepArgs &a, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, EDGE ? 1 : 0);
+    const hipError_t e = ensure_lds(step_kernel<NB, EDGE, ST>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((step_kernel<NB, EDGE, ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a);
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
+                                 DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s) {
+    const dim3 grid(stream_blocks(npx, 4)), block(kThreads);
+    ST *d = static_cast<ST *>(dst);
+    switch (src_dtype) {
+        case LSE_F32:
+            hipLaunchKernelGGL((init_image_kernel<float, ST>), grid, block, 0, s, static_cast<const float *>(src), B,
+                               NB, d, npx, st, fix, want_gray, gray_scale);
+            break;
+        case LSE_F16:
+            hipLaunchKernelGGL((init_image_kernel<__half, ST>), grid, block, 0, s, static_cast<const __half *>(src),
+                               B, NB, d, npx, st, fix, want_gray, gray_scale);
+            break;
+        case LSE_BF16:
+            hipLaunchKernelGGL((init_image_kernel<__hip_bfloat16, ST>), grid, block, 0, s,
+                               static_cast<const __hip_bfloat16 *>(src), B, NB, d, npx, st, fix, want_gray,
+                               gray_scale);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::edge_g(const float *Is, void *g, int H, int W, hipStream_t s) {
+    const long long n = (long long)H * W;
+    hipLaunchKernelGGL((edge_g_kernel<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Is,
+                       static_cast<ST *>(g), H, W);
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s) {
+    const unsigned nblk = (unsigned)(((W + kMBX - 1) / kMBX) * ((H + kMBY - 1) / kMBY));
+    const ST *p = static_cast<const ST *>(img);
+    switch (NB) {
+        case 2: hipLaunchKernelGGL((mbox_kernel<2, ST>), dim3(nblk), dim3(kThreads), 0, s, p, H, W, boxes); break;
+        case 4: hipLaunchKernelGGL((mbox_kernel<4, ST>), dim3(nblk), dim3(kThreads), 0, s, p, H, W, boxes); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// The statistics kernel uses the same tiling as the step kernel that would
+// have produced the statistics, so that resumed runs match bit for bit.
+template <typename ST>
+hipError_t Store<ST>::stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s) {
+    switch (a.r) {
+        case 3: return launch_stats_fast_r<3, ST>(a, NB, raw, slot, s);
+        case 4: return launch_stats_fast_r<4, ST>(a, NB, raw, slot, s);
+        case 5: return launch_stats_fast_r<5, ST>(a, NB, raw, slot, s);
+        case 6: return launch_stats_fast_r<6, ST>(a, NB, raw, slot, s);
+        case 7: return launch_stats_fast_r<7, ST>(a, NB, raw, slot, s);
+        default: break;
+    }
+    switch (NB) {
+        case 1: return launch_stats_generic_t<1, ST>(a, raw, slot, s);
+        case 2: return launch_stats_generic_t<2, ST>(a, raw, slot, s);
+        case 4: return launch_stats_generic_t<4, ST>(a, raw, slot, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+hipError_t Store<ST>::step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
+                           int r, int NB, int edge, hipStream_t s) {
+    switch (r) {
+        case 3: return launch_step_fast_r<3, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+        case 4: return launch_step_fast_r<4, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+        case 5: return launch_step_fast_r<5, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+        case 6: return launch_step_fast_r<6, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+        case 7: return launch_step_fast_r<7, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+hipError_t Store<ST>::step_generic(const StepArgs &a, int NB, int edge, hipStream_t s) {
+    if (edge) return launch_step_generic_t<1, true, ST>(a, s);
+    switch (NB) {
+        case 1: return launch_step_generic_t<1, false, ST>(a, s);
+        case 2: return launch_step_generic_t<2, false, ST>(a, s);
+        case 4: return launch_step_generic_t<4, false, ST>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+hipError_t Store<ST>::mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
+                            int NB, hipStream_t s) {
+    switch (NB) {
+        case 2:
+            hipLaunchKernelGGL((mpass_kernel<2, ST>), dim3(grid), dim3(kThreads), 0, s, args, map, unit_bits, k, stop);
+            break;
+        case 4:
+            hipLaunchKernelGGL((mpass_kernel<4, ST>), dim3(grid), dim3(kThreads), 0, s, args, map, unit_bits, k, stop);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lse

@@ -32,7 +32,8 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTS = (
     "lse_params_default", "lse_workspace_bytes", "lse_init", "lse_step", "lse_run", "lse_mask",
     "lse_lsf", "lse_set_mask", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
-    "lse_step_bytes_per_pixel", "lse_destroy", "lse_status_str", "lse_version",
+    "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_run",
+    "lse_batch_destroy", "lse_status_str", "lse_version",
 )
 
 
@@ -65,6 +66,7 @@ class lse_profile_t(ctypes.Structure):
 
 PROFILE_TIMING = 1
 PROFILE_COUNT = 2
+BATCH_GRAPH = 1
 
 
 class LSEError(RuntimeError):
@@ -114,6 +116,14 @@ def load() -> ctypes.CDLL:
     lib.lse_step_bytes_per_pixel.restype = ctypes.c_double
     lib.lse_destroy.argtypes = [vp]
     lib.lse_destroy.restype = None
+    lib.lse_batch_bytes.argtypes = [P(vp), i32]
+    lib.lse_batch_bytes.restype = ctypes.c_size_t
+    lib.lse_batch_create.argtypes = [P(vp), i32, P(i32), vp, ctypes.c_size_t, vp, P(vp)]
+    lib.lse_batch_create.restype = st
+    lib.lse_batch_run.argtypes = [vp, i32, i32, i32, vp]
+    lib.lse_batch_run.restype = st
+    lib.lse_batch_destroy.argtypes = [vp]
+    lib.lse_batch_destroy.restype = None
     lib.lse_status_str.argtypes = [st]
     lib.lse_status_str.restype = ctypes.c_char_p
     lib.lse_version.argtypes = []
@@ -204,6 +214,36 @@ def lse_version() -> int:
     return int(load().lse_version())
 
 
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))()
+    for i, c in enumerate(ctxs):
+        arr[i] = c.value if isinstance(c, ctypes.c_void_p) else c
+    return arr
+
+
+def lse_batch_bytes(ctxs) -> int:
+    return int(load().lse_batch_bytes(_ctx_array(ctxs), len(ctxs)))
+
+
+def lse_batch_create(ctxs, targets, table_ptr: int, table_bytes: int, stream: int = 0) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    tg = None
+    if targets is not None:
+        tg = (ctypes.c_int32 * len(ctxs))(*[int(t) for t in targets])
+    _check(load().lse_batch_create(_ctx_array(ctxs), len(ctxs), tg, table_ptr, table_bytes, stream,
+                                   ctypes.byref(b)), "lse_batch_create")
+    return b
+
+
+def lse_batch_run(batch, iters: int, stop_when_unchanged: bool = False, flags: int = 0, stream: int = 0) -> None:
+    _check(load().lse_batch_run(batch, int(iters), int(bool(stop_when_unchanged)), int(flags), stream),
+           "lse_batch_run")
+
+
+def lse_batch_destroy(batch) -> None:
+    load().lse_batch_destroy(batch)
+
+
 # ------------------------------------------------------------ torch wrapper
 
 def _torch():
@@ -281,6 +321,14 @@ class LSE:
     def _s(self) -> int:
         return int(self.stream.cuda_stream)
 
+    def _handoff(self, out):
+        # `out` is written on this job's stream; order the caller's current
+        # stream after it so that torch work there sees the result.
+        cur = _torch().cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+        return out
+
     def step(self) -> None:
         lse_step(self.ctx, self._s())
 
@@ -292,14 +340,14 @@ class LSE:
         h, w, _ = self.shape
         out = out if out is not None else torch.empty((h, w), dtype=torch.uint8, device=self.device)
         lse_mask(self.ctx, out.data_ptr(), self._s())
-        return out
+        return self._handoff(out)
 
     def lsf(self, out=None):
         torch = _torch()
         h, w, _ = self.shape
         out = out if out is not None else torch.empty((h, w), dtype=torch.float32, device=self.device)
         lse_lsf(self.ctx, out.data_ptr(), self._s())
-        return out
+        return self._handoff(out)
 
     def set_mask(self, mask, smoothed: bool) -> None:
         mask = mask.to(_torch().uint8).contiguous()
@@ -332,6 +380,43 @@ class LSE:
         if getattr(self, "ctx", None):
             lse_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several LSE jobs advanced together (lse_batch_*).  The table memory is a
+    torch uint8 tensor owned by this object; the jobs must outlive it."""
+
+    def __init__(self, jobs, targets=None, stream=None):
+        torch = _torch()
+        if not jobs:
+            raise ValueError("empty batch")
+        self.jobs = list(jobs)
+        self.device = self.jobs[0].device
+        self.stream = stream if stream is not None else self.jobs[0].stream
+        ctxs = [j.ctx for j in self.jobs]
+        nbytes = lse_batch_bytes(ctxs)
+        if nbytes == 0:
+            self.batch = lse_batch_create(ctxs, targets, 0, 0, self._s())  # raises with the reason
+        self.table = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.table.data_ptr()
+        self.batch = lse_batch_create(ctxs, targets, base + (-base) % 256, nbytes, self._s())
+
+    def _s(self) -> int:
+        return int(self.stream.cuda_stream)
+
+    def run(self, iters: int, stop_when_unchanged: bool = False, graph: bool = False) -> None:
+        lse_batch_run(self.batch, iters, stop_when_unchanged, BATCH_GRAPH if graph else 0, self._s())
+
+    def close(self) -> None:
+        if getattr(self, "batch", None):
+            lse_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

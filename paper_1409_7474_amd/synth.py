@@ -139,8 +139,9 @@ def _strip(img, truth, seeds, rng, cy, cx, theta, width, length, means, seed_eve
     sub = img[y_lo:y_hi, x_lo:x_hi, :]
     sub[inside] = means
     truth[y_lo:y_hi, x_lo:x_hi][inside] = 1
-    # seeds every `seed_every` px along the centre line, inside the image
-    half_len = (length / 2.0) if length is not None else float(h + w)
+    # seeds (5 x 5) every `seed_every` px along the centre line, inside the
+    # image and, for a finite strip, at least 5 px inside its ends
+    half_len = (length / 2.0 - 5.0) if length is not None else float(h + w)
     t = -half_len
     while t <= half_len:
         py, px = int(round(cy + t * dy)), int(round(cx + t * dx))
@@ -162,15 +163,18 @@ def scene_multiband(seed: int = 0, size: int = 4096, bands: int = 4, n_roofs: in
 
     Initial curves: region term -- centred square of half the side; edge term --
     5 x 5 seeds at roof centres and every 128 px along road/runway centre lines.
-    The side is scaled down with `size` for test-sized scenes."""
+    Sizes are those of a 4096 px side (roads, roofs) and of an 8192 px side
+    (runway), scaled down for smaller scenes, never up."""
     rng = _rng(workload, image_id, seed)
     h = height or size
     w = width or size
+    runway_geom = None
     img = np.empty((h, w, bands))
     img[:] = rng.uniform(0.2, 0.4, size=bands)
     truth = np.zeros((h, w), np.uint8)
     seeds = np.zeros((h, w), np.uint8)
-    scale = min(h, w) / 4096.0
+    scale = min(1.0, min(h, w) / 4096.0)   # roads and roofs: sizes given at a 4096 px side
+    rscale = min(1.0, min(h, w) / 8192.0)  # runway: sizes given at an 8192 px side
     for _ in range(n_roads):
         width_px = rng.uniform(8, 20)
         theta = rng.uniform(0, math.pi)
@@ -178,8 +182,8 @@ def scene_multiband(seed: int = 0, size: int = 4096, bands: int = 4, n_roofs: in
         means = rng.uniform(0.45, 0.6, size=bands)
         _strip(img, truth, seeds, rng, cy, cx, theta, width_px, None, means)
     if runway:
-        width_px = rng.uniform(60, 120) * max(scale, 1.0 / 64)
-        length = rng.uniform(2000, 4000) * max(scale, 1.0 / 64)
+        width_px = rng.uniform(60, 120) * max(rscale, 1.0 / 64)
+        length = rng.uniform(2000, 4000) * max(rscale, 1.0 / 64)
         theta = rng.uniform(0, math.pi)
         ext_y = abs(math.sin(theta)) * length / 2 + width_px
         ext_x = abs(math.cos(theta)) * length / 2 + width_px
@@ -187,6 +191,7 @@ def scene_multiband(seed: int = 0, size: int = 4096, bands: int = 4, n_roofs: in
         cx = rng.uniform(min(ext_x, w / 2), max(w - ext_x, w / 2))
         means = rng.uniform(0.45, 0.6, size=bands)
         _strip(img, truth, seeds, rng, cy, cx, theta, width_px, length, means)
+        runway_geom = (cy, cx, theta, width_px, length)
     side_hi = max(12, int(round(120 * max(scale, 0.125))))
     side_lo = min(10, side_hi)
     rects = _paint_rects(img, truth, rng, n_roofs, side_lo, side_hi,
@@ -195,7 +200,16 @@ def scene_multiband(seed: int = 0, size: int = 4096, bands: int = 4, n_roofs: in
     img += rng.normal(0.0, noise, size=img.shape)
     np.clip(img, 0.0, 1.0, out=img)
     init = centred_square(h, w, h // 2, w // 2)
-    return Scene(img, init, seeds, truth, {"rects": rects, "seed": seed})
+    return Scene(img, init, seeds, truth, {"rects": rects, "seed": seed, "runway": runway_geom})
+
+
+def crop_scene(sc: Scene, y0: int, x0: int, h: int, w: int) -> Scene:
+    """An H x W window of a scene, with its own initial curve (centred square
+    of half the window side) and the window's edge seeds and truth."""
+    img = np.ascontiguousarray(sc.image[y0:y0 + h, x0:x0 + w])
+    truth = np.ascontiguousarray(sc.truth[y0:y0 + h, x0:x0 + w])
+    seeds = np.ascontiguousarray(sc.init_edge[y0:y0 + h, x0:x0 + w])
+    return Scene(img, centred_square(h, w, h // 2, w // 2), seeds, truth, {"crop": (y0, x0, h, w)})
 
 
 def scene_large(seed: int = 0, size: int = 4096) -> Scene:

@@ -71,8 +71,27 @@ def test_huge_image_rejected():
     assert lse.lse_workspace_bytes(p) == 0
 
 
+def test_storage_type_sizes_workspace():
+    # The resident image (region) or edge map (edge) takes 2 bytes per value
+    # with 16-bit storage; everything else is the same.
+    for term, nb in (("region", 4), ("edge", 1)):
+        sizes = {st: lse.lse_workspace_bytes(lse.make_params(512, 512, 4, term=term, storage=st))
+                 for st in ("f32", "f16", "bf16")}
+        assert sizes["f16"] == sizes["bf16"]
+        assert sizes["f32"] - sizes["f16"] == 512 * 512 * nb * 2
+
+
+def test_16bit_storage_allows_larger_images():
+    # 32-bit byte offsets bound the resident copy: 2^28 pixels x 4 bands x 4 B
+    # is out of range in FP32 but fits at 2 bytes per value.
+    p32 = lse.make_params(16384, 16384, 4, storage="f32")
+    p16 = lse.make_params(16384, 16384, 4, storage="f16")
+    assert lse.lse_workspace_bytes(p32) == 0
+    assert lse.lse_workspace_bytes(p16) > 0
+
+
 def test_unsupported_modes_reported():
-    for kw in ({"order": "listing"}, {"storage": "f16"}, {"reinit_every": 0}):
+    for kw in ({"order": "listing"}, {"reinit_every": 0}):
         p = lse.make_params(64, 64, 1, **kw)
         ctx = ctypes.c_void_p()
         st = lse.load().lse_init(ctypes.byref(p), 16, 16, 256, 1 << 30, None, ctypes.byref(ctx))
@@ -105,3 +124,17 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lse_profile(None, 8) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_step_bytes_per_pixel(None) == 0.0
     lib.lse_destroy(None)
+
+
+def test_batch_argument_checks():
+    lib = lse.load()
+    assert lib.lse_batch_bytes(None, 0) == 0
+    assert lib.lse_batch_bytes(None, 3) == 0
+    out = ctypes.c_void_p()
+    assert lib.lse_batch_create(None, 1, None, 256, 1 << 20, None, ctypes.byref(out)) == lse.LSE_ERR_INVALID_ARG
+    assert not out.value
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.lse_batch_create(arr, 2, None, 256, 1 << 20, None, ctypes.byref(out)) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_batch_create(arr, 0, None, 256, 1 << 20, None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_batch_run(None, 3, 0, 0, None) == lse.LSE_ERR_INVALID_ARG
+    lib.lse_batch_destroy(None)

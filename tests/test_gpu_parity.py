@@ -12,7 +12,6 @@ or float16 values, promoted to float64).
 """
 import numpy as np
 import pytest
-import scipy.ndimage as ndi
 
 import oracle
 from paper_1409_7474_amd import synth
@@ -21,74 +20,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-LSF_TOL = 1e-5
-MASK_TOL = 1e-4
-
-
-@pytest.fixture(scope="module")
-def dev():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1409_7474_amd import lse
-    lse.load()
-    return torch.device("cuda:0")
-
-
-def _as_gpu(img, dev, dtype=torch.float32):
-    t = torch.tensor(img, dtype=dtype, device=dev)
-    return t, t.float().cpu().double().numpy()
-
-
-def _make(dev, img, mask, **kw):
-    from paper_1409_7474_amd import lse
-    return lse.LSE(img, torch.tensor(mask, dtype=torch.uint8, device=dev), **kw)
-
-
-def one_step(job, img64, *, term="region", dt=15.0, sigma=1.0, ts=7, g=None):
-    """Advance the GPU one iteration and compare with the oracle from the
-    GPU's own LSF.  The binary result must match the oracle's everywhere
-    except at ambiguous pixels (|u| < 1e-5 max(1, dt)); the LSF must match
-    within 1e-5 outside their Gaussian footprint.  Returns (max LSF error,
-    ambiguous count, oracle result)."""
-    phi = job.lsf().cpu().double().numpy()
-    ref = oracle.step(phi, img64 if term == "region" else None, term=term, dt=dt, sigma=sigma, ts=ts, g=g)
-    job.step()
-    got = job.lsf().cpu().double().numpy()
-    amb = np.abs(ref.u) < 1e-5 * max(1.0, dt)
-    bits = job.mask().cpu().numpy().astype(bool)
-    wrong = (bits != (ref.b > 0)) & ~amb
-    assert not wrong.any(), f"{int(wrong.sum())} binary decisions differ outside the ambiguity band"
-    assert amb.sum() <= max(4, 1e-4 * amb.size), int(amb.sum())
-    excl = ndi.binary_dilation(amb, structure=np.ones((ts, ts), bool)) if amb.any() else amb
-    err = float(np.abs(got - ref.phi)[~excl].max()) if (~excl).any() else 0.0
-    return err, int(amb.sum()), ref
-
-
-def check_normaliser(st, img64, ref_M):
-    """The normaliser of eq. (17) must be the maximum of |D| over every pixel.
-    Recompute that maximum in FP64 from the GPU's own FP32 means; the GPU's
-    value (a pruned block scan for B > 1) may differ only by the FP32
-    rounding of D, bounded by 12 u * sum_b |a_b| (2 max|I_b| + |m_b|).  The
-    oracle's M (FP64 means) must agree within the effect of rounding the means
-    themselves to FP32 on that same scale."""
-    nb = img64.shape[2]
-    cp = np.array(st["c_plus"][:nb], np.float32)
-    cm = np.array(st["c_minus"][:nb], np.float32)
-    a32 = (cp - cm).astype(np.float64)
-    m32 = (cp + cm).astype(np.float64)
-    D = np.zeros(img64.shape[:2])
-    for b in range(nb):
-        D += a32[b] * (2.0 * img64[:, :, b] - m32[b])
-    M64 = float(np.abs(D).max())
-    amax = np.abs(img64).reshape(-1, nb).max(0)
-    scale = float(np.sum(np.abs(a32) * (2.0 * amax + np.abs(m32))))
-    assert abs(st["M"] - M64) <= 12 * 2.0 ** -24 * scale + 1e-30, (st["M"], M64, scale)
-    cscale = float(np.sum((np.abs(cp) + np.abs(cm)) * (2.0 * amax + np.abs(m32))))
-    assert abs(st["M"] - ref_M) <= 12 * 2.0 ** -24 * (scale + cscale), (st["M"], ref_M)
-
-
-def mask_disagreement(a, b):
-    return float(np.mean(a.astype(bool) != b.astype(bool)))
+from parity_helpers import LSF_TOL, MASK_TOL, _as_gpu, _make, check_normaliser, mask_disagreement, one_step  # noqa: E402,F401
 
 
 # ------------------------------------------------------------ one step ---

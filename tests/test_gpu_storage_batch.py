@@ -1,0 +1,255 @@
+"""GPU tests of 16-bit storage and of batched execution, through the C ABI.
+
+Storage: the library rounds the image (region term) or the edge map (edge
+term) once, at init, to FP16 or BF16 and computes in FP32.  One-step parity
+is checked against the FP64 oracle fed the same rounded values, with the
+bars of the FP32 path; the error of each storage type against the FP64
+oracle on the unrounded image is measured over whole runs.
+
+Batching: contexts advanced together by lse_batch_run (one launch per
+iteration and kernel family, optionally replayed from a HIP graph) must give
+bit for bit the results of each context run alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_7474_amd import synth
+from parity_helpers import (LSF_TOL, _make, check_normaliser, iou, mask_disagreement, one_step,
+                            round_storage)
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DT16 = {"f16": torch.float16, "bf16": torch.bfloat16}
+# Relative rounding step (one ulp at 1) of the storage types.
+ULP1 = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}
+
+
+def _img(dev, image, dtype=torch.float32):
+    return torch.tensor(np.asarray(image, np.float32), device=dev).to(dtype)
+
+
+# ------------------------------------------------------------- storage ---
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("bands,h,w,ts,sigma", [(4, 200, 333, 11, 1.5), (1, 150, 97, 7, 1.0),
+                                                (2, 97, 130, 13, 2.0)])
+def test_region_storage_one_step_parity(dev, storage, bands, h, w, ts, sigma):
+    """Region term with the image stored in 16 bits: the oracle, given the
+    rounded image, agrees to the FP32 bars (the rounding is the only
+    difference, and it is applied identically on both sides)."""
+    sc = synth.scene_multiband(11, size=max(h, w), bands=bands, n_roofs=10, n_roads=2, height=h, width=w)
+    img64 = round_storage(sc.image, storage)
+    job = _make(dev, _img(dev, sc.image), sc.init_region, sigma=sigma, ksize=ts, storage=storage)
+    for it in range(6):
+        err, _, ref = one_step(job, img64, sigma=sigma, ts=ts)
+        assert err <= LSF_TOL, (storage, it, err)
+        st = job.stats()
+        np.testing.assert_allclose(st["c_plus"], ref.c_plus, rtol=2e-6, atol=1e-7)
+        np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6, atol=1e-7)
+        check_normaliser(st, img64, ref.M)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_input_with_matching_storage_is_exact(dev, storage):
+    """A 16-bit caller image stored in the same type is copied exactly: the
+    run equals the run on the same values given as FP32."""
+    sc = synth.scene_multiband(3, size=160, bands=4, n_roofs=6, n_roads=1)
+    t16 = _img(dev, sc.image, DT16[storage])
+    a = _make(dev, t16, sc.init_region, sigma=1.5, ksize=11, storage=storage)
+    b = _make(dev, t16.float(), sc.init_region, sigma=1.5, ksize=11, storage=storage)
+    a.run(25)
+    b.run(25)
+    assert torch.equal(a.lsf(), b.lsf())
+    assert a.stats() == b.stats()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_edge_storage_one_step_parity(dev, storage):
+    """Edge term with g stored in 16 bits.  The oracle takes its own FP64 g
+    rounded to the storage type; the GPU rounds its FP32 g, so the two stored
+    maps may differ by one storage ulp where FP32 and FP64 straddle a rounding
+    boundary.  Decisions may then differ only where |u| is below
+    dt * max|grad phi| * ulp(1) (max|grad phi| <= 2 sqrt 2 for phi in
+    [-1, 1], one-sided differences at the border)."""
+    sc = synth.scene_multiband(5, size=192, bands=3, n_roofs=8, n_roads=1)
+    x = np.asarray(sc.image, np.float32).astype(np.float64)
+    g = round_storage(oracle.edge_map(x, 1.0, 9, 255.0), storage)
+    job = _make(dev, _img(dev, sc.image), sc.init_edge, term="edge", sigma=1.5, ksize=11, storage=storage)
+    tau = 15.0 * 2.0 * np.sqrt(2.0) * ULP1[storage]
+    for it in range(6):
+        err, amb, _ = one_step(job, None, term="edge", sigma=1.5, ts=11, g=g, tau=tau)
+        assert err <= LSF_TOL, (storage, it, err, amb)
+
+
+def test_storage_precision_against_fp64(dev):
+    """Whole runs (512 x 512 x 4, sigma 1.5 / TS 11, 150 iterations): each
+    storage type against the FP64 oracle on the unrounded image -- final mask
+    sign disagreement <= 1e-4 and IoU -- and the LSF max-abs error, printed
+    per storage type."""
+    sc = synth.scene_multiband(21, size=512, bands=4, n_roofs=10, n_roads=2)
+    x = np.asarray(sc.image, np.float32).astype(np.float64)
+    ref = oracle.run(x, sc.init_region, term="region", iters=150, sigma=1.5, ts=11)
+    ref_mask = ref.b > 0
+    report = {}
+    for storage in ("f32", "f16", "bf16"):
+        job = _make(dev, _img(dev, sc.image), sc.init_region, sigma=1.5, ksize=11, storage=storage)
+        job.run(150)
+        mask = job.mask().cpu().numpy().astype(bool)
+        lsf = job.lsf().cpu().double().numpy()
+        d = mask_disagreement(mask, ref_mask)
+        report[storage] = (float(np.abs(lsf - ref.phi).max()), d, iou(mask, ref_mask))
+        assert d <= 1e-4, (storage, report[storage])
+    print("storage precision vs FP64 oracle (LSF max-abs, mask disagreement, IoU):", report)
+
+
+# ------------------------------------------------------------- batches ---
+
+def _jobs_spec():
+    """Uneven images of every kernel family the batch groups by."""
+    return [
+        dict(h=300, w=211, bands=4, term="region", storage="f32", ts=7, sigma=1.0, seed=1),
+        dict(h=97, w=450, bands=4, term="region", storage="f32", ts=7, sigma=1.0, seed=2),
+        dict(h=256, w=256, bands=1, term="region", storage="f32", ts=7, sigma=1.0, seed=3),
+        dict(h=180, w=140, bands=3, term="region", storage="f16", ts=11, sigma=1.5, seed=4),
+        dict(h=210, w=333, bands=2, term="edge", storage="f32", ts=11, sigma=1.5, seed=5),
+        dict(h=64, w=64, bands=4, term="region", storage="f32", ts=7, sigma=1.0, seed=6),
+        dict(h=130, w=150, bands=1, term="edge", storage="bf16", ts=7, sigma=1.0, seed=7),
+    ]
+
+
+def _build(dev, spec):
+    jobs, inputs = [], []
+    for s in spec:
+        sc = synth.scene_multiband(s["seed"], size=max(s["h"], s["w"]), bands=s["bands"], n_roofs=8, n_roads=1,
+                                   height=s["h"], width=s["w"])
+        init = sc.init_region if s["term"] == "region" else sc.init_edge
+        jobs.append(_make(dev, _img(dev, sc.image), init, term=s["term"], storage=s["storage"], sigma=s["sigma"],
+                          ksize=s["ts"]))
+        inputs.append(sc)
+    return jobs
+
+
+def _state(job):
+    return job.mask().cpu().numpy(), job.lsf().cpu().numpy(), job.stats()
+
+
+def _assert_same(a, b, what):
+    assert np.array_equal(a[0], b[0]), f"{what}: masks differ"
+    assert np.array_equal(a[1], b[1]), f"{what}: LSFs differ"
+    assert a[2] == b[2], f"{what}: statistics differ"
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_alone(dev, graph):
+    """Seven uneven images (both terms, B = 1..4, three storage types, two
+    template sizes), per-image iteration targets: the batch reproduces every
+    image's solo run bit for bit, also when its launches replay from a graph
+    (two graph launches with host reads in between)."""
+    from paper_1409_7474_amd import lse
+    spec = _jobs_spec()
+    targets = [23, 17, 30, 23, 11, 30, 5]
+    alone = _build(dev, spec)
+    for j, t in zip(alone, targets):
+        j.run(t)
+    want = [_state(j) for j in alone]
+
+    stream = torch.cuda.Stream(dev)  # graphs need a non-default stream
+    with torch.cuda.stream(stream):
+        jobs = _build(dev, spec)
+        for j in jobs:
+            j.stream = stream
+        batch = lse.Batch(jobs, targets=targets, stream=stream)
+        batch.run(15, graph=graph)
+        mid = jobs[0].stats()
+        assert mid["iters_done"] == 15
+        batch.run(15, graph=graph)
+        stream.synchronize()
+    for i, (j, t) in enumerate(zip(jobs, targets)):
+        got = _state(j)
+        assert got[2]["iters_done"] == t, (i, got[2]["iters_done"], t)
+        _assert_same(got, want[i], f"image {i}")
+    batch.close()
+
+
+def test_batch_interleaves_with_single_steps(dev):
+    """Batch runs, solo steps of one member and lse_set_mask between them keep
+    every image identical to its solo history."""
+    from paper_1409_7474_amd import lse
+    spec = _jobs_spec()[:4]
+    alone = _build(dev, spec)
+    jobs = _build(dev, spec)
+    batch = lse.Batch(jobs)
+    batch.run(4)
+    jobs[1].step()
+    batch.run(3)
+    for i, j in enumerate(alone):
+        j.run(4)
+        if i == 1:
+            j.step()
+        j.run(3)
+    for i in range(len(jobs)):
+        _assert_same(_state(jobs[i]), _state(alone[i]), f"image {i}")
+    # restart one member from its initial mask: the batch follows
+    sc = synth.scene_multiband(spec[2]["seed"], size=256, bands=1, n_roofs=8, n_roads=1, height=256, width=256)
+    m = torch.tensor(sc.init_region, device=dev)
+    jobs[2].set_mask(m, smoothed=False)
+    alone[2].set_mask(m, smoothed=False)
+    batch.run(6)
+    for i, j in enumerate(alone):
+        j.run(6)
+    for i in range(len(jobs)):
+        _assert_same(_state(jobs[i]), _state(alone[i]), f"image {i} after set_mask")
+    batch.close()
+
+
+def test_batch_stop_when_unchanged(dev):
+    """Step 5 inside a batch: the noise-free rectangle reaches its exact mask
+    and stops; a noisy partner keeps iterating; both equal their solo runs."""
+    from paper_1409_7474_amd import lse
+    img, truth = synth.rectangle_scene()
+    init = synth.centred_square(256, 256, 128, 128)
+    sc = synth.scene_tiny(2)
+    alone = [_make(dev, _img(dev, img), init), _make(dev, _img(dev, sc.image), sc.init_region)]
+    for j in alone:
+        j.run(80, stop_when_unchanged=True)
+    jobs = [_make(dev, _img(dev, img), init), _make(dev, _img(dev, sc.image), sc.init_region)]
+    batch = lse.Batch(jobs)
+    batch.run(80, stop_when_unchanged=True)
+    for i in range(2):
+        _assert_same(_state(jobs[i]), _state(alone[i]), f"image {i}")
+    assert jobs[0].stats()["converged"]
+    assert np.array_equal(jobs[0].mask().cpu().numpy(), truth)
+    batch.close()
+
+
+def test_batch_many_small_images_parity(dev):
+    """A batch of 24 small uneven tiny-workload images (region, B = 4, 7 x 7):
+    after 10 iterations each image matches the FP64 oracle one step further
+    (one-step parity from the batch's own state)."""
+    from paper_1409_7474_amd import lse
+    shapes = synth.batch_shapes(3, n=24, lo=40, hi=200)
+    scenes = [synth.scene_batch_image(3, i, h, w) for i, (h, w) in enumerate(shapes)]
+    jobs = [_make(dev, _img(dev, s.image), s.init_region, sigma=1.0, ksize=7) for s in scenes]
+    batch = lse.Batch(jobs)
+    batch.run(10)
+    for s, j in zip(scenes, jobs):
+        x = np.asarray(s.image, np.float32).astype(np.float64)
+        err, _, _ = one_step(j, x, sigma=1.0, ts=7)
+        assert err <= LSF_TOL
+    batch.close()
+
+
+def test_batch_rejects_repeated_context(dev):
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_tiny(0, size=64, n_rects=1)
+    j = _make(dev, _img(dev, sc.image), sc.init_region)
+    with pytest.raises(lse.LSEError) as e:
+        lse.Batch([j, j])
+    assert e.value.status == lse.LSE_ERR_INVALID_ARG
+    big = _make(dev, _img(dev, sc.image), sc.init_region, sigma=5.0, ksize=31)
+    with pytest.raises(lse.LSEError) as e:
+        lse.Batch([j, big])
+    assert e.value.status == lse.LSE_ERR_UNSUPPORTED

@@ -41,3 +41,20 @@ def test_batch_shapes_and_serving_trace():
     arr = np.array([j.arrival_s for j in jobs])
     assert np.all(np.diff(arr) > 0)
     assert abs(arr[-1] / 200 - 1 / 50.0) < 0.01
+
+
+def test_runway_sizes_are_given_at_8192():
+    # the runway is 60-120 px wide and 2000-4000 px long at an 8192 px side,
+    # scaled down (never up) for smaller scenes; its edge seeds lie inside it
+    sc = synth.scene_multiband(4, size=2048, n_roofs=0, n_roads=0, runway=True, noise=0.0)
+    cy, cx, theta, width, length = sc.meta["runway"]
+    assert 60 / 4 <= width <= 120 / 4 and 2000 / 4 <= length <= 4000 / 4
+    assert sc.init_edge.any() and not (sc.init_edge & (1 - sc.truth)).any()
+
+
+def test_crop_scene_has_its_own_initial_curve():
+    sc = synth.scene_multiband(1, size=512)
+    c = synth.crop_scene(sc, 100, 50, 128, 200)
+    assert c.image.shape == (128, 200, 4)
+    assert np.array_equal(c.image, sc.image[100:228, 50:250])
+    assert c.init_region.sum() == 64 * 100 and c.init_region[32:96, 50:150].all()

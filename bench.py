@@ -18,8 +18,13 @@ the K timed steps (2 x 200 x 4096^2 per step).  The line also carries
     FP16 storage) against the 64 images run one after another (plain FP32);
   * precision -- 8192 x 8192 x 4 runway scene (sigma 2 / 13 x 13, 300
     iterations) with the image / edge map stored in FP32, FP16 and BF16:
-    throughput, and agreement of the 16-bit runs with the FP32 run; and the
-    same generator at 1024 x 1024 against the FP64 oracle.
+    throughput, and agreement of the 16-bit runs with the FP32 run; and a
+    1024 x 1024 window of it against the FP64 oracle;
+  * serving -- 2000 jobs (sides log-uniform 256-4096, 1 or 4 bands, region or
+    edge, 100-300 iterations) arriving as a Poisson stream at 80 % of the
+    measured batched capacity: continuous batching with FP16 storage under a
+    200 GB budget (and a 2 GB budget for queueing) against one-at-a-time
+    plain FP32 solves of the same trace; throughput and p50 / p99 latency.
 """
 import argparse
 import json
@@ -48,8 +53,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="batched,precision",
-                    help="extra sections after the headline job: batched, precision (comma-separated; empty for none)")
+    ap.add_argument("--sections", default="batched,precision,serving",
+                    help="extra sections after the headline job: batched, precision, serving (comma-separated; "
+                         "empty for none)")
+    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of batched capacity")
     ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations per term in the CPU sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -263,6 +271,47 @@ def section_precision(args):
     return out
 
 
+def section_serving(args):
+    """Continuous-batching server vs one-at-a-time plain solves on one trace."""
+    import dataclasses
+
+    import torch
+
+    from paper_1409_7474_amd import serve, synth
+    dev = torch.device("cuda:0")
+    pool = serve.PoolInputs(synth.serving_pool(0), dev)
+    base = synth.serving_trace(0, n_jobs=args.serve_jobs, qps=1.0)
+    work = [j.side * j.side * j.iters for j in base]
+    mean_work = sum(work) / len(work)
+    budget = 200 << 30
+    # Capacity: the first 300 jobs all present at t = 0 (saturated batching).
+    probe = [dataclasses.replace(j, arrival_s=0.0) for j in base[:300]]
+    serve.serve(probe[:20], pool, budget_bytes=budget, storage="f16")  # warm-up
+    cap = serve.serve(probe, pool, budget_bytes=budget, storage="f16")
+    cap_pxit = cap.pixel_iters / cap.makespan_s
+    qps = args.serve_load * cap_pxit / mean_work
+    trace = synth.serving_trace(0, n_jobs=args.serve_jobs, qps=qps)
+    served = serve.serve(trace, pool, budget_bytes=budget, storage="f16", keep_masks=True)
+    plain = serve.serve_plain(trace, pool, storage="f32", keep_masks=True)
+    dis, px = 0, 0
+    worst = 0.0
+    for a, b in zip(served.records, plain.records):
+        d = int((a.mask != b.mask).sum().item())
+        dis += d
+        px += a.pixels
+        worst = max(worst, d / a.pixels)
+        a.mask = b.mask = None
+    small = serve.serve(trace[:300], pool, budget_bytes=2 << 30, storage="f16")
+    return {"workload": f"{len(trace)} jobs, Poisson arrivals at {qps:.1f} jobs/s ({args.serve_load:.0%} of the "
+                        f"measured batched capacity), side log-uniform 256-4096, 1 or 4 bands, region/edge 50/50, "
+                        f"100-300 iterations, sigma 1.5 / 11x11; inputs cut from a resident 4096^2 pool scene",
+            "capacity": {"Mpixel_iter_per_s": round(cap_pxit / 1e6, 1),
+                         "jobs_per_s": round(cap_pxit / mean_work, 2), "probe_jobs": len(probe)},
+            "batched_f16_200GB": served.summary(), "plain_f32": plain.summary(),
+            "batched_f16_2GB_first300": small.summary(),
+            "mask_disagreement_batched_f16_vs_plain_f32": {"all_pixels": dis / px, "worst_job": worst}}
+
+
 def main():
     args = parse()
     if args.calibrate_copy_mib:
@@ -387,6 +436,8 @@ def main():
         out["batched"] = section_batched(args)
     if "precision" in sections:
         out["precision"] = section_precision(args)
+    if "serving" in sections:
+        out["serving"] = section_serving(args)
     print(json.dumps(out), flush=True)
 
 

@@ -250,6 +250,21 @@ def serving_trace(seed: int = 0, n_jobs: int = 2000, qps: float = 10.0):
     return jobs
 
 
+def serving_pool(seed: int = 0, size: int = 4096) -> Scene:
+    """Resident source of serving inputs: one multiband scene of the large
+    workload's model (roads, roofs) at `size`; every job takes a window of it
+    (serving_window), so jobs of side s see object counts scaled by area."""
+    return scene_multiband(seed, size=size, n_roofs=max(1, int(round(40 * (size / 4096.0) ** 2))),
+                           n_roads=max(1, int(round(6 * size / 4096.0))), workload=SERVING, image_id=0)
+
+
+def serving_window(job: Job, pool_size: int = 4096, seed: int = 0):
+    """Top-left corner of job's side x side window in the serving pool."""
+    rng = _rng(SERVING, job.job_id + 1, seed)
+    side = min(job.side, pool_size)
+    return int(rng.integers(0, pool_size - side + 1)), int(rng.integers(0, pool_size - side + 1))
+
+
 def serving_scene(job: Job, seed: int = 0) -> Scene:
     """Scene for one serving job: the multiband generator with counts scaled
     by area; single-band jobs take the band mean."""

@@ -1,0 +1,61 @@
+"""GPU test of the serving loop: continuous batching under an HBM budget.
+
+Every served job's mask must equal the mask of the same job run alone (plain
+lse_run on the same input, same storage): the batch keeps per-image state and
+exact statistics, so the comparison is bit for bit (the stated tolerance,
+1e-4 of the pixels, is therefore met with margin)."""
+import numpy as np
+import pytest
+
+from paper_1409_7474_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _trace():
+    # 14 small jobs, both terms, 1 and 4 bands, staggered arrivals (some at
+    # once), uneven iteration counts.
+    rng = np.random.default_rng(5)
+    jobs = []
+    t = 0.0
+    for i in range(14):
+        t += float(rng.exponential(0.01)) if i % 3 else 0.0
+        jobs.append(synth.Job(i, t, int(rng.integers(64, 400)), 1 if i % 2 else 4,
+                              "region" if i % 4 < 2 else "edge", int(rng.integers(20, 60))))
+    return jobs
+
+
+@pytest.mark.parametrize("budget_mb", [4096, 24])
+def test_served_results_equal_solo_runs(dev, budget_mb):
+    """With a large budget every job runs concurrently; with 24 MB jobs queue
+    for memory and join running batches as others finish."""
+    from paper_1409_7474_amd import lse, serve
+    pool = serve.PoolInputs(synth.serving_pool(0, size=512), dev)
+    trace = _trace()
+    st = serve.serve(trace, pool, budget_bytes=budget_mb << 20, storage="f16", chunk=8, keep_masks=True)
+    assert len(st.records) == len(trace)
+    if budget_mb == 24:
+        assert st.max_queue > 0 and st.batches_built > 3
+    else:
+        assert st.max_running > 3
+    for rec, job in zip(st.records, sorted(trace, key=lambda j: j.job_id)):
+        assert rec.completed_s >= rec.admitted_s >= rec.arrival_s - 1e-9
+        img, init = pool(job)
+        solo = lse.LSE(img, init, term=job.term, sigma=1.5, ksize=11, storage="f16")
+        solo.run(job.iters)
+        assert solo.stats()["iters_done"] == job.iters
+        assert torch.equal(rec.mask, solo.mask()), f"job {job.job_id} differs from its solo run"
+    s = st.summary()
+    assert s["jobs"] == len(trace) and s["latency_p99_ms"] >= s["latency_p50_ms"] > 0
+
+
+def test_plain_server_matches(dev):
+    from paper_1409_7474_amd import serve
+    pool = serve.PoolInputs(synth.serving_pool(0, size=512), dev)
+    trace = _trace()[:5]
+    a = serve.serve_plain(trace, pool, storage="f32", keep_masks=True)
+    b = serve.serve(trace, pool, budget_bytes=1 << 30, storage="f32", keep_masks=True)
+    for ra, rb in zip(a.records, b.records):
+        assert torch.equal(ra.mask, rb.mask)

@@ -54,14 +54,17 @@ typedef enum {
     LSE_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
 } lse_status;
 
-/* Data term: region, eq. (17); edge, eq. (14). */
-typedef enum { LSE_TERM_REGION = 0, LSE_TERM_EDGE = 1 } lse_term;
+/* Data term: region, eq. (17), on the band vector; edge, eq. (14) (on the band
+ * mean); region on the band-mean intensity only (B values averaged at init,
+ * then the single-band region term). */
+typedef enum { LSE_TERM_REGION = 0, LSE_TERM_EDGE = 1, LSE_TERM_REGION_INTENSITY = 2 } lse_term;
 
 /* Element types of caller buffers and of the device-resident image copy. */
 typedef enum { LSE_F32 = 0, LSE_F16 = 1, LSE_BF16 = 2 } lse_dtype;
 
 /* Step order.  TABLE1: update -> binarise -> smooth (Table I steps 2-4).
- * LISTING: update -> smooth -> binarise (the appendix code). */
+ * LISTING: update -> smooth -> binarise (the appendix code): the LSF is the
+ * sign of the smoothed update; lse_lsf then returns that pre-sign field. */
 typedef enum { LSE_ORDER_TABLE1 = 0, LSE_ORDER_LISTING = 1 } lse_order;
 
 typedef struct {
@@ -69,7 +72,7 @@ typedef struct {
                               below 4 GiB - 1 MiB (edge term: H * W * 4)      */
     int32_t bands;         /* B in 1..4                                       */
     int32_t term;          /* lse_term                                        */
-    int32_t order;         /* lse_order (this build: TABLE1)                  */
+    int32_t order;         /* lse_order                                       */
     int32_t image_dtype;   /* lse_dtype of the caller's image buffer          */
     int32_t storage;       /* lse_dtype of the resident image (region) or edge
                               map (edge); values are rounded to it once at
@@ -84,7 +87,12 @@ typedef struct {
     float edge_scale;      /* edge term: intensity scale applied to the band
                               mean before g(I) (255 = 8-bit numbers as in the
                               listing, for images given in [0, 1])            */
-    int32_t reinit_every;  /* 1 = binarise every iteration (this build: 1)    */
+    int32_t reinit_every;  /* binarise in iteration n (0-based) iff
+                              (n + 1) % reinit_every == 0; 1 = every iteration
+                              (the fast binary-state path), 0 = never (region
+                              terms only; the edge term needs reinitialisation).
+                              Other than TABLE1 with 1, the LSF is kept as a
+                              continuous plane of the storage type.            */
 } lse_params;
 
 /* Fill *p with the defaults (region term, Table I order, dt 15, sigma 1,
@@ -100,7 +108,9 @@ typedef struct {
     int32_t iters_done;  /* iterations executed since lse_init / lse_set_mask */
     int32_t converged;   /* 1 once an iteration changed no pixel (Step 5)     */
     int32_t bad_value;   /* 1 if lse_init found a non-finite / out-of-range value */
-    int32_t reserved;
+    int32_t lsf_overflow;/* 1 if a continuous LSF (no binarisation in some
+                            iterations) left the range of the storage type;
+                            the iteration stopped there                       */
     float c_plus[4];     /* c+ used by the last iteration (region term)       */
     float c_minus[4];    /* c- used by the last iteration (region term)       */
     float M;             /* normaliser max|D| used by the last iteration      */
@@ -165,8 +175,8 @@ lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, v
 /* Copy the state summary to *host_out; synchronises `stream`. */
 lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream);
 
-/* Synchronise `stream`; LSE_ERR_BAD_VALUE if lse_init found a bad value,
- * LSE_ERR_DEVICE on a pending device error, LSE_OK otherwise. */
+/* Synchronise `stream`; LSE_ERR_BAD_VALUE if lse_init found a bad value or the
+ * LSF overflowed, LSE_ERR_DEVICE on a pending device error, LSE_OK otherwise. */
 lse_status lse_check(const lse_ctx *c, void *stream);
 
 /* Profiling of this context; `flags` (0 = off) resets the totals.

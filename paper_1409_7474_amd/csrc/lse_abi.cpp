@@ -18,6 +18,9 @@ struct lse_ctx {
     lse_params p;
     int NB;             // stored bands (1, 2 or 4)
     int esz;            // bytes of one stored value (storage type)
+    int region;         // region data term (eq. (17)), on the bands or on their mean
+    int dense;          // continuous LSF kept in a plane (any mode but Table I with binarisation every iteration)
+    int phi_binary;     // dense: the next iteration's phi is the binary function in the bit plane
     int r, ts, nch;     // LSF smoothing
     int r1, ts1;        // edge term: image pre-smoothing
     int WW;             // bit words per row
@@ -32,6 +35,7 @@ struct lse_ctx {
     void *img;          // region: storage image; edge: edge map g
     float *boxes;       // region, B > 1: per-block band min / max for the normaliser
     uint32_t *bits[2];
+    void *plane[2];     // dense: LSF planes (storage type), iteration n reads plane[n & 1]
     float *tmp[2];
     Taps host_taps;
     hipStream_t last_stream;
@@ -89,7 +93,8 @@ lse_status validate(const lse_params *p) {
     if (p->height < 2 || p->width < 2) return LSE_ERR_INVALID_ARG;
     if ((long long)p->height * (long long)p->width >= (1ll << 31)) return LSE_ERR_INVALID_ARG;
     if (p->bands < 1 || p->bands > 4) return LSE_ERR_INVALID_ARG;
-    if (p->term != LSE_TERM_REGION && p->term != LSE_TERM_EDGE) return LSE_ERR_INVALID_ARG;
+    if (p->term != LSE_TERM_REGION && p->term != LSE_TERM_EDGE && p->term != LSE_TERM_REGION_INTENSITY)
+        return LSE_ERR_INVALID_ARG;
     if (p->order != LSE_ORDER_TABLE1 && p->order != LSE_ORDER_LISTING) return LSE_ERR_INVALID_ARG;
     if (p->image_dtype != LSE_F32 && p->image_dtype != LSE_F16 && p->image_dtype != LSE_BF16)
         return LSE_ERR_INVALID_ARG;
@@ -97,7 +102,7 @@ lse_status validate(const lse_params *p) {
     {
         // The device image copy (region: bands padded to 1, 2 or 4 values;
         // edge: one value) is addressed with 32-bit byte offsets.
-        const unsigned long long nb = p->term == LSE_TERM_EDGE ? 1 : (p->bands == 3 ? 4 : p->bands);
+        const unsigned long long nb = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
         const unsigned long long es = p->storage == LSE_F32 ? 4 : 2;
         if ((unsigned long long)p->height * p->width * nb * es >= 0xfff00000ull) return LSE_ERR_INVALID_ARG;
     }
@@ -110,19 +115,20 @@ lse_status validate(const lse_params *p) {
         if (!(isfinite(p->edge_scale) && p->edge_scale > 0.f)) return LSE_ERR_INVALID_ARG;
     }
     if (p->reinit_every < 0) return LSE_ERR_INVALID_ARG;
-    // Valid requests that this build does not implement.
-    if (p->order != LSE_ORDER_TABLE1) return LSE_ERR_UNSUPPORTED;
-    if (p->reinit_every != 1) return LSE_ERR_UNSUPPORTED;
+    // The edge term needs reinitialisation (periodic at least).
+    if (p->term == LSE_TERM_EDGE && p->reinit_every == 0) return LSE_ERR_INVALID_ARG;
     return LSE_OK;
 }
 
 struct Layout {
-    size_t state, taps, args, img, boxes, bits0, bits1, tmp0, tmp1, total;
+    size_t state, taps, args, img, boxes, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
 };
+
+bool dense_mode(const lse_params *p) { return !(p->order == LSE_ORDER_TABLE1 && p->reinit_every == 1); }
 
 Layout layout_of(const lse_params *p) {
     const size_t hw = (size_t)p->height * p->width;
-    const int NB = p->bands == 3 ? 4 : p->bands;
+    const int NB = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
     const size_t WW = ((size_t)p->width + 31) / 32;
     Layout L;
     size_t o = 0;
@@ -134,9 +140,9 @@ Layout layout_of(const lse_params *p) {
     o = align_up(o + sizeof(ImgArgs));
     const size_t es = p->storage == LSE_F32 ? 4 : 2;
     L.img = o;
-    o = align_up(o + (p->term == LSE_TERM_REGION ? hw * NB * es : hw * es));
+    o = align_up(o + hw * NB * es);
     L.boxes = 0;
-    if (p->term == LSE_TERM_REGION && NB > 1) {
+    if (NB > 1) {
         L.boxes = o;
         o = align_up(o + mbox_floats(p->height, p->width, NB) * 4);
     }
@@ -144,6 +150,13 @@ Layout layout_of(const lse_params *p) {
     o = align_up(o + (size_t)p->height * WW * 4);
     L.bits1 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
+    L.plane0 = L.plane1 = 0;
+    if (dense_mode(p)) {
+        L.plane0 = o;
+        o = align_up(o + hw * es);
+        L.plane1 = o;
+        o = align_up(o + hw * es);
+    }
     if (p->term == LSE_TERM_EDGE) {
         L.tmp0 = o;
         o = align_up(o + hw * 4);
@@ -230,6 +243,11 @@ StepArgs step_args(const lse_ctx *c) {
     a.fix = c->fix;
     a.inv_fix = c->inv_fix;
     a.hw = c->hw;
+    a.plane_in = nullptr;
+    a.plane_out = nullptr;
+    a.order = c->p.order;
+    a.reinit = 1;
+    a.phi_binary = 0;
     return a;
 }
 
@@ -258,9 +276,25 @@ void prof_end(lse_ctx *c, hipStream_t s, lse_ctx::Ev *ev) {
     c->pending.push_back(*ev);
 }
 
+// The LSF of iteration 0 from the binary function in bits[0] (raw: phi is the
+// binary function; else its Gaussian smoothing) and its region statistics.
+hipError_t load_lsf(lse_ctx *c, int raw, hipStream_t s) {
+    StepArgs a = step_args(c);
+    a.bits_in = c->bits[0];
+    hipError_t e = hipSuccess;
+    if (c->dense) {
+        c->phi_binary = raw;
+        e = launch_plane_fill(a, c->bits[0], raw, c->plane[0], c->p.storage, s);
+        if (e == hipSuccess && c->region) e = launch_plane_stats(a, c->plane[0], c->NB, c->p.storage, 0, s);
+    } else if (c->region) {
+        e = launch_stats(a, c->NB, c->p.storage, raw, 0, s);
+    }
+    return e;
+}
+
 lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     hipError_t e = hipSuccess;
-    const bool region = c->p.term == LSE_TERM_REGION;
+    const bool region = c->region;
     const int storage = c->p.storage;
     if (region && c->NB > 1) {
         lse_ctx::Ev ev{nullptr, nullptr, -1};
@@ -273,14 +307,26 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     a.stop = stop;
     lse_ctx::Ev ev{nullptr, nullptr, -1};
     prof_begin(c, 0, s, &ev);
-    if (fast_radius(c->r))
+    int next_binary = 0;
+    if (c->dense) {
+        const int every = c->p.reinit_every;
+        a.reinit = every > 0 && ((c->n + 1) % every) == 0;
+        a.order = c->p.order;
+        a.phi_binary = c->phi_binary;
+        a.plane_in = c->plane[c->n & 1];
+        a.plane_out = c->plane[(c->n + 1) & 1];
+        e = launch_dense_step(a, c->NB, region ? 0 : 1, storage, s);
+        next_binary = a.order == LSE_ORDER_LISTING && a.reinit;
+    } else if (fast_radius(c->r)) {
         e = launch_step(c->dargs, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
                         region ? 0 : 1, storage, s);
-    else
+    } else {
         e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
+    }
     prof_end(c, s, &ev);
     if (e != hipSuccess) return LSE_ERR_DEVICE;
-    if (c->prof & LSE_PROFILE_COUNT) {
+    c->phi_binary = next_binary;
+    if ((c->prof & LSE_PROFILE_COUNT) && !c->dense) {
         if (launch_count_needed(a, a.raw, region ? 0 : 1, s) != hipSuccess) return LSE_ERR_DEVICE;
     }
     c->n += 1;
@@ -334,8 +380,11 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     lse_ctx *c = new (std::nothrow) lse_ctx();
     if (!c) return LSE_ERR_INVALID_ARG;
     c->p = *p;
-    c->NB = p->bands == 3 ? 4 : p->bands;
+    c->region = p->term != LSE_TERM_EDGE;
+    c->NB = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
     c->esz = p->storage == LSE_F32 ? 4 : 2;
+    c->dense = dense_mode(p) ? 1 : 0;
+    c->phi_binary = 1;
     c->ts = resolved_ksize(p->ksize, p->sigma);
     c->r = c->ts / 2;
     c->nch = (c->ts + kChunkBits - 1) / kChunkBits;
@@ -356,6 +405,8 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     c->boxes = L.boxes ? reinterpret_cast<float *>(base + L.boxes) : nullptr;
     c->bits[0] = reinterpret_cast<uint32_t *>(base + L.bits0);
     c->bits[1] = reinterpret_cast<uint32_t *>(base + L.bits1);
+    c->plane[0] = L.plane0 ? base + L.plane0 : nullptr;
+    c->plane[1] = L.plane1 ? base + L.plane1 : nullptr;
     c->tmp[0] = L.tmp0 ? reinterpret_cast<float *>(base + L.tmp0) : nullptr;
     c->tmp[1] = L.tmp1 ? reinterpret_cast<float *>(base + L.tmp1) : nullptr;
     c->prof = 0;
@@ -381,7 +432,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.target = 0x7fffffff;
         A.hw = c->hw;
         A.n0 = 0;
-        A.mgroups = (p->term == LSE_TERM_REGION && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
+        A.mgroups = (c->region && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
     }
 
     hipStream_t st = as_stream(stream);
@@ -390,9 +441,9 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     if (e == hipSuccess) e = hipMemcpyAsync(c->dargs, &c->host_args, sizeof(ImgArgs), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_init_state(c->st, 1, st);
     if (e == hipSuccess) {
-        if (p->term == LSE_TERM_REGION) {
+        if (c->region) {
             e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st, c->fix,
-                                  0, 0.f, st);
+                                  p->term == LSE_TERM_REGION ? 0 : 2, 0.f, st);
             if (e == hipSuccess && c->NB > 1)
                 e = launch_mbox(c->img, p->height, p->width, c->NB, p->storage, c->boxes, st);
         } else {
@@ -404,11 +455,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         }
     }
     if (e == hipSuccess) e = launch_pack_mask(init_mask_dev, c->bits[0], p->height, p->width, c->WW, st);
-    if (e == hipSuccess && p->term == LSE_TERM_REGION) {
-        StepArgs a = step_args(c);
-        a.bits_in = c->bits[0];
-        e = launch_stats(a, c->NB, p->storage, 1, 0, st);
-    }
+    if (e == hipSuccess) e = load_lsf(c, 1, st);
     if (e != hipSuccess) {
         delete c;
         return LSE_ERR_DEVICE;
@@ -440,6 +487,9 @@ lse_status lse_mask(const lse_ctx *c, uint8_t *mask_dev, void *stream) {
 
 lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream) {
     if (!c || !lsf_dev || (reinterpret_cast<uintptr_t>(lsf_dev) & 3)) return LSE_ERR_INVALID_ARG;
+    if (c->dense)
+        return dev_status(launch_plane_out(c->plane[0], c->plane[1], c->st, lsf_dev, c->hw, c->p.storage,
+                                           as_stream(stream)));
     const uint32_t *const b[2] = {c->bits[0], c->bits[1]};
     StepArgs a = step_args(c);
     return dev_status(launch_lsf_out(a, b, c->raw_next, lsf_dev, as_stream(stream)));
@@ -452,11 +502,7 @@ lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, v
     if (e == hipSuccess) e = launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
     c->n = 0;
     c->raw_next = smoothed ? 0 : 1;
-    if (e == hipSuccess && c->p.term == LSE_TERM_REGION) {
-        StepArgs a = step_args(c);
-        a.bits_in = c->bits[0];
-        e = launch_stats(a, c->NB, c->p.storage, c->raw_next, 0, s);
-    }
+    if (e == hipSuccess) e = load_lsf(c, c->raw_next, s);
     c->last_stream = s;
     return dev_status(e);
 }
@@ -477,7 +523,8 @@ lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream) {
     host_out->flips = h.iters > 0 ? flips : 0;
     host_out->iters_done = h.iters;
     host_out->converged = h.done;
-    host_out->bad_value = h.bad ? 1 : 0;
+    host_out->bad_value = h.bad == kBadInput ? 1 : 0;
+    host_out->lsf_overflow = h.bad == kBadOverflow ? 1 : 0;
     for (int b = 0; b < 4; ++b) {
         host_out->c_plus[b] = h.last_cp[b];
         host_out->c_minus[b] = h.last_cm[b];
@@ -491,7 +538,7 @@ lse_status lse_check(const lse_ctx *c, void *stream) {
     const lse_status v = lse_stats(c, &st, stream);
     if (v != LSE_OK) return v;
     if (hipGetLastError() != hipSuccess) return LSE_ERR_DEVICE;
-    return st.bad_value ? LSE_ERR_BAD_VALUE : LSE_OK;
+    return (st.bad_value || st.lsf_overflow) ? LSE_ERR_BAD_VALUE : LSE_OK;
 }
 
 lse_status lse_profile(lse_ctx *c, int32_t flags) {
@@ -533,8 +580,8 @@ lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out) {
 double lse_step_bytes_per_pixel(const lse_ctx *c) {
     if (!c) return 0.0;
     const double state = 2.0 / 8.0;  // binary state: one bit read, one bit written
-    if (c->p.term == LSE_TERM_EDGE) return (double)c->esz + state;
-    return (double)c->esz * c->NB + state;
+    const double plane = c->dense ? 2.0 * c->esz : 0.0;  // continuous LSF: read and written
+    return (double)c->esz * c->NB + state + plane;
 }
 
 void lse_destroy(lse_ctx *c) {
@@ -580,7 +627,7 @@ size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
     std::vector<int> order;
     for (int i = 0; i < n; ++i) {
         if (!cs[i] || !seen.insert(cs[i]).second) return 0;  // null or repeated context
-        if (!fast_radius(cs[i]->r)) return 0;
+        if (!fast_radius(cs[i]->r) || cs[i]->dense) return 0;
         order.push_back(i);
     }
     auto key = [&](int i) {

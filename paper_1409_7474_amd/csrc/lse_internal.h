@@ -19,6 +19,8 @@ constexpr int kRowWords = 5;     // bit words staged per row in LDS (4 used + 1 
 constexpr uint64_t kNoFlips = ~0ull;  // "no previous iteration" marker
 
 constexpr int kBins = 64;             // accumulation lines (one per lane of a wave)
+constexpr int kBadInput = 1;          // DevState::bad values
+constexpr int kBadOverflow = 2;
 
 // One accumulation line of the region statistics of one LSF: fixed-point band
 // sums over {phi >= 0}, the count, the flip count of the iteration that
@@ -50,7 +52,7 @@ static_assert(sizeof(ImgBin) == 128, "one bin per 128-byte line");
 struct DevState {
     Bin slot[3][kBins];           // triple-buffered: read n%3, write (n+1)%3, clear (n+2)%3
     ImgBin img[kBins];
-    int bad;                      // nonzero: bad value found by init
+    int bad;                      // kBadInput: bad value found by init; kBadOverflow: LSF left the storage range
     int done;                     // sticky "stopped" flag (Step 5)
     int iters;                    // iterations executed since init / set_mask
     int raw;                      // iteration 0 starts from the binary function itself (no smoothing)
@@ -89,6 +91,12 @@ struct StepArgs {
     float fix;                // 2^s, fixed-point scale of the band sums
     float inv_fix;            // 2^-s
     long long hw;
+    // Continuous-LSF modes (other step orders / reinitialisation schedules):
+    const void *plane_in;     // phi^n (or the pre-sign field of a binarised phi^n), storage type
+    void *plane_out;          // the field stored by this iteration
+    int order;                // lse_order
+    int reinit;               // this iteration binarises (Table I step 3)
+    int phi_binary;           // phi^n is the binary function in bits_in (sign of the stored field)
 };
 
 // Device-resident arguments of one image for the step and normaliser
@@ -118,7 +126,7 @@ constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare wor
 template <typename T>
 struct Store {
     static hipError_t init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
-                                 DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s);
+                                 DevState *st, float fix, int mode, float gray_scale, hipStream_t s);
     static hipError_t edge_g(const float *Is, void *g, int H, int W, hipStream_t s);
     static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
@@ -127,6 +135,14 @@ struct Store {
     static hipError_t step_generic(const StepArgs &a, int NB, int edge, hipStream_t s);
     static hipError_t mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                             int NB, hipStream_t s);
+    // Continuous-LSF modes: one iteration; the LSF plane from the binary
+    // function (raw: +-1; else its Gaussian smoothing); the region statistics
+    // of a plane; the plane as FP32.
+    static hipError_t dense_step(const StepArgs &a, int NB, int edge, hipStream_t s);
+    static hipError_t plane_fill(const StepArgs &a, const uint32_t *bits, int raw, void *plane, hipStream_t s);
+    static hipError_t plane_stats(const StepArgs &a, const void *plane, int NB, int slot, hipStream_t s);
+    static hipError_t plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n,
+                                hipStream_t s);
 };
 
 // Kernel launchers (lse_kernels.hip).  All return hipSuccess or the launch
@@ -137,8 +153,10 @@ int step_tiles(int H, int W);            // workgroup tiles of the step kernel f
 int mpass_groups(int H, int W);          // workgroups of the normaliser pass
 hipError_t launch_init_state(DevState *st, int raw, hipStream_t s);
 hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);
+// mode 0: bands; 1: band mean x gray_scale in FP32 (edge map input); 2: band
+// mean (intensity-only region term).
 hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
-                             DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s);
+                             DevState *st, float fix, int mode, float gray_scale, hipStream_t s);
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s);
 hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slot, hipStream_t s);
 hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
@@ -152,6 +170,12 @@ unsigned step_launch_grid(int tiles);
 hipError_t launch_step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop, int r,
                        int NB, int edge, int storage, hipStream_t s);
 hipError_t launch_step_generic(const StepArgs &a, int NB, int edge, int storage, hipStream_t s);
+hipError_t launch_dense_step(const StepArgs &a, int NB, int edge, int storage, hipStream_t s);
+hipError_t launch_plane_fill(const StepArgs &a, const uint32_t *bits, int raw, void *plane, int storage,
+                             hipStream_t s);
+hipError_t launch_plane_stats(const StepArgs &a, const void *plane, int NB, int storage, int slot, hipStream_t s);
+hipError_t launch_plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n, int storage,
+                            hipStream_t s);
 hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                         int NB, int storage, hipStream_t s);
 hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s);

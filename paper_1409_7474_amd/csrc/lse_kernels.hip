@@ -275,12 +275,12 @@ hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s) {
 }
 
 hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
-                             DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s) {
-    if (want_gray) return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 1, gray_scale, s);
+                             DevState *st, float fix, int mode, float gray_scale, hipStream_t s) {
+    if (mode == 1) return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 1, gray_scale, s);
     switch (storage) {
-        case LSE_F32: return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 0, 0.f, s);
-        case LSE_F16: return Store<__half>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 0, 0.f, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 0, 0.f, s);
+        case LSE_F32: return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
+        case LSE_F16: return Store<__half>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
     }
     return hipErrorInvalidValue;
 }
@@ -367,6 +367,44 @@ hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits,
         case LSE_F32: return Store<float>::mpass(args, map, unit_bits, grid, k, stop, NB, s);
         case LSE_F16: return Store<__half>::mpass(args, map, unit_bits, grid, k, stop, NB, s);
         case LSE_BF16: return Store<__hip_bfloat16>::mpass(args, map, unit_bits, grid, k, stop, NB, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_step(const StepArgs &a, int NB, int edge, int storage, hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::dense_step(a, NB, edge, s);
+        case LSE_F16: return Store<__half>::dense_step(a, NB, edge, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::dense_step(a, NB, edge, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_fill(const StepArgs &a, const uint32_t *bits, int raw, void *plane, int storage,
+                             hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::plane_fill(a, bits, raw, plane, s);
+        case LSE_F16: return Store<__half>::plane_fill(a, bits, raw, plane, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::plane_fill(a, bits, raw, plane, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_stats(const StepArgs &a, const void *plane, int NB, int storage, int slot, hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::plane_stats(a, plane, NB, slot, s);
+        case LSE_F16: return Store<__half>::plane_stats(a, plane, NB, slot, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::plane_stats(a, plane, NB, slot, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n, int storage,
+                            hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::plane_out(p0, p1, st, out, n, s);
+        case LSE_F16: return Store<__half>::plane_out(p0, p1, st, out, n, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::plane_out(p0, p1, st, out, n, s);
     }
     return hipErrorInvalidValue;
 }

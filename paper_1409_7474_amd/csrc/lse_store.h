@@ -9,16 +9,19 @@
 
 namespace lse {
 
-// Convert the caller's image to the interleaved storage of type ST (NB >= B
-// bands, extra bands zero), check values, and reduce per-band min / max and
-// totals of the stored (rounded) values, so that the statistics describe
-// exactly the image the iterations read.  want_gray: write the band mean
-// times gray_scale (FP32) instead, for the edge map.
+// Convert the caller's image (B bands of type T) to the resident copy of type
+// ST and check its values.  mode 0: the bands (NB >= B slots, extra ones
+// zero); mode 1: the band mean times gray_scale (input of the edge map);
+// mode 2: the band mean (intensity-only region term).  The per-band totals,
+// minima and maxima of the stored (rounded) values are reduced into the image
+// statistics lines, so that they describe exactly the image the iterations
+// read.
 template <typename T, typename ST>
 __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restrict__ src, int B, int NB,
                                                               ST *__restrict__ dst, long long npx,
-                                                              DevState *st, float fix, int want_gray,
+                                                              DevState *st, float fix, int mode,
                                                               float gray_scale) {
+    const int nsv = mode == 0 ? B : (mode == 2 ? 1 : 0);  // statistics values per pixel
     float sum[4] = {0.f, 0.f, 0.f, 0.f};
     float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -32,12 +35,16 @@ __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restric
                 if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // also catches NaN / Inf
             }
         }
-        if (want_gray) {
-            float s = 0.f;
+        if (mode != 0) {
+            float g = 0.f;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                if (b < B) s += v[b];
-            dst[i] = from_f32<ST>(gray_scale * (s / (float)B));
+                if (b < B) g += v[b];
+            g = g / (float)B;
+            if (mode == 1) g = gray_scale * g;
+            const ST q = from_f32<ST>(g);
+            dst[i] = q;
+            v[0] = to_f32<ST>(q);
         } else {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -45,13 +52,13 @@ __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restric
                     const ST q = from_f32<ST>(v[b]);
                     dst[i * NB + b] = q;
                     v[b] = to_f32<ST>(q);
-                    if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // overflow of the storage type
                 }
             }
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            if (b < B) {
+            if (b < nsv) {
+                if (!(fabsf(v[b]) < 65536.f)) bad = 1;  // overflow of the storage type
                 sum[b] += v[b];
                 mn[b] = fminf(mn[b], v[b]);
                 mx[b] = fmaxf(mx[b], v[b]);
@@ -75,16 +82,15 @@ __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restric
     __syncthreads();
     if (threadIdx.x == 0) {
         ImgBin &bin = st->img[blockIdx.x % kBins];
-        for (int b = 0; b < B; ++b) {
+        for (int b = 0; b < nsv; ++b) {
             float s = 0.f, lo = INFINITY, hi = -INFINITY;
             for (int w = 0; w < kThreads / 64; ++w) {
                 s += red[w][b][0];
                 lo = fminf(lo, red[w][b][1]);
                 hi = fmaxf(hi, red[w][b][2]);
             }
-            if (!want_gray)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&bin.total[b]),
-                          (unsigned long long)__float2ll_rn(s * fix));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&bin.total[b]),
+                      (unsigned long long)__float2ll_rn(s * fix));
             atomicMin(&bin.imin_key[b], float_key(lo));
             atomicMax(&bin.imax_key[b], float_key(hi));
         }
@@ -859,6 +865,297 @@ __global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int ra
     reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
 }
 
+// ------------------------------------------------------ continuous LSF
+//
+// Step orders and reinitialisation schedules other than "binarise every
+// iteration, then smooth" keep a continuous LSF, stored as a plane of the
+// storage type.  One iteration on a 64 x 32 tile:
+//   1. phi^n on the tile plus an r+1 halo (from the plane, or +-1 from the bit
+//      plane when phi^n is a binary function: the initial LSF of eq. (13), or
+//      the sign of the field stored by a listing-order iteration);
+//   2. u = phi^n + dt R |grad phi^n| (eq. (18)) on the tile plus an r halo,
+//      binarised there when Table I step 3 applies in this iteration;
+//   3. the separable Gaussian of that field (zero padding): psi on the tile;
+//   4. the stored field is psi (the LSF, or in listing order with
+//      binarisation the pre-sign field whose sign is the LSF);
+//   5. the binary result b^n (sign of u after step 3, else sign of the new
+//      LSF) as bit words, flips against b^{n-1}, and the region statistics of
+//      the new LSF for the next iteration.
+// The new LSF's sign is taken from the value as stored (after rounding to the
+// storage type), so the statistics describe what the next iteration reads.
+
+struct DenseSmem {
+    float *P, *U, *Hh, *k, *red;
+};
+
+__host__ __device__ inline size_t dense_smem_words(int r) {
+    const size_t PH = kTileY + 2 * r + 2, PW = kTileX + 2 * r + 2;
+    const size_t UH = kTileY + 2 * r, UW = kTileX + 2 * r;
+    return PH * PW + UH * UW + UH * kTileX + 32 + 32;
+}
+
+__device__ __forceinline__ DenseSmem dense_carve(float *smem, int r) {
+    const int PH = kTileY + 2 * r + 2, PW = kTileX + 2 * r + 2;
+    const int UH = kTileY + 2 * r, UW = kTileX + 2 * r;
+    DenseSmem d;
+    d.P = smem;
+    d.U = d.P + PH * PW;
+    d.Hh = d.U + UH * UW;
+    d.k = d.Hh + UH * kTileX;
+    d.red = d.k + 32;
+    return d;
+}
+
+template <int NB, bool EDGE, typename ST>
+__global__ __launch_bounds__(kThreads) void dense_step_kernel(StepArgs A) {
+    extern __shared__ float smem[];
+    __shared__ Totals tot;
+    DevState *st = A.st;
+    const int sl = A.n % 3;
+    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
+    load_totals(st, sl, !EDGE, &tot);
+    {
+        int done = tot.done | tot.bad;
+        if (!done && A.stop && tot.flips == 0) done = 1;
+        if (done) {
+            if (lead && !tot.bad) st->done = 1;
+            return;
+        }
+    }
+    const int r = A.r, ts = A.ts, H = A.H, W = A.W;
+    const int PH = kTileY + 2 * r + 2, PW = kTileX + 2 * r + 2;
+    const int UH = kTileY + 2 * r, UW = kTileX + 2 * r;
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const DenseSmem d = dense_carve(smem, r);
+    const ST *plane_in = static_cast<const ST *>(A.plane_in);
+    ST *plane_out = static_cast<ST *>(A.plane_out);
+    const bool listing = A.order == LSE_ORDER_LISTING;
+    const bool bin_u = !listing && A.reinit;   // Table I step 3 in this iteration
+
+    // 1: phi^n on rows y0 - r - 1 .., columns x0 - r - 1 ..
+    for (int i = tid; i < ts; i += kThreads) d.k[i] = A.taps->k[i];
+    for (int i = tid; i < PH * PW; i += kThreads) {
+        const int q = i / PW, p = i - q * PW;
+        const int y = y0 - r - 1 + q, x = x0 - r - 1 + p;
+        float v = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            if (A.phi_binary)
+                v = ((A.bits_in[(size_t)y * A.WW + (x >> 5)] >> (x & 31)) & 1u) ? 1.f : -1.f;
+            else
+                v = to_f32<ST>(plane_in[(size_t)y * W + x]);
+        }
+        d.P[i] = v;
+    }
+    // Data-term coefficients.
+    float a[NB], m[NB], w = 0.f;
+    float cp[NB], cm[NB], M = 0.f;
+    if constexpr (!EDGE) {
+        slot_means<NB>(tot, A.hw, A.inv_fix, cp, cm);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            a[b] = cp[b] - cm[b];
+            m[b] = cp[b] + cm[b];
+        }
+        if constexpr (NB == 1) {
+            Px<1> lo, hi;
+            lo.v[0] = key_float(tot.imin_key[0]);
+            hi.v[0] = key_float(tot.imax_key[0]);
+            M = fmaxf(fabsf(region_D<1>(lo, a, m)), fabsf(region_D<1>(hi, a, m)));
+        } else {
+            M = __uint_as_float((unsigned int)(tot.mkey >> 32));
+        }
+        w = M > 0.f ? A.dt / M : 0.f;
+    }
+    __syncthreads();
+
+    // 2: u (or its sign) on the tile plus an r halo; zero outside the image.
+    for (int i = tid; i < UH * UW; i += kThreads) {
+        const int uy = i / UW, ux = i - uy * UW;
+        const int y = y0 - r + uy, x = x0 - r + ux;
+        float v = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            const float *c = d.P + (uy + 1) * PW + (ux + 1);
+            float gx, gy;
+            if (x == 0)
+                gx = c[1] - c[0];
+            else if (x == W - 1)
+                gx = c[0] - c[-1];
+            else
+                gx = 0.5f * (c[1] - c[-1]);
+            if (y == 0)
+                gy = c[PW] - c[0];
+            else if (y == H - 1)
+                gy = c[0] - c[-PW];
+            else
+                gy = 0.5f * (c[PW] - c[-PW]);
+            float u = c[0];
+            if (!(gx == 0.f && gy == 0.f)) {
+                const long long pix = (long long)y * W + x;
+                const float gm = sqrtf(gx * gx + gy * gy);
+                float coef;
+                if constexpr (EDGE)
+                    coef = A.dt * to_f32<ST>(static_cast<const ST *>(A.img)[pix]);
+                else
+                    coef = w * region_D<NB>(load_px<ST, NB>(static_cast<const ST *>(A.img), pix), a, m);
+                u = fmaf(coef, gm, u);
+            }
+            v = bin_u ? (u >= 0.f ? 1.f : -1.f) : u;
+        }
+        d.U[i] = v;
+    }
+    __syncthreads();
+
+    // 3: horizontal then vertical Gaussian (taps in order, FMA).
+    for (int i = tid; i < UH * kTileX; i += kThreads) {
+        const int uy = i / kTileX, ox = i - uy * kTileX;
+        const float *row = d.U + uy * UW + ox;
+        float h = 0.f;
+        for (int j = 0; j < ts; ++j) h = fmaf(d.k[j], row[j], h);
+        d.Hh[i] = h;
+    }
+    __syncthreads();
+
+    // 4-5: store, binary result, statistics of the new LSF.
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    int cnt = 0, flips = 0;
+    bool overflow = false;
+    for (int row = wave; row < kTileY; row += kThreads / 64) {
+        const int y = y0 + row, x = x0 + lane;
+        const bool ok = y < H && x < W;
+        bool bit = false, inside = false;
+        if (ok) {
+            float psi = 0.f;
+            const float *col = d.Hh + row * kTileX + lane;
+            for (int i = 0; i < ts; ++i) psi = fmaf(d.k[i], col[i * kTileX], psi);
+            const ST q = from_f32<ST>(psi);
+            plane_out[(size_t)y * W + x] = q;
+            const float stored = to_f32<ST>(q);
+            overflow |= !isfinite(stored);
+            // The next iteration's LSF: sign(psi) in listing order with
+            // binarisation (read from the bit plane), else the stored value.
+            inside = (listing && A.reinit) ? psi >= 0.f : stored >= 0.f;
+            bit = bin_u ? d.U[(row + r) * UW + lane + r] > 0.f : inside;
+            if constexpr (!EDGE) {
+                if (inside) {
+                    const Px<NB> p = load_px<ST, NB>(static_cast<const ST *>(A.img), (long long)y * W + x);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+                    ++cnt;
+                }
+            }
+        }
+        const unsigned long long bal = __ballot(bit);
+        if (lane < 2) {
+            const int gw = (x0 >> 5) + lane;
+            if (y < H && gw < A.WW) {
+                const int xs = gw * 32;
+                const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                const uint32_t nw = (uint32_t)(bal >> (32 * lane)) & valid;
+                const uint32_t ow = A.bits_in[(size_t)y * A.WW + gw] & valid;
+                A.bits_out[(size_t)y * A.WW + gw] = nw;
+                flips += __popc(nw ^ ow);
+            }
+        }
+    }
+    // Without binarisation the LSF can grow until it leaves the range of the
+    // storage type; such a state is flagged and stops the iteration.
+    if (__any(overflow) && lane == 0) st->bad = kBadOverflow;
+    TileSmem rs;
+    rs.red = d.red;
+    reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][block_linear_id() % kBins], A.fix, !EDGE);
+    if (lead_block) {
+        unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
+        for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+    }
+    if (lead) {
+        st->iters += 1;
+        if constexpr (!EDGE) {
+            for (int b = 0; b < NB; ++b) {
+                st->last_cp[b] = cp[b];
+                st->last_cm[b] = cm[b];
+            }
+            st->last_M = M;
+        }
+    }
+}
+
+// LSF plane from the binary function: +-1 (raw) or its Gaussian smoothing
+// (the same tile arithmetic as the LSF export), rounded to the storage type.
+template <typename ST>
+__global__ __launch_bounds__(kThreads) void plane_fill_kernel(StepArgs A, const uint32_t *__restrict__ bits, int raw,
+                                                              ST *__restrict__ plane) {
+    extern __shared__ float smem[];
+    const TileSmem s = carve(smem, A.r, A.nch, 0);
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    stage_tables(s, A.taps, A.ts, A.nch);
+    stage_bits(s.bn, bits, y0 - A.r, kTileY + 2 * A.r, x0, A.H, A.WW);
+    __syncthreads();
+    if (!raw) {
+        for (int i = threadIdx.x; i < (kTileY + 2 * A.r) * kTileX; i += kThreads) {
+            const int uy = i / kTileX, ox = i - uy * kTileX;
+            const int y = y0 - A.r + uy, x = x0 + ox;
+            float h = 0.f;
+            if (y >= 0 && y < A.H && x < A.W)
+                h = hconv_bits(s.bn + uy * kRowWords, ox + 32, x, A.W, A.r, A.ts, A.nch, s.lut, s.cum);
+            s.h[i] = h;
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < (kTileX * kTileY) / kThreads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int oy = i / kTileX, ox = i - oy * kTileX;
+        const int y = y0 + oy, x = x0 + ox;
+        if (y < A.H && x < A.W) {
+            float v;
+            if (raw) {
+                const uint32_t wd = s.bn[(oy + A.r) * kRowWords + ((ox + 32) >> 5)];
+                v = ((wd >> ((ox + 32) & 31)) & 1u) ? 1.f : -1.f;
+            } else {
+                v = vconv(s.h + oy * kTileX + ox, kTileX, s.k, A.ts);
+            }
+            plane[(size_t)y * A.W + x] = from_f32<ST>(v);
+        }
+    }
+}
+
+// Region statistics (eq. (15)) of the LSF stored in a plane.
+template <int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void plane_stats_kernel(StepArgs A, const ST *__restrict__ plane, int slot) {
+    __shared__ float red[kThreads / 64 * 8];
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+    int cnt = 0;
+    for (int k = 0; k < (kTileX * kTileY) / kThreads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int oy = i / kTileX, ox = i - oy * kTileX;
+        const int y = y0 + oy, x = x0 + ox;
+        if (y < A.H && x < A.W && to_f32<ST>(plane[(size_t)y * A.W + x]) >= 0.f) {
+            const Px<NB> p = load_px<ST, NB>(static_cast<const ST *>(A.img), (long long)y * A.W + x);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] += p.v[b];
+            ++cnt;
+        }
+    }
+    TileSmem rs;
+    rs.red = red;
+    reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
+}
+
+// The stored field as FP32: plane (iterations executed) & 1 holds it.
+template <typename ST>
+__global__ void plane_out_kernel(const ST *__restrict__ p0, const ST *__restrict__ p1, const DevState *st,
+                                 float *__restrict__ out, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const ST *plane = (st->iters & 1) ? p1 : p0;
+    if (i < n) out[i] = to_f32<ST>(plane[i]);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int R, int NB, bool EDGE, typename ST>
@@ -922,21 +1219,21 @@ static hipError_t launch_step_generic_t(const StepArgs &a, hipStream_t s) {
 
 template <typename ST>
 hipError_t Store<ST>::init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
-                                 DevState *st, float fix, int want_gray, float gray_scale, hipStream_t s) {
+                                 DevState *st, float fix, int mode, float gray_scale, hipStream_t s) {
     const dim3 grid(stream_blocks(npx, 4)), block(kThreads);
     ST *d = static_cast<ST *>(dst);
     switch (src_dtype) {
         case LSE_F32:
             hipLaunchKernelGGL((init_image_kernel<float, ST>), grid, block, 0, s, static_cast<const float *>(src), B,
-                               NB, d, npx, st, fix, want_gray, gray_scale);
+                               NB, d, npx, st, fix, mode, gray_scale);
             break;
         case LSE_F16:
             hipLaunchKernelGGL((init_image_kernel<__half, ST>), grid, block, 0, s, static_cast<const __half *>(src),
-                               B, NB, d, npx, st, fix, want_gray, gray_scale);
+                               B, NB, d, npx, st, fix, mode, gray_scale);
             break;
         case LSE_BF16:
             hipLaunchKernelGGL((init_image_kernel<__hip_bfloat16, ST>), grid, block, 0, s,
-                               static_cast<const __hip_bfloat16 *>(src), B, NB, d, npx, st, fix, want_gray,
+                               static_cast<const __hip_bfloat16 *>(src), B, NB, d, npx, st, fix, mode,
                                gray_scale);
             break;
         default:
@@ -1022,6 +1319,56 @@ hipError_t Store<ST>::mpass(const ImgArgs *args, const uint32_t *map, int unit_b
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int NB, bool EDGE, typename ST>
+static hipError_t launch_dense_t(const StepArgs &a, hipStream_t s) {
+    const size_t sm = dense_smem_words(a.r) * 4;
+    const hipError_t e = ensure_lds(dense_step_kernel<NB, EDGE, ST>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((dense_step_kernel<NB, EDGE, ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a);
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::dense_step(const StepArgs &a, int NB, int edge, hipStream_t s) {
+    if (edge) return launch_dense_t<1, true, ST>(a, s);
+    switch (NB) {
+        case 1: return launch_dense_t<1, false, ST>(a, s);
+        case 2: return launch_dense_t<2, false, ST>(a, s);
+        case 4: return launch_dense_t<4, false, ST>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+hipError_t Store<ST>::plane_fill(const StepArgs &a, const uint32_t *bits, int raw, void *plane, hipStream_t s) {
+    const size_t sm = tile_smem_bytes(a.r, a.nch, 0);
+    const hipError_t e = ensure_lds(plane_fill_kernel<ST>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((plane_fill_kernel<ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a, bits, raw,
+                       static_cast<ST *>(plane));
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::plane_stats(const StepArgs &a, const void *plane, int NB, int slot, hipStream_t s) {
+    const ST *p = static_cast<const ST *>(plane);
+    switch (NB) {
+        case 1: hipLaunchKernelGGL((plane_stats_kernel<1, ST>), tile_grid(a.H, a.W), dim3(kThreads), 0, s, a, p, slot); break;
+        case 2: hipLaunchKernelGGL((plane_stats_kernel<2, ST>), tile_grid(a.H, a.W), dim3(kThreads), 0, s, a, p, slot); break;
+        case 4: hipLaunchKernelGGL((plane_stats_kernel<4, ST>), tile_grid(a.H, a.W), dim3(kThreads), 0, s, a, p, slot); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n,
+                                hipStream_t s) {
+    hipLaunchKernelGGL((plane_out_kernel<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       static_cast<const ST *>(p0), static_cast<const ST *>(p1), st, out, n);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ LSE_ERR_DEVICE = -4
 LSE_ERR_STATE = -5
 LSE_ERR_UNSUPPORTED = -6
 
-TERMS = {"region": 0, "edge": 1}
+TERMS = {"region": 0, "edge": 1, "region_intensity": 2}
 ORDERS = {"table1": 0, "listing": 1}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -50,7 +50,7 @@ class lse_params(ctypes.Structure):
 class lse_stats_t(ctypes.Structure):
     _fields_ = [
         ("n_plus", ctypes.c_uint64), ("flips", ctypes.c_uint64), ("iters_done", ctypes.c_int32),
-        ("converged", ctypes.c_int32), ("bad_value", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("converged", ctypes.c_int32), ("bad_value", ctypes.c_int32), ("lsf_overflow", ctypes.c_int32),
         ("c_plus", ctypes.c_float * 4), ("c_minus", ctypes.c_float * 4), ("M", ctypes.c_float),
         ("pad", ctypes.c_float * 3),
     ]
@@ -356,9 +356,10 @@ class LSE:
 
     def stats(self) -> dict:
         s = lse_stats(self.ctx, self._s())
-        nb = self.shape[2]
+        nb = 1 if self.params.term == TERMS["region_intensity"] else self.shape[2]
         return {"n_plus": int(s.n_plus), "flips": int(s.flips), "iters_done": int(s.iters_done),
                 "converged": bool(s.converged), "bad_value": bool(s.bad_value),
+                "lsf_overflow": bool(s.lsf_overflow),
                 "c_plus": list(s.c_plus)[:nb], "c_minus": list(s.c_minus)[:nb], "M": float(s.M)}
 
     def check(self) -> int:

@@ -90,12 +90,24 @@ def test_16bit_storage_allows_larger_images():
     assert lse.lse_workspace_bytes(p16) > 0
 
 
-def test_unsupported_modes_reported():
-    for kw in ({"order": "listing"}, {"reinit_every": 0}):
-        p = lse.make_params(64, 64, 1, **kw)
-        ctx = ctypes.c_void_p()
-        st = lse.load().lse_init(ctypes.byref(p), 16, 16, 256, 1 << 30, None, ctypes.byref(ctx))
-        assert st == lse.LSE_ERR_UNSUPPORTED, kw
+def test_variant_modes_are_valid():
+    # listing order, reinitialisation schedules and the intensity-only term
+    # are implemented; they keep a continuous LSF plane in the workspace
+    base = lse.lse_workspace_bytes(lse.make_params(64, 64, 4))
+    for kw in ({"order": "listing"}, {"reinit_every": 0}, {"reinit_every": 3}):
+        n = lse.lse_workspace_bytes(lse.make_params(64, 64, 4, **kw))
+        assert n == base + 2 * 64 * 64 * 4, kw
+    gray = lse.lse_workspace_bytes(lse.make_params(64, 64, 4, term="region_intensity"))
+    assert gray < base  # one stored value per pixel, no normaliser boxes
+
+
+def test_edge_term_requires_reinitialisation():
+    p = lse.make_params(64, 64, 1, term="edge", reinit_every=0)
+    assert lse.lse_workspace_bytes(p) == 0
+    ctx = ctypes.c_void_p()
+    st = lse.load().lse_init(ctypes.byref(p), 16, 16, 256, 1 << 30, None, ctypes.byref(ctx))
+    assert st == lse.LSE_ERR_INVALID_ARG
+    assert lse.lse_workspace_bytes(lse.make_params(64, 64, 1, term="edge", reinit_every=4)) > 0
 
 
 def test_init_pointer_and_workspace_checks():

@@ -121,7 +121,7 @@ lse_status validate(const lse_params *p) {
 }
 
 struct Layout {
-    size_t state, taps, args, img, boxes, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
+    size_t state, taps, args, img, boxes, tilesum, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
 };
 
 bool dense_mode(const lse_params *p) { return !(p->order == LSE_ORDER_TABLE1 && p->reinit_every == 1); }
@@ -145,6 +145,11 @@ Layout layout_of(const lse_params *p) {
     if (NB > 1) {
         L.boxes = o;
         o = align_up(o + mbox_floats(p->height, p->width, NB) * 4);
+    }
+    L.tilesum = 0;
+    if (p->term != LSE_TERM_EDGE && !dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
+        L.tilesum = o;
+        o = align_up(o + (size_t)step_tiles(p->height, p->width) * sizeof(TileSum));
     }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
@@ -327,7 +332,8 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     if (e != hipSuccess) return LSE_ERR_DEVICE;
     c->phi_binary = next_binary;
     if ((c->prof & LSE_PROFILE_COUNT) && !c->dense) {
-        if (launch_count_needed(a, a.raw, region ? 0 : 1, s) != hipSuccess) return LSE_ERR_DEVICE;
+        if (launch_count_needed(a, a.raw, region ? 0 : 1, c->host_args.tilesum != nullptr, s) != hipSuccess)
+            return LSE_ERR_DEVICE;
     }
     c->n += 1;
     c->raw_next = 0;
@@ -433,6 +439,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.hw = c->hw;
         A.n0 = 0;
         A.mgroups = (c->region && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
+        A.tilesum = L.tilesum ? reinterpret_cast<const TileSum *>(base + L.tilesum) : nullptr;
     }
 
     hipStream_t st = as_stream(stream);
@@ -446,6 +453,9 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
                                   p->term == LSE_TERM_REGION ? 0 : 2, 0.f, st);
             if (e == hipSuccess && c->NB > 1)
                 e = launch_mbox(c->img, p->height, p->width, c->NB, p->storage, c->boxes, st);
+            if (e == hipSuccess && L.tilesum)
+                e = launch_tile_sums(c->dargs, c->host_args.tiles, c->r, c->NB, p->storage,
+                                     reinterpret_cast<TileSum *>(base + L.tilesum), st);
         } else {
             e = launch_init_image(image_dev, p->image_dtype, LSE_F32, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
                                   p->edge_scale, st);

@@ -428,10 +428,12 @@ __device__ __forceinline__ void stats_tile(const TileSmem &s, const ST *__restri
     }
 }
 
-// Workgroup reduction of (NB sums, count, flips) and one atomic per value.
+// Workgroup reduction of (NB sums, count, flips): the totals are valid in
+// thread 0.  FP32 sums in a fixed order (wave butterfly, then waves in
+// order), so a tile's partial sums are a function of its data alone.
 template <int NB>
-__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Bin *out,
-                                             float fix, bool with_sums) {
+__device__ __forceinline__ void block_reduce(const TileSmem &s, float (&acc)[NB], int cnt, int flips, bool with_sums,
+                                             float (&S)[NB], int &C, int &F) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (with_sums) {
 #pragma unroll
@@ -447,11 +449,11 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
         reinterpret_cast<int *>(rw)[7] = flips;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float S[NB];
-        int C = 0, F = 0;
+    C = 0;
+    F = 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) S[b] = 0.f;
+    for (int b = 0; b < NB; ++b) S[b] = 0.f;
+    if (threadIdx.x == 0) {
         for (int w = 0; w < kThreads / 64; ++w) {
             const float *rw = s.red + w * 8;
 #pragma unroll
@@ -459,6 +461,17 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
             C += reinterpret_cast<const int *>(rw)[6];
             F += reinterpret_cast<const int *>(rw)[7];
         }
+    }
+}
+
+// Workgroup reduction of (NB sums, count, flips) and one atomic per value.
+template <int NB>
+__device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Bin *out,
+                                             float fix, bool with_sums) {
+    float S[NB];
+    int C, F;
+    block_reduce<NB>(s, acc, cnt, flips, with_sums, S, C, F);
+    if (threadIdx.x == 0) {
         if (with_sums) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)

@@ -63,6 +63,14 @@ struct DevState {
     unsigned long long acc_steps;   // profiling: steps counted into acc_needed
 };
 
+// Region sums of one step tile when all of its pixels are on the + side:
+// the fixed-point value the step kernel's own reduction would produce.
+struct alignas(64) TileSum {
+    long long sum[4];
+    long long cnt;
+    long long pad[3];
+};
+
 // Constant tables, copied once into the workspace.
 struct Taps {
     float k[32];                    // 1-D LSF smoothing taps, k[j] for offset j - r
@@ -116,6 +124,8 @@ struct alignas(16) ImgArgs {
     long long hw;
     int n0;                   // iteration index of launch k = 0
     int mgroups;              // workgroups of the normaliser pass (B > 1)
+    const TileSum *tilesum;   // region term: per-tile sums of the all-inside case
+    long long pad;
 };
 
 constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare workgroup
@@ -143,6 +153,8 @@ struct Store {
     static hipError_t plane_stats(const StepArgs &a, const void *plane, int NB, int slot, hipStream_t s);
     static hipError_t plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n,
                                 hipStream_t s);
+    // Per-tile region sums of the all-inside case (args[0], radius r).
+    static hipError_t tile_sums(const ImgArgs *args, int tiles, int r, int NB, TileSum *out, hipStream_t s);
 };
 
 // Kernel launchers (lse_kernels.hip).  All return hipSuccess or the launch
@@ -179,11 +191,12 @@ hipError_t launch_plane_out(const void *p0, const void *p1, const DevState *st, 
 hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                         int NB, int storage, hipStream_t s);
 hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s);
+hipError_t launch_tile_sums(const ImgArgs *args, int tiles, int r, int NB, int storage, TileSum *out, hipStream_t s);
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W,
                            int WW, hipStream_t s);
 hipError_t launch_lsf_out(const StepArgs &a, const uint32_t *const bits[2], int raw, float *out,
                           hipStream_t s);
-hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, hipStream_t s);
+hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, int fast_quiet, hipStream_t s);
 hipError_t launch_reset_profile(DevState *st, hipStream_t s);
 
 }  // namespace lse

@@ -167,9 +167,10 @@ __global__ __launch_bounds__(kThreads) void lsf_out_kernel(StepArgs A, const uin
 // Recomputes phi^n from b^{n-1} (bits_in) and phi^{n+1} from b^n (bits_out)
 // with the step's own arithmetic, so the decisions match the step kernel's.
 // Profiling only; not part of any timed path.
-__global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int raw, int edge) {
+__global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int raw, int edge, int fast_quiet) {
     extern __shared__ float smem[];
     __shared__ int part[kThreads / 64];
+    __shared__ int quiet1[2];
     if (A.st->done || A.st->bad) return;  // the step did not run
     const int r = A.r, ts = A.ts, nch = A.nch, H = A.H, W = A.W;
     const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
@@ -223,6 +224,33 @@ __global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int 
         }
         __syncthreads();
     }
+    // The step kernel takes the region sums of a quiet all-inside tile (its
+    // 96 x 64 tiling, b^{n-1} uniform over the tile's whole bit window, away
+    // from the image border) from the sums stored at init: such pixels need
+    // no image read for the statistics.
+    for (int q = 0; q < 2; ++q) {
+        const int fx = x0 / kFX + q, fy = y0 / kFY;
+        const int X0 = fx * kFX, Y0 = fy * kFY;
+        const int BY0 = Y0 - 2 * r - 1, NR = kFY + 4 * r + 2;
+        int ones = 0;
+        if (fast_quiet && !edge && X0 < W && !(X0 - 2 * r - 2 < 0 || X0 + kFX + 2 * r + 2 > W) && BY0 >= 0 &&
+            BY0 + NR <= H) {
+            const int c0 = X0 - 1 - 2 * r, c1 = X0 + kFX + 1 + 2 * r;  // bit columns [c0, c1)
+            const int w0 = c0 >> 5, w1 = (c1 - 1) >> 5, nw = w1 - w0 + 1;
+            int all1 = 1;
+            for (int i = threadIdx.x; i < NR * nw; i += kThreads) {
+                const int row = i / nw, wi = w0 + i % nw;
+                uint32_t m = ~0u;
+                if (wi == w0) m &= ~0u << (c0 & 31);
+                if (wi == w1) m &= ~0u >> (31 - ((c1 - 1) & 31));
+                const uint32_t v = A.bits_in[(size_t)(BY0 + row) * A.WW + wi];
+                all1 &= (v & m) == m;
+            }
+            ones = __syncthreads_and(all1);
+        }
+        if (threadIdx.x == 0) quiet1[q] = ones;
+    }
+    __syncthreads();
     int cnt = 0;
     for (int i = threadIdx.x; i < kTileY * kTileX; i += kThreads) {
         const int oy = i / kTileX, ox = i - oy * kTileX, y = y0 + oy, x = x0 + ox;
@@ -236,7 +264,8 @@ __global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int 
         else if (y == H - 1) gy = c[0] - c[-PWc];
         else gy = 0.5f * (c[PWc] - c[-PWc]);
         bool need = !(gx == 0.f && gy == 0.f);
-        if (!edge) need = need || vconv(h + oy * kTileX + ox, kTileX, k, ts) >= 0.f;
+        if (!edge && !quiet1[x / kFX - x0 / kFX])
+            need = need || vconv(h + oy * kTileX + ox, kTileX, k, ts) >= 0.f;
         cnt += need ? 1 : 0;
     }
     cnt = wave_sum_i(cnt);
@@ -409,6 +438,15 @@ hipError_t launch_plane_out(const void *p0, const void *p1, const DevState *st, 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_tile_sums(const ImgArgs *args, int tiles, int r, int NB, int storage, TileSum *out, hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::tile_sums(args, tiles, r, NB, out, s);
+        case LSE_F16: return Store<__half>::tile_sums(args, tiles, r, NB, out, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::tile_sums(args, tiles, r, NB, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_prepare_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, args, n);
@@ -423,13 +461,14 @@ hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, ui
     return hipGetLastError();
 }
 
-hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, hipStream_t s) {
+hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, int fast_quiet, hipStream_t s) {
     const int BPR = kTileY + 2 + 2 * a.r, BCR = kTileY + 2 * a.r;
     const size_t words = (size_t)a.nch * 64 + 36 + 32 + (size_t)(BPR + BCR) * kRowWords +
                          (size_t)BPR * (kTileX + 2) + (size_t)(kTileY + 2) * (kTileX + 2);
     const hipError_t e = ensure_lds(count_needed_kernel, words * 4);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(count_needed_kernel, tile_grid(a.H, a.W), dim3(kThreads), words * 4, s, a, raw, edge);
+    hipLaunchKernelGGL(count_needed_kernel, tile_grid(a.H, a.W), dim3(kThreads), words * 4, s, a, raw, edge,
+                       fast_quiet);
     return hipGetLastError();
 }
 

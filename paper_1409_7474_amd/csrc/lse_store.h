@@ -597,227 +597,264 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
         }
         __syncthreads();
 
-        // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
-        {
-            const int chunk = wave & 1, seg = wave >> 1;
-            const int p = chunk * 64 + lane;
-            const int x = px0 + p;
-            const int xb = x - x0 + 32;
-            const bool colok = p < G::PW && x >= 0 && x < W;
-            if (raw) {
-                for (int j = 0; j < G::SEG; ++j) {
-                    const int q = seg * G::SEG + j, y = py0 + q;
-                    float v = 0.f;
-                    if (colok && y >= 0 && y < H) {
-                        const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
-                        v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
-                    }
-                    if (p < G::PW) s_phi[q * G::PS + p] = v;
-                    if (lane == 0) s_pcode[q * 2 + chunk] = 2;
-                }
-            } else {
-                constexpr int NW = 2 * R + kSB;
-                float win[NW];
-                const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
-                bool have_win = false;
-#pragma unroll 1
-                for (int blk = 0; blk < G::NBLK; ++blk) {
-                    const int rb = brow0 + blk * kSB;
-                    int uni = -1;
-                    if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
-                        uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
-                    if (uni >= 0) {
-                        const float v = uni ? phi_one : phi_zero;
-#pragma unroll
-                        for (int j = 0; j < kSB; ++j) {
-                            const int q = rb + j;
-                            if (p < G::PW) s_phi[q * G::PS + p] = colok ? v : 0.f;
-                        }
-                        if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
-                        have_win = false;
-                        continue;
-                    }
-                    if (!have_win) {
-#pragma unroll
-                        for (int t2 = 0; t2 < 2 * R; ++t2) {
-                            const int y = by0 + rb + t2;
-                            const float v =
-                                hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, border, lut, cum);
-                            win[t2] = (y >= 0 && y < H) ? v : 0.f;
-                        }
-                    }
-#pragma unroll
-                    for (int t2 = 0; t2 < kSB; ++t2) {
-                        const int brow = rb + 2 * R + t2;
-                        const int y = by0 + brow;
-                        const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
-                        win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
-                    }
-#pragma unroll
-                    for (int j = 0; j < kSB; ++j) {
-                        float ph = 0.f;
-#pragma unroll
-                        for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
-                        const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
-                        if (p < G::PW) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
-                    }
-                    if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
-#pragma unroll
-                    for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + kSB];
-                    have_win = true;
-                }
+        // Quiet tile: inside the image with its whole halo, and b^{n-1}
+        // uniform over every staged bit it reads.  Then phi^n is one constant
+        // there, |grad phi^n| = 0 and u = phi^n exactly (eq. (18)), so b^n =
+        // b^{n-1} on the tile plus its halo, and phi^{n+1} = G * b^n has that
+        // sign on every owned pixel: the tile's region sums are all or
+        // nothing.  The all-inside sums were computed at init by this
+        // kernel's own reduction (tile_sums_kernel), so the totals are those
+        // of the full computation bit for bit.
+        int quiet = -1;
+        if (!border && by0 >= 0 && by0 + G::PH + 2 * R <= H) {
+            int all1 = 1, all0 = 1;
+            for (int i = tid; i < (G::PH + 2 * R) * 2; i += kThreads) {
+                all1 &= s_codes[i] == 1;
+                all0 &= s_codes[i] == 0;
             }
+            all1 = __syncthreads_and(all1);
+            all0 = __syncthreads_and(all0);
+            quiet = all1 ? 1 : (all0 ? 0 : -1);
         }
-        __syncthreads();
-
-        // C: update eq. (18) and binarisation on U = tile + RU halo, in blocks
-        // of 8 rows per wave task; blocks whose phi rows are one uniform
-        // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
-        int flips = 0;
-        constexpr int NBC = (G::UH + kSB - 1) / kSB;
-#pragma unroll 1
-        for (int bi = wave; bi < NBC; bi += kThreads / 64) {
-            const int u0 = bi * kSB;
-            const int nr = min(kSB, G::UH - u0);
-            int rc = -1;
-            if (!border) {
-                const int ncode = (nr + 2) * 2;  // phi rows u0 .. u0 + nr + 1, both chunks
-                const int c = lane < ncode ? s_pcode[u0 * 2 + lane] : -1;
-                const unsigned long long full = (1ull << ncode) - 1ull;
-                if (__ballot(c == 1) == full)
-                    rc = 1;
-                else if (__ballot(c == 0) == full)
-                    rc = 0;
+        if (quiet >= 0) {
+            if (tid < kFY * 3) {
+                const int row = tid / 3, k = tid - row * 3;
+                A.bits_out[(size_t)(y0 + row) * A.WW + (x0 >> 5) + k] = quiet ? ~0u : 0u;
             }
-            if (rc >= 0) {
-                if (lane < nr * kFWords) {
-                    const int r = lane / kFWords, k = lane - r * kFWords;
-                    const int uy = u0 + r, y = y0 - G::RU + uy;
-                    const uint32_t word = rc ? (bits_extract(~0ull, 32 - G::RU, k) |
-                                                bits_extract(ones1, 96 - G::RU, k))
-                                             : 0u;
-                    s_bn[uy * kFWords + k] = word;
-                    const int gw = (x0 >> 5) - 1 + k;
-                    if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + kFY && y < H && gw < A.WW) {
-                        const int xs = gw * 32;
-                        const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
-                        const uint32_t nw = word & valid;
-                        const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + k] & valid;
-                        A.bits_out[(size_t)y * A.WW + gw] = nw;
-                        flips += __popc(nw ^ ow);
-                    }
+            if constexpr (!EDGE) {
+                if (quiet && tid == 0) {
+                    const TileSum &ts = E.tilesum[t];
+                    Bin *out = &st->slot[(A.n + 1) % 3][blockIdx.x % kBins];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]),
+                                  (unsigned long long)ts.sum[b]);
+                    atomicAdd(&out->nplus, (unsigned long long)ts.cnt);
                 }
-                continue;
             }
-            // Rows in groups of kCG: gradients first (LDS), then every data-term
-            // load of the group, then the updates, so that one memory round
-            // trip serves the whole group.
-#pragma unroll 1
-            for (int r0 = 0; r0 < nr; r0 += kCG) {
-                float phv[kCG][2], gmv[kCG][2];
-                bool need[kCG][2], pred[kCG][2];
-                int pixv[kCG][2];
-#pragma unroll
-                for (int i = 0; i < kCG; ++i) {
-                    const int uy = u0 + r0 + i;
-                    const int y = y0 - G::RU + uy;
-                    const bool rowok = r0 + i < nr && y >= 0 && y < H;
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const int xb = 32 - G::RU + c * 64 + lane;
-                        const int x = x0 - 32 + xb;
-                        need[i][c] = false;
-                        pred[i][c] = false;
-                        phv[i][c] = 0.f;
-                        gmv[i][c] = 0.f;
-                        pixv[i][c] = 0;
-                        if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
-                            const int p = c * 64 + lane + 1;
-                            const float *cc = s_phi + (uy + 1) * G::PS + p;
-                            float gx, gy;
-                            if (x == 0)
-                                gx = cc[1] - cc[0];
-                            else if (x == W - 1)
-                                gx = cc[0] - cc[-1];
-                            else
-                                gx = 0.5f * (cc[1] - cc[-1]);
-                            if (y == 0)
-                                gy = cc[G::PS] - cc[0];
-                            else if (y == H - 1)
-                                gy = cc[0] - cc[-G::PS];
-                            else
-                                gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
-                            phv[i][c] = cc[0];
-                            pred[i][c] = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                            if (!(gx == 0.f && gy == 0.f)) {
-                                need[i][c] = true;
-                                gmv[i][c] = sqrtf(gx * gx + gy * gy);
-                                pixv[i][c] = y * W + x;
+        } else {
+            // B: phi^n on P = tile + (RU + 1) halo; wave = (column chunk, row segment).
+            {
+                const int chunk = wave & 1, seg = wave >> 1;
+                const int p = chunk * 64 + lane;
+                const int x = px0 + p;
+                const int xb = x - x0 + 32;
+                const bool colok = p < G::PW && x >= 0 && x < W;
+                if (raw) {
+                    for (int j = 0; j < G::SEG; ++j) {
+                        const int q = seg * G::SEG + j, y = py0 + q;
+                        float v = 0.f;
+                        if (colok && y >= 0 && y < H) {
+                            const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
+                            v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
+                        }
+                        if (p < G::PW) s_phi[q * G::PS + p] = v;
+                        if (lane == 0) s_pcode[q * 2 + chunk] = 2;
+                    }
+                } else {
+                    constexpr int NW = 2 * R + kSB;
+                    float win[NW];
+                    const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
+                    bool have_win = false;
+    #pragma unroll 1
+                    for (int blk = 0; blk < G::NBLK; ++blk) {
+                        const int rb = brow0 + blk * kSB;
+                        int uni = -1;
+                        if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
+                            uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
+                        if (uni >= 0) {
+                            const float v = uni ? phi_one : phi_zero;
+    #pragma unroll
+                            for (int j = 0; j < kSB; ++j) {
+                                const int q = rb + j;
+                                if (p < G::PW) s_phi[q * G::PS + p] = colok ? v : 0.f;
+                            }
+                            if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
+                            have_win = false;
+                            continue;
+                        }
+                        if (!have_win) {
+    #pragma unroll
+                            for (int t2 = 0; t2 < 2 * R; ++t2) {
+                                const int y = by0 + rb + t2;
+                                const float v =
+                                    hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, border, lut, cum);
+                                win[t2] = (y >= 0 && y < H) ? v : 0.f;
                             }
                         }
+    #pragma unroll
+                        for (int t2 = 0; t2 < kSB; ++t2) {
+                            const int brow = rb + 2 * R + t2;
+                            const int y = by0 + brow;
+                            const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
+                            win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
+                        }
+    #pragma unroll
+                        for (int j = 0; j < kSB; ++j) {
+                            float ph = 0.f;
+    #pragma unroll
+                            for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
+                            const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
+                            if (p < G::PW) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
+                        }
+                        if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
+    #pragma unroll
+                        for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + kSB];
+                        have_win = true;
                     }
                 }
-                float coef[kCG][2];
-                {
-                    Px<NV> v[kCG][2];
-#pragma unroll
-                    for (int i = 0; i < kCG; ++i)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
-#pragma unroll
-                    for (int i = 0; i < kCG; ++i)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            if constexpr (EDGE)
-                                coef[i][c] = A.dt * v[i][c].v[0];
-                            else
-                                coef[i][c] = w * region_D<NB>(v[i][c], a, m);
-                        }
+            }
+            __syncthreads();
+
+            // C: update eq. (18) and binarisation on U = tile + RU halo, in blocks
+            // of 8 rows per wave task; blocks whose phi rows are one uniform
+            // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
+            int flips = 0;
+            constexpr int NBC = (G::UH + kSB - 1) / kSB;
+    #pragma unroll 1
+            for (int bi = wave; bi < NBC; bi += kThreads / 64) {
+                const int u0 = bi * kSB;
+                const int nr = min(kSB, G::UH - u0);
+                int rc = -1;
+                if (!border) {
+                    const int ncode = (nr + 2) * 2;  // phi rows u0 .. u0 + nr + 1, both chunks
+                    const int c = lane < ncode ? s_pcode[u0 * 2 + lane] : -1;
+                    const unsigned long long full = (1ull << ncode) - 1ull;
+                    if (__ballot(c == 1) == full)
+                        rc = 1;
+                    else if (__ballot(c == 0) == full)
+                        rc = 0;
                 }
-#pragma unroll
-                for (int i = 0; i < kCG; ++i) {
-                    if (r0 + i >= nr) break;
-                    const int uy = u0 + r0 + i;
-                    const int y = y0 - G::RU + uy;
-                    const bool rowok = y >= 0 && y < H;
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
-                    const unsigned long long m0 = __ballot(pred[i][0]);
-                    const unsigned long long m1 = __ballot(pred[i][1]);
-                    if (lane < kFWords) {
-                        const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
-                        s_bn[uy * kFWords + lane] = word;
-                        const int gw = (x0 >> 5) - 1 + lane;
-                        if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                if (rc >= 0) {
+                    if (lane < nr * kFWords) {
+                        const int r = lane / kFWords, k = lane - r * kFWords;
+                        const int uy = u0 + r, y = y0 - G::RU + uy;
+                        const uint32_t word = rc ? (bits_extract(~0ull, 32 - G::RU, k) |
+                                                    bits_extract(ones1, 96 - G::RU, k))
+                                                 : 0u;
+                        s_bn[uy * kFWords + k] = word;
+                        const int gw = (x0 >> 5) - 1 + k;
+                        if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + kFY && y < H && gw < A.WW) {
                             const int xs = gw * 32;
                             const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
                             const uint32_t nw = word & valid;
-                            const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                            const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + k] & valid;
                             A.bits_out[(size_t)y * A.WW + gw] = nw;
                             flips += __popc(nw ^ ow);
                         }
                     }
+                    continue;
+                }
+                // Rows in groups of kCG: gradients first (LDS), then every data-term
+                // load of the group, then the updates, so that one memory round
+                // trip serves the whole group.
+    #pragma unroll 1
+                for (int r0 = 0; r0 < nr; r0 += kCG) {
+                    float phv[kCG][2], gmv[kCG][2];
+                    bool need[kCG][2], pred[kCG][2];
+                    int pixv[kCG][2];
+    #pragma unroll
+                    for (int i = 0; i < kCG; ++i) {
+                        const int uy = u0 + r0 + i;
+                        const int y = y0 - G::RU + uy;
+                        const bool rowok = r0 + i < nr && y >= 0 && y < H;
+    #pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int xb = 32 - G::RU + c * 64 + lane;
+                            const int x = x0 - 32 + xb;
+                            need[i][c] = false;
+                            pred[i][c] = false;
+                            phv[i][c] = 0.f;
+                            gmv[i][c] = 0.f;
+                            pixv[i][c] = 0;
+                            if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
+                                const int p = c * 64 + lane + 1;
+                                const float *cc = s_phi + (uy + 1) * G::PS + p;
+                                float gx, gy;
+                                if (x == 0)
+                                    gx = cc[1] - cc[0];
+                                else if (x == W - 1)
+                                    gx = cc[0] - cc[-1];
+                                else
+                                    gx = 0.5f * (cc[1] - cc[-1]);
+                                if (y == 0)
+                                    gy = cc[G::PS] - cc[0];
+                                else if (y == H - 1)
+                                    gy = cc[0] - cc[-G::PS];
+                                else
+                                    gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
+                                phv[i][c] = cc[0];
+                                pred[i][c] = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                                if (!(gx == 0.f && gy == 0.f)) {
+                                    need[i][c] = true;
+                                    gmv[i][c] = sqrtf(gx * gx + gy * gy);
+                                    pixv[i][c] = y * W + x;
+                                }
+                            }
+                        }
+                    }
+                    float coef[kCG][2];
+                    {
+                        Px<NV> v[kCG][2];
+    #pragma unroll
+                        for (int i = 0; i < kCG; ++i)
+    #pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
+    #pragma unroll
+                        for (int i = 0; i < kCG; ++i)
+    #pragma unroll
+                            for (int c = 0; c < 2; ++c) {
+                                if constexpr (EDGE)
+                                    coef[i][c] = A.dt * v[i][c].v[0];
+                                else
+                                    coef[i][c] = w * region_D<NB>(v[i][c], a, m);
+                            }
+                    }
+    #pragma unroll
+                    for (int i = 0; i < kCG; ++i) {
+                        if (r0 + i >= nr) break;
+                        const int uy = u0 + r0 + i;
+                        const int y = y0 - G::RU + uy;
+                        const bool rowok = y >= 0 && y < H;
+    #pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
+                        const unsigned long long m0 = __ballot(pred[i][0]);
+                        const unsigned long long m1 = __ballot(pred[i][1]);
+                        if (lane < kFWords) {
+                            const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
+                            s_bn[uy * kFWords + lane] = word;
+                            const int gw = (x0 >> 5) - 1 + lane;
+                            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                                const int xs = gw * 32;
+                                const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                                const uint32_t nw = word & valid;
+                                const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
+                                A.bits_out[(size_t)y * A.WW + gw] = nw;
+                                flips += __popc(nw ^ ow);
+                            }
+                        }
+                    }
                 }
             }
-        }
-        __syncthreads();
-
-        float acc[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = 0.f;
-        int cnt = 0;
-        if constexpr (!EDGE) {
-            // D: statistics of phi^{n+1} = G * b^n for the next iteration.
-            code_rows_owned<R>(s_bn, G::UH, s_codes);
             __syncthreads();
-            stats_fast<R, NB, ST>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, H, W, border, false,
-                                  lut, kk, cum, acc, cnt);
+
+            float acc[NB];
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+            int cnt = 0;
+            if constexpr (!EDGE) {
+                // D: statistics of phi^{n+1} = G * b^n for the next iteration.
+                code_rows_owned<R>(s_bn, G::UH, s_codes);
+                __syncthreads();
+                stats_fast<R, NB, ST>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, H, W, border, false,
+                                      lut, kk, cum, acc, cnt);
+            }
+            TileSmem rs;
+            rs.red = red;
+            reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][blockIdx.x % kBins], A.fix, !EDGE);
         }
-        TileSmem rs;
-        rs.red = red;
-        reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][blockIdx.x % kBins], A.fix, !EDGE);
     }
     if (lead_block) {
         // Clear the slot of iteration n + 2 (nobody reads or writes it now).
@@ -833,6 +870,47 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
             }
             st->last_M = M;
         }
+    }
+}
+
+// Region sums of each step tile in the all-inside case, through the step
+// kernel's own statistics code and reduction (stats_fast with every pixel on
+// the + side, block_reduce), converted to fixed point as the step would.
+template <int R, int NB, typename ST>
+__global__ __launch_bounds__(kThreads) void tile_sums_kernel(const ImgArgs *__restrict__ args,
+                                                             TileSum *__restrict__ out) {
+    extern __shared__ float smem[];
+    __shared__ float red[kThreads / 64 * 8];
+    using G = FastGeom<R, false>;
+    const ImgArgs &E = args[0];
+    const int t = blockIdx.x;
+    const int ntx = (E.W + kFX - 1) / kFX;
+    const int x0 = (t % ntx) * kFX, y0 = (t / ntx) * kFY;
+    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > E.W;
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
+    for (int i = threadIdx.x; i < G::UH * kFWords; i += kThreads) s_bn[i] = ~0u;
+    int lut[G::NCH];
+    load_luts<G::NCH>(E.taps, lut);
+    float kk[2 * R + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * R + 1; ++i) kk[i] = E.taps->k[i];
+    __syncthreads();
+    float acc[NB];
+    int cnt;
+    stats_fast<R, NB, ST>(s_bn, nullptr, static_cast<const ST *>(E.img), x0, y0, E.H, E.W, border, true, lut, kk,
+                          E.taps->cum, acc, cnt);
+    TileSmem rs;
+    rs.red = red;
+    float S[NB];
+    int C, F;
+    block_reduce<NB>(rs, acc, cnt, 0, true, S, C, F);
+    if (threadIdx.x == 0) {
+        TileSum v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v.sum[b] = b < NB ? __float2ll_rn(S[b] * E.fix) : 0;
+        v.cnt = C;
+        v.pad[0] = v.pad[1] = v.pad[2] = 0;
+        out[t] = v;
     }
 }
 
@@ -1362,6 +1440,36 @@ hipError_t Store<ST>::plane_stats(const StepArgs &a, const void *plane, int NB, 
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int R, int NB, typename ST>
+static hipError_t launch_tile_sums_t(const ImgArgs *args, int tiles, TileSum *out, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, false>::UH * kFWords * 4;
+    hipLaunchKernelGGL((tile_sums_kernel<R, NB, ST>), dim3((unsigned)tiles), dim3(kThreads), sm, s, args, out);
+    return hipGetLastError();
+}
+
+template <int R, typename ST>
+static hipError_t launch_tile_sums_r(const ImgArgs *args, int tiles, int NB, TileSum *out, hipStream_t s) {
+    switch (NB) {
+        case 1: return launch_tile_sums_t<R, 1, ST>(args, tiles, out, s);
+        case 2: return launch_tile_sums_t<R, 2, ST>(args, tiles, out, s);
+        case 4: return launch_tile_sums_t<R, 4, ST>(args, tiles, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename ST>
+hipError_t Store<ST>::tile_sums(const ImgArgs *args, int tiles, int r, int NB, TileSum *out, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    switch (r) {
+        case 3: return launch_tile_sums_r<3, ST>(args, tiles, NB, out, s);
+        case 4: return launch_tile_sums_r<4, ST>(args, tiles, NB, out, s);
+        case 5: return launch_tile_sums_r<5, ST>(args, tiles, NB, out, s);
+        case 6: return launch_tile_sums_r<6, ST>(args, tiles, NB, out, s);
+        case 7: return launch_tile_sums_r<7, ST>(args, tiles, NB, out, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename ST>

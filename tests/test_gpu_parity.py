@@ -221,27 +221,49 @@ def test_large_multiband_one_step_parity(dev, term):
         np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6)
 
 
+def _quiet_inside_tiles(bits_prev, r, fx=96, fy=64):
+    """Pixels of the step kernel's quiet all-inside tiles: 96 x 64 tiles away
+    from the border whose previous binary state is all ones over every bit
+    the tile reads (rows y0 - 2r - 1 ..  + 64 + 4r + 2, columns
+    x0 - 1 - 2r .. x0 + 97 + 2r); their region sums come from init."""
+    h, w = bits_prev.shape
+    out = np.zeros((h, w), bool)
+    for y0 in range(0, h, fy):
+        for x0 in range(0, w, fx):
+            by0, nr = y0 - 2 * r - 1, fy + 4 * r + 2
+            if x0 - 2 * r - 2 < 0 or x0 + fx + 2 * r + 2 > w or by0 < 0 or by0 + nr > h:
+                continue
+            if bits_prev[by0:by0 + nr, x0 - 1 - 2 * r:x0 + fx + 1 + 2 * r].all():
+                out[y0:y0 + fy, x0:x0 + fx] = True
+    return out
+
+
 def test_profile_counts_needed_pixels(dev):
     """The algorithmic-bytes count used for roofline figures: per step, the
-    pixels on the + side of the new LSF (read for the region sums) or with
-    |grad phi| != 0 (read for the update), recomputed here from the exported
-    LSFs."""
+    pixels on the + side of the new LSF (read for the region sums) except in
+    quiet all-inside tiles, or with |grad phi| != 0 (read for the update),
+    recomputed here from the exported LSFs and masks."""
     from paper_1409_7474_amd import lse
-    sc = synth.scene_multiband(9, size=200, bands=4, n_roofs=6, n_roads=1)
+    sc = synth.scene_multiband(9, size=500, bands=4, n_roofs=6, n_roads=1, height=400, width=500)
     img, _ = _as_gpu(sc.image, dev)
     for term, mask in (("region", sc.init_region), ("edge", sc.init_edge)):
         job = _make(dev, img, mask, term=term, sigma=1.5, ksize=11)
         job.run(2)
         job.profile(lse.PROFILE_COUNT)
-        expect = 0
+        expect, quiet_px = 0, 0
         for _ in range(3):
             phi_n = job.lsf().cpu().double().numpy()
+            b_prev = job.mask().cpu().numpy().astype(bool)
             job.step()
             phi_n1 = job.lsf().cpu().double().numpy()
             gx, gy = oracle.gradient(phi_n)
             need = (gx != 0) | (gy != 0)
             if term == "region":
-                need |= phi_n1 >= 0
+                q = _quiet_inside_tiles(b_prev, 5)
+                quiet_px += int(q.sum())
+                need |= (phi_n1 >= 0) & ~q
             expect += int(need.sum())
         p = job.profile_read()
         assert p["counted_steps"] == 3 and p["needed_pixels"] == expect, (term, p, expect)
+        if term == "region":
+            assert quiet_px > 0  # the case is exercised

@@ -520,7 +520,10 @@ struct FastGeom {
     static constexpr int SEGD = kFY / 2;         // statistics rows per wave
     static constexpr int NCH = (TS + 5) / 6;     // lookup chunks
     static constexpr int PS = PW;                // phi row stride (floats)
-    static constexpr int smem_words = BH * kFWords + PHP * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
+    // phi is stored for its PH rows only (the segment loop computes up to
+    // PHP rows; the extra ones are not kept), which keeps the step kernel
+    // within a quarter of the CU's LDS for the common radii.
+    static constexpr int smem_words = BH * kFWords + PH * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
 };
 
 template <int NCH>

@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
     float *s_phi = smem + G::BH * kFWords;
-    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PHP * G::PS);
+    uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PH * G::PS);
     int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);    // [max(BH, UH)][2]
     int *s_pcode = s_codes + G::BH * 2;                                  // [PHP][2]: phi row uniformity
     uint32_t *s_const = reinterpret_cast<uint32_t *>(s_pcode + G::PHP * 2);  // all-ones / all-zeros rows
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                             const uint32_t wd = s_bits[(q + R) * kFWords + (xb >> 5)];
                             v = ((wd >> (xb & 31)) & 1u) ? 1.f : -1.f;
                         }
-                        if (p < G::PW) s_phi[q * G::PS + p] = v;
+                        if (p < G::PW && q < G::PH) s_phi[q * G::PS + p] = v;
                         if (lane == 0) s_pcode[q * 2 + chunk] = 2;
                     }
                 } else {
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     #pragma unroll
                             for (int j = 0; j < kSB; ++j) {
                                 const int q = rb + j;
-                                if (p < G::PW) s_phi[q * G::PS + p] = colok ? v : 0.f;
+                                if (p < G::PW && q < G::PH) s_phi[q * G::PS + p] = colok ? v : 0.f;
                             }
                             if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
                             have_win = false;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     #pragma unroll
                             for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
                             const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
-                            if (p < G::PW) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
+                            if (p < G::PW && q < G::PH) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
                         }
                         if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
     #pragma unroll

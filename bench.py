@@ -79,14 +79,25 @@ def calibrate_copy(mib):
                       "launches": 3}), flush=True)
 
 
+def kernel_source_digest():
+    """SHA-256 over the HIP sources of the library (kernels and their headers),
+    in name order: profiler figures apply only to the code they were taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1409_7474_amd", "csrc", "*"))):
+        if path.endswith((".hip", ".h")):
+            h.update(os.path.basename(path).encode())
+            h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel_name):
     """HBM bytes per launch of `kernel_name` from a committed rocprofv3
     summary (profiles/*.md, FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel
     calibration), only if it was taken on the current kernel source."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_1409_7474_amd", "csrc", "lse_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         text = open(path).read()
         for block in text.split("```json")[1:]:

@@ -121,7 +121,7 @@ lse_status validate(const lse_params *p) {
 }
 
 struct Layout {
-    size_t state, taps, args, img, boxes, tilesum, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
+    size_t state, taps, args, img, boxes, tilesum, sched, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
 };
 
 bool dense_mode(const lse_params *p) { return !(p->order == LSE_ORDER_TABLE1 && p->reinit_every == 1); }
@@ -150,6 +150,11 @@ Layout layout_of(const lse_params *p) {
     if (p->term != LSE_TERM_EDGE && !dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
         L.tilesum = o;
         o = align_up(o + (size_t)step_tiles(p->height, p->width) * sizeof(TileSum));
+    }
+    L.sched = 0;
+    if (!dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
+        L.sched = o;
+        o = align_up(o + 3 * (((size_t)step_tiles(p->height, p->width) + 31) / 32) * 4);
     }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
@@ -440,6 +445,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.n0 = 0;
         A.mgroups = (c->region && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
         A.tilesum = L.tilesum ? reinterpret_cast<const TileSum *>(base + L.tilesum) : nullptr;
+        A.sched_mask = L.sched ? reinterpret_cast<uint32_t *>(base + L.sched) : nullptr;
     }
 
     hipStream_t st = as_stream(stream);
@@ -447,6 +453,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     hipError_t e = hipMemcpyAsync(c->taps, &c->host_taps, sizeof(Taps), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dargs, &c->host_args, sizeof(ImgArgs), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_init_state(c->st, 1, st);
+    if (e == hipSuccess) e = launch_sched_reset(&c->host_args, st);
     if (e == hipSuccess) {
         if (c->region) {
             e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st, c->fix,
@@ -509,6 +516,7 @@ lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, v
     if (!c || !mask_dev) return LSE_ERR_INVALID_ARG;
     const hipStream_t s = as_stream(stream);
     hipError_t e = launch_reset_state(c->st, smoothed ? 0 : 1, s);
+    if (e == hipSuccess) e = launch_sched_reset(&c->host_args, s);
     if (e == hipSuccess) e = launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
     c->n = 0;
     c->raw_next = smoothed ? 0 : 1;

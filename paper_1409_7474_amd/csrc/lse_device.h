@@ -748,6 +748,63 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
+// Tile of workgroup j in heavy-first order, computed by one wave: the j-th
+// tile whose bit is set in `mask` (the tiles that were heavy, not quiet, in
+// the previous iteration), then, for j >= H = number of set bits, the
+// (j - H)-th tile whose bit is clear.  Long tiles thus start first and spread
+// over the XCDs.  Returns -1 for j >= ntiles.
+__device__ __forceinline__ int heavy_first_tile(const uint32_t *__restrict__ mask, int ntiles, int j) {
+    const int lane = (int)threadIdx.x & 63;
+    if (j >= ntiles) return -1;
+    const int nw = (ntiles + 31) >> 5;
+    const int per = (nw + 63) >> 6;  // words per lane
+    const int w0 = lane * per;
+    int ones = 0, tiles = 0;
+    for (int i = 0; i < per; ++i) {
+        const int w = w0 + i;
+        if (w < nw) {
+            const int valid = min(32, ntiles - 32 * w);
+            ones += __popc(mask[w] & (valid >= 32 ? ~0u : ((1u << valid) - 1u)));
+            tiles += valid;
+        }
+    }
+    int inc1 = ones, inc0 = tiles - ones;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v1 = __shfl_up(inc1, d, 64), v0 = __shfl_up(inc0, d, 64);
+        if (lane >= d) {
+            inc1 += v1;
+            inc0 += v0;
+        }
+    }
+    const int H = __shfl(inc1, 63, 64);
+    const bool heavy = j < H;
+    const int r = heavy ? j : j - H;
+    const int lo = heavy ? inc1 - ones : inc0 - (tiles - ones);
+    const int hi = heavy ? inc1 : inc0;
+    const unsigned long long owner = __ballot(lo <= r && r < hi);
+    const int src = __ffsll((long long)owner) - 1;
+    int t = -1;
+    if (lane == src) {
+        int left = r - lo;
+        for (int i = 0; i < per && t < 0; ++i) {
+            const int w = w0 + i;
+            const int valid = min(32, ntiles - 32 * w);
+            const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+            const uint32_t bits = (heavy ? mask[w] : ~mask[w]) & vm;
+            const int c = __popc(bits);
+            if (left < c) {
+                uint32_t b = bits;
+                for (int q = 0; q < left; ++q) b &= b - 1u;  // drop the lowest set bits
+                t = 32 * w + (__ffs((int)b) - 1);
+            } else {
+                left -= c;
+            }
+        }
+    }
+    return __shfl(t, src < 0 ? 0 : src, 64);
+}
+
 // ---------------------------------------------------------------- launchers
 
 // Workgroups may use more than 64 KB of LDS (gfx950 has 160 KB per CU) for

@@ -125,7 +125,8 @@ struct alignas(16) ImgArgs {
     int n0;                   // iteration index of launch k = 0
     int mgroups;              // workgroups of the normaliser pass (B > 1)
     const TileSum *tilesum;   // region term: per-tile sums of the all-inside case
-    long long pad;
+    uint32_t *sched_mask;     // 3 x ceil(tiles / 32) words: tiles that were heavy (not quiet), by
+                              // iteration n % 3 (fast path)
 };
 
 constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare workgroup
@@ -191,6 +192,7 @@ hipError_t launch_plane_out(const void *p0, const void *p1, const DevState *st, 
 hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                         int NB, int storage, hipStream_t s);
 hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s);
+hipError_t launch_sched_reset(const ImgArgs *host_args, hipStream_t s);
 hipError_t launch_tile_sums(const ImgArgs *args, int tiles, int r, int NB, int storage, TileSum *out, hipStream_t s);
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W,
                            int WW, hipStream_t s);

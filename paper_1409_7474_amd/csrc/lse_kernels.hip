@@ -287,6 +287,21 @@ __global__ void reset_profile_kernel(DevState *st) {
 }
 
 
+// Schedule masks: no tile recorded as heavy (the first iteration takes the
+// tiles in order).
+__global__ void sched_reset_kernel(uint32_t *mask, int nwords) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) mask[i] = 0u;
+}
+
+hipError_t launch_sched_reset(const ImgArgs *a, hipStream_t s) {
+    if (!a->sched_mask) return hipSuccess;
+    const int nwords = 3 * ((a->tiles + 31) >> 5);
+    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s, a->sched_mask,
+                       nwords);
+    return hipGetLastError();
+}
+
 // Batch: freeze each image's iteration count as the index of launch k = 0.
 __global__ void batch_prepare_kernel(ImgArgs *args, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

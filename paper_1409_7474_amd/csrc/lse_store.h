@@ -490,12 +490,22 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     extern __shared__ float smem[];
     __shared__ Totals tot;
     __shared__ float red[kThreads / 64 * 8];
+    __shared__ int s_tile;
     int ii, t;
     if (!batch_unit(map, unit_bits, ii, t)) return;
     const ImgArgs &E = args[ii];
-    if (!map) t = tile_of(E.tiles);
+    // Single image: heavy-first order from the previous iteration's record.
+    const bool dyn = map == nullptr && E.sched_mask != nullptr;
+    if (!map && !dyn) t = tile_of(E.tiles);
     const int n = E.n0 + k;
-    if (t < 0 || n >= E.target) return;
+    if (n >= E.target) return;
+    if (dyn ? (int)blockIdx.x >= E.tiles : t < 0) return;
+    const int nw = (E.tiles + 31) >> 5;                  // words of one schedule mask
+    const int sbn = (n + 1) % 3, sbr = (n + 2) % 3;     // masks written / cleared by this iteration
+    if (dyn && (threadIdx.x >> 6) == 3) {
+        const int tt = heavy_first_tile(E.sched_mask + (size_t)(n % 3) * nw, E.tiles, (int)blockIdx.x);
+        if ((threadIdx.x & 63) == 0) s_tile = tt;
+    }
     StepArgs A;
     A.img = E.img;
     A.bits_in = E.bits[n & 1];
@@ -513,15 +523,20 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     A.hw = E.hw;
     DevState *st = A.st;
     const int sl = A.n % 3;
-    const bool lead_block = t == 0;
-    const bool lead = lead_block && threadIdx.x == 0;
     const int H = A.H, W = A.W;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ntx = (W + kFX - 1) / kFX;
-    const int x0 = (t >= 0 ? t % ntx : 0) * kFX, y0 = (t >= 0 ? t / ntx : 0) * kFY;
-    const int by0 = y0 - G::RU - 1 - R;  // image row of staged bit row 0
-    const int px0 = x0 - G::RU - 1, py0 = y0 - G::RU - 1;
-    const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
+    int x0 = 0, y0 = 0, by0 = 0, px0 = 0, py0 = 0;
+    bool border = true;
+    auto set_tile = [&](int tt) {
+        x0 = (tt % ntx) * kFX;
+        y0 = (tt / ntx) * kFY;
+        by0 = y0 - G::RU - 1 - R;  // image row of staged bit row 0
+        px0 = x0 - G::RU - 1;
+        py0 = y0 - G::RU - 1;
+        border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
+    };
+    if (!dyn) set_tile(t);
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
     float *s_phi = smem + G::BH * kFWords;
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PH * G::PS);
@@ -530,8 +545,9 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     uint32_t *s_const = reinterpret_cast<uint32_t *>(s_pcode + G::PHP * 2);  // all-ones / all-zeros rows
 
     // A: b^{n-1} on the tile + 2R+1 halo.  Issued before the statistics
-    // loads so that the two memory round trips overlap.
-    if (t >= 0) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    // loads so that the two memory round trips overlap (batch; a single
+    // image learns its tile together with the statistics).
+    if (!dyn) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
     if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
     // Tables do not depend on the statistics either: load them before the
     // statistics barrier (one memory round trip for the whole set-up).
@@ -546,11 +562,19 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
         int done = tot.done | tot.bad;
         if (!done && A.stop && tot.flips == 0) done = 1;
         if (done) {
-            if (lead && !tot.bad) st->done = 1;
+            if ((dyn ? blockIdx.x == 0 : t == 0) && threadIdx.x == 0 && !tot.bad) st->done = 1;
             return;
         }
     }
     const bool raw = tot.raw && n == 0;
+    if (dyn) {
+        t = s_tile;
+        set_tile(t);
+        stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+        __syncthreads();
+    }
+    const bool lead_block = t == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
 
     float a[NB], m[NB], w = 0.f;
     float cp[NB], cm[NB], M = 0.f;
@@ -588,7 +612,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     // U-row words of an all-ones binarised row (the two ballots' valid lanes).
     const unsigned long long ones1 = (32 + 2 * G::RU >= 64) ? ~0ull : ((1ull << (32 + 2 * G::RU)) - 1ull);
 
-    if (t >= 0) {
+    {
         // Codes of the staged rows over each chunk's window span.
         for (int i = tid; i < G::BH * 2; i += kThreads) {
             const int row = i >> 1, c = i & 1;
@@ -616,6 +640,9 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
             all0 = __syncthreads_and(all0);
             quiet = all1 ? 1 : (all0 ? 0 : -1);
         }
+        // Record heavy tiles for the next iteration's order.
+        if (tid == 0 && quiet < 0 && E.sched_mask)
+            atomicOr(&E.sched_mask[(size_t)sbn * nw + (t >> 5)], 1u << (t & 31));
         if (quiet >= 0) {
             if (tid < kFY * 3) {
                 const int row = tid / 3, k = tid - row * 3;
@@ -857,9 +884,12 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
         }
     }
     if (lead_block) {
-        // Clear the slot of iteration n + 2 (nobody reads or writes it now).
+        // Clear the slot of iteration n + 2 and the schedule mask that
+        // iteration n + 1 will fill (nobody reads or writes them now).
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
+        if (E.sched_mask)
+            for (int i = threadIdx.x; i < nw; i += kThreads) E.sched_mask[(size_t)sbr * nw + i] = 0u;
     }
     if (lead) {
         st->iters += 1;

@@ -149,12 +149,12 @@ Layout layout_of(const lse_params *p) {
     L.tilesum = 0;
     if (p->term != LSE_TERM_EDGE && !dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
         L.tilesum = o;
-        o = align_up(o + (size_t)step_tiles(p->height, p->width) * sizeof(TileSum));
+        o = align_up(o + (size_t)step_tiles(p->height, p->width, 0) * sizeof(TileSum));
     }
     L.sched = 0;
     if (!dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
         L.sched = o;
-        o = align_up(o + 3 * (((size_t)step_tiles(p->height, p->width) + 31) / 32) * 4);
+        o = align_up(o + 3 * (((size_t)step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE) + 31) / 32) * 4);
     }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
@@ -436,7 +436,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.H = p->height;
         A.W = p->width;
         A.WW = c->WW;
-        A.tiles = step_tiles(p->height, p->width);
+        A.tiles = step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE);
         A.dt = p->dt;
         A.fix = c->fix;
         A.inv_fix = c->inv_fix;

@@ -500,7 +500,8 @@ __device__ __forceinline__ unsigned long long mkey_of(float absd, unsigned int p
 // per chunk and are read with ds_bpermute (a crossbar, no bank conflicts).
 
 constexpr int kFX = 96;        // owned columns (3 bit words)
-constexpr int kFY = 64;        // owned rows
+constexpr int kFYRegion = 48;  // owned rows, region term (the front tiles are the critical path)
+constexpr int kFYEdge = 64;    // owned rows, edge term
 constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 - 1 .. x0/32 + 4
 
 constexpr int kSB = 8;         // rows per block of the rolling vertical window
@@ -510,14 +511,15 @@ template <int R, bool EDGE>
 struct FastGeom {
     static constexpr int TS = 2 * R + 1;
     static constexpr int RU = EDGE ? 0 : R;      // halo of the binarised field
-    static constexpr int UH = kFY + 2 * RU;      // rows where b^n is computed
+    static constexpr int FY = EDGE ? kFYEdge : kFYRegion;  // owned rows
+    static constexpr int UH = FY + 2 * RU;       // rows where b^n is computed
     static constexpr int PH = UH + 2;            // rows of phi^n
     static constexpr int PW = kFX + 2 * RU + 2;  // columns of phi^n (<= 128)
     static constexpr int NBLK = (PH + 2 * kSB - 1) / (2 * kSB);  // window blocks per segment
     static constexpr int SEG = NBLK * kSB;       // phi rows per wave (2 segments x 2 chunks)
     static constexpr int PHP = 2 * SEG;          // phi rows allocated (>= PH)
     static constexpr int BH = PHP + 2 * R;       // staged rows of b^{n-1}
-    static constexpr int SEGD = kFY / 2;         // statistics rows per wave
+    static constexpr int SEGD = FY / 2;          // statistics rows per wave
     static constexpr int NCH = (TS + 5) / 6;     // lookup chunks
     static constexpr int PS = PW;                // phi row stride (floats)
     // phi is stored for its PH rows only (the segment loop computes up to
@@ -621,8 +623,8 @@ __device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, i
     }
 }
 
-// Statistics of phi^{n+1} = G * b on the owned 96 x 64 tile (b in `bn`, rows
-// y0 - R .. y0 + 64 + R, bit 0 of each row = column x0 - 32).  raw: phi = b.
+// Statistics of phi^{n+1} = G * b on the owned 96 x FY tile (b in `bn`, rows
+// y0 - R .. y0 + FY + R, bit 0 of each row = column x0 - 32).  raw: phi = b.
 // Every owned pixel of the image is read once (dense streaming); blocks of
 // 8 rows whose whole bit window is uniform take the sign without the
 // Gaussian sums (their value would be the same constant in every pixel).

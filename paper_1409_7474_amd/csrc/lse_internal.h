@@ -162,7 +162,7 @@ struct Store {
 // error; `storage` is an lse_dtype.
 size_t tile_smem_bytes(int r, int nch, int edge);
 bool fast_radius(int r);                 // the step kernel has a compiled variant for radius r
-int step_tiles(int H, int W);            // workgroup tiles of the step kernel for an H x W image
+int step_tiles(int H, int W, int edge);  // workgroup tiles of the step kernel for an H x W image
 int mpass_groups(int H, int W);          // workgroups of the normaliser pass
 hipError_t launch_init_state(DevState *st, int raw, hipStream_t s);
 hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);

@@ -11,7 +11,7 @@
 // the taps with FMAs.  Zero padding at the image border is exact: taps that
 // fall outside are forced to +1 and their weight subtracted.
 //
-// One iteration of the region term is one fused kernel per 96 x 64 tile
+// One iteration of the region term is one fused kernel per 96 x 48 tile
 // (lse_store.h; plus, for B > 1, a read-only pass for the normaliser of
 // eq. (17)):
 //   A. stage b^{n-1} on the tile plus a halo of 2r+1 in LDS;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void lsf_out_kernel(StepArgs A, const uin
 __global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int raw, int edge, int fast_quiet) {
     extern __shared__ float smem[];
     __shared__ int part[kThreads / 64];
-    __shared__ int quiet1[2];
+    __shared__ int quiet1[4];
     if (A.st->done || A.st->bad) return;  // the step did not run
     const int r = A.r, ts = A.ts, nch = A.nch, H = A.H, W = A.W;
     const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
@@ -225,16 +225,18 @@ __global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int 
         __syncthreads();
     }
     // The step kernel takes the region sums of a quiet all-inside tile (its
-    // 96 x 64 tiling, b^{n-1} uniform over the tile's whole bit window, away
-    // from the image border) from the sums stored at init: such pixels need
-    // no image read for the statistics.
-    for (int q = 0; q < 2; ++q) {
-        const int fx = x0 / kFX + q, fy = y0 / kFY;
-        const int X0 = fx * kFX, Y0 = fy * kFY;
-        const int BY0 = Y0 - 2 * r - 1, NR = kFY + 4 * r + 2;
+    // 96 x kFYRegion tiling, b^{n-1} uniform over the tile's whole bit
+    // window, away from the image border) from the sums stored at init: such
+    // pixels need no image read for the statistics.  This 64 x 32 tile meets
+    // at most 2 x 2 of those tiles.
+    const int fx0 = x0 / kFX, fy0 = y0 / kFYRegion;
+    for (int q = 0; q < 4; ++q) {
+        const int fx = fx0 + (q & 1), fy = fy0 + (q >> 1);
+        const int X0 = fx * kFX, Y0 = fy * kFYRegion;
+        const int BY0 = Y0 - 2 * r - 1, NR = kFYRegion + 4 * r + 2;
         int ones = 0;
-        if (fast_quiet && !edge && X0 < W && !(X0 - 2 * r - 2 < 0 || X0 + kFX + 2 * r + 2 > W) && BY0 >= 0 &&
-            BY0 + NR <= H) {
+        if (fast_quiet && !edge && X0 < W && Y0 < H && !(X0 - 2 * r - 2 < 0 || X0 + kFX + 2 * r + 2 > W) &&
+            BY0 >= 0 && BY0 + NR <= H) {
             const int c0 = X0 - 1 - 2 * r, c1 = X0 + kFX + 1 + 2 * r;  // bit columns [c0, c1)
             const int w0 = c0 >> 5, w1 = (c1 - 1) >> 5, nw = w1 - w0 + 1;
             int all1 = 1;
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void count_needed_kernel(StepArgs A, int 
         else if (y == H - 1) gy = c[0] - c[-PWc];
         else gy = 0.5f * (c[PWc] - c[-PWc]);
         bool need = !(gx == 0.f && gy == 0.f);
-        if (!edge && !quiet1[x / kFX - x0 / kFX])
+        if (!edge && !quiet1[(x / kFX - fx0) + 2 * (y / kFYRegion - fy0)])
             need = need || vconv(h + oy * kTileX + ox, kTileX, k, ts) >= 0.f;
         cnt += need ? 1 : 0;
     }
@@ -339,7 +341,10 @@ size_t tile_smem_bytes(int r, int nch, int edge) { return tile_smem_words(r, nch
 
 bool fast_radius(int r) { return r >= 3 && r <= 7; }
 
-int step_tiles(int H, int W) { return ((W + kFX - 1) / kFX) * ((H + kFY - 1) / kFY); }
+int step_tiles(int H, int W, int edge) {
+    const int fy = edge ? kFYEdge : kFYRegion;
+    return ((W + kFX - 1) / kFX) * ((H + fy - 1) / fy);
+}
 
 int mpass_groups(int H, int W) {
     const int nblk = ((W + kMBX - 1) / kMBX) * ((H + kMBY - 1) / kMBY);

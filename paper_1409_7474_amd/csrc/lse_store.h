@@ -478,7 +478,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
 }
 
 // One iteration (Table I steps 2-4, plus the statistics of step 2.1 for the
-// next iteration) on one 96 x 64 tile of one image.  Launch k runs iteration
+// next iteration) on one 96 x FY tile of one image (FY = 48 rows for the
+// region term, 64 for the edge term).  Launch k runs iteration
 // n = n0 + k of every image it covers (one image when map is null; else the
 // workgroup map names image and tile).
 template <int R, int NB, bool EDGE, typename ST>
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     bool border = true;
     auto set_tile = [&](int tt) {
         x0 = (tt % ntx) * kFX;
-        y0 = (tt / ntx) * kFY;
+        y0 = (tt / ntx) * G::FY;
         by0 = y0 - G::RU - 1 - R;  // image row of staged bit row 0
         px0 = x0 - G::RU - 1;
         py0 = y0 - G::RU - 1;
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
         if (tid == 0 && quiet < 0 && E.sched_mask)
             atomicOr(&E.sched_mask[(size_t)sbn * nw + (t >> 5)], 1u << (t & 31));
         if (quiet >= 0) {
-            if (tid < kFY * 3) {
+            if (tid < G::FY * 3) {
                 const int row = tid / 3, k = tid - row * 3;
                 A.bits_out[(size_t)(y0 + row) * A.WW + (x0 >> 5) + k] = quiet ? ~0u : 0u;
             }
@@ -761,7 +762,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                                                  : 0u;
                         s_bn[uy * kFWords + k] = word;
                         const int gw = (x0 >> 5) - 1 + k;
-                        if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + kFY && y < H && gw < A.WW) {
+                        if (k >= 1 && k <= 3 && uy >= G::RU && uy < G::RU + G::FY && y < H && gw < A.WW) {
                             const int xs = gw * 32;
                             const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
                             const uint32_t nw = word & valid;
@@ -853,7 +854,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                             const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
                             s_bn[uy * kFWords + lane] = word;
                             const int gw = (x0 >> 5) - 1 + lane;
-                            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + kFY && rowok && gw < A.WW) {
+                            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + G::FY && rowok && gw < A.WW) {
                                 const int xs = gw * 32;
                                 const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
                                 const uint32_t nw = word & valid;
@@ -915,7 +916,7 @@ __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const ImgArgs *__re
     const ImgArgs &E = args[0];
     const int t = blockIdx.x;
     const int ntx = (E.W + kFX - 1) / kFX;
-    const int x0 = (t % ntx) * kFX, y0 = (t / ntx) * kFY;
+    const int x0 = (t % ntx) * kFX, y0 = (t / ntx) * G::FY;
     const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > E.W;
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
     for (int i = threadIdx.x; i < G::UH * kFWords; i += kThreads) s_bn[i] = ~0u;
@@ -952,7 +953,7 @@ __global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int ra
     __shared__ float red[kThreads / 64 * 8];
     using G = FastGeom<R, false>;
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
-    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * kFY;
+    const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * G::FY;
     const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > A.W;
     int lut[G::NCH];
     load_luts<G::NCH>(A.taps, lut);
@@ -1292,7 +1293,7 @@ static hipError_t launch_step_fast_r(const ImgArgs *args, const uint32_t *map, i
 template <int R, int NB, typename ST>
 static hipError_t launch_stats_fast_t(const StepArgs &a, int raw, int slot, hipStream_t s) {
     const size_t sm = (size_t)FastGeom<R, false>::UH * (kFWords + 2) * 4;
-    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFY - 1) / kFY);
+    const dim3 grid((a.W + kFX - 1) / kFX, (a.H + kFYRegion - 1) / kFYRegion);
     hipLaunchKernelGGL((stats_fast_kernel<R, NB, ST>), grid, dim3(kThreads), sm, s, a, raw, slot);
     return hipGetLastError();
 }

@@ -221,10 +221,10 @@ def test_large_multiband_one_step_parity(dev, term):
         np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6)
 
 
-def _quiet_inside_tiles(bits_prev, r, fx=96, fy=64):
-    """Pixels of the step kernel's quiet all-inside tiles: 96 x 64 tiles away
-    from the border whose previous binary state is all ones over every bit
-    the tile reads (rows y0 - 2r - 1 ..  + 64 + 4r + 2, columns
+def _quiet_inside_tiles(bits_prev, r, fx=96, fy=48):
+    """Pixels of the region step kernel's quiet all-inside tiles: 96 x 48
+    tiles away from the border whose previous binary state is all ones over
+    every bit the tile reads (rows y0 - 2r - 1 .. + fy + 4r + 2, columns
     x0 - 1 - 2r .. x0 + 97 + 2r); their region sums come from init."""
     h, w = bits_prev.shape
     out = np.zeros((h, w), bool)

@@ -121,7 +121,8 @@ lse_status validate(const lse_params *p) {
 }
 
 struct Layout {
-    size_t state, taps, args, img, boxes, tilesum, sched, bits0, bits1, plane0, plane1, tmp0, tmp1, total;
+    size_t state, taps, args, img, boxes, tilesum, tilelast, sched, plan, bits0, bits1, plane0, plane1, tmp0, tmp1,
+        total;
 };
 
 bool dense_mode(const lse_params *p) { return !(p->order == LSE_ORDER_TABLE1 && p->reinit_every == 1); }
@@ -146,15 +147,20 @@ Layout layout_of(const lse_params *p) {
         L.boxes = o;
         o = align_up(o + mbox_floats(p->height, p->width, NB) * 4);
     }
-    L.tilesum = 0;
+    L.tilesum = L.tilelast = 0;
     if (p->term != LSE_TERM_EDGE && !dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
         L.tilesum = o;
         o = align_up(o + (size_t)step_tiles(p->height, p->width, 0) * sizeof(TileSum));
+        L.tilelast = o;
+        o = align_up(o + (size_t)step_tiles(p->height, p->width, 0) * sizeof(TileSum));
     }
-    L.sched = 0;
+    L.sched = L.plan = 0;
     if (!dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
+        const size_t tiles = (size_t)step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE);
         L.sched = o;
-        o = align_up(o + 3 * (((size_t)step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE) + 31) / 32) * 4);
+        o = align_up(o + 3 * ((tiles + 31) / 32) * 4);
+        L.plan = o;
+        o = align_up(o + (1 + tiles) * 4);
     }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
@@ -258,6 +264,7 @@ StepArgs step_args(const lse_ctx *c) {
     a.order = c->p.order;
     a.reinit = 1;
     a.phi_binary = 0;
+    a.tilelast = c->host_args.tilelast;
     return a;
 }
 
@@ -277,12 +284,21 @@ void prof_begin(lse_ctx *c, int kind, hipStream_t s, lse_ctx::Ev *ev) {
     *ev = c->pool.back();
     c->pool.pop_back();
     ev->kind = kind;
-    (void)hipEventRecord(ev->a, s);
+    (void)s;
+    launch_timing() = LaunchTiming{ev->a, ev->b};
 }
 
+// The launch between prof_begin and prof_end took the events into its dispatch
+// packet; if it never launched (an error), the pair goes back unused.
 void prof_end(lse_ctx *c, hipStream_t s, lse_ctx::Ev *ev) {
+    (void)s;
     if (!(c->prof & LSE_PROFILE_TIMING) || ev->kind < 0) return;
-    (void)hipEventRecord(ev->b, s);
+    LaunchTiming &t = launch_timing();
+    if (t.start) {
+        t = LaunchTiming{nullptr, nullptr};
+        c->pool.push_back(*ev);
+        return;
+    }
     c->pending.push_back(*ev);
 }
 
@@ -309,7 +325,9 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     if (region && c->NB > 1) {
         lse_ctx::Ev ev{nullptr, nullptr, -1};
         prof_begin(c, 1, s, &ev);
-        e = launch_mpass(c->dargs, nullptr, 0, (unsigned)c->host_args.mgroups, c->n, stop, c->NB, storage, s);
+        // one more workgroup builds the step's visit list (fast path)
+        const unsigned grid = (unsigned)c->host_args.mgroups + (c->host_args.plan && !c->dense ? 1u : 0u);
+        e = launch_mpass(c->dargs, nullptr, 0, grid, c->n, stop, c->NB, storage, s);
         prof_end(c, s, &ev);
         if (e != hipSuccess) return LSE_ERR_DEVICE;
     }
@@ -328,8 +346,10 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
         e = launch_dense_step(a, c->NB, region ? 0 : 1, storage, s);
         next_binary = a.order == LSE_ORDER_LISTING && a.reinit;
     } else if (fast_radius(c->r)) {
-        e = launch_step(c->dargs, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
-                        region ? 0 : 1, storage, s);
+        if (c->host_args.plan && !(region && c->NB > 1)) e = launch_plan(c->dargs, c->n, s);
+        if (e == hipSuccess)
+            e = launch_step(c->dargs, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
+                            region ? 0 : 1, storage, s);
     } else {
         e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
     }
@@ -445,7 +465,12 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.n0 = 0;
         A.mgroups = (c->region && c->NB > 1) ? mpass_groups(p->height, p->width) : 0;
         A.tilesum = L.tilesum ? reinterpret_cast<const TileSum *>(base + L.tilesum) : nullptr;
+        A.tilelast = L.tilelast ? reinterpret_cast<TileSum *>(base + L.tilelast) : nullptr;
         A.sched_mask = L.sched ? reinterpret_cast<uint32_t *>(base + L.sched) : nullptr;
+        // Visit list: built by the normaliser pass when there is one, else
+        // by its own pass for large tile counts.
+        const bool use_plan = (c->region && c->NB > 1) || A.tiles > kPlanMinTiles;
+        A.plan = L.plan && use_plan ? reinterpret_cast<int *>(base + L.plan) : nullptr;
     }
 
     hipStream_t st = as_stream(stream);

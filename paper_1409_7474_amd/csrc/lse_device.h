@@ -464,20 +464,43 @@ __device__ __forceinline__ void block_reduce(const TileSmem &s, float (&acc)[NB]
     }
 }
 
-// Workgroup reduction of (NB sums, count, flips) and one atomic per value.
+// One thread: commit a tile's fixed-point region sums `cur` and count as the
+// change from its previous record `prev` (null: nothing recorded, commit the
+// values), and record them in `rec` (if not null).  Integer arithmetic
+// modulo 2^64, so the totals stay exactly the sum of each tile's latest
+// contribution and tiles that are not revisited keep theirs.
+template <int NB>
+__device__ __forceinline__ void commit_tile(const long long (&cur)[NB], long long cnt, const TileSum *prev,
+                                            TileSum *rec, Bin *out) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const long long d = prev ? cur[b] - prev->sum[b] : cur[b];
+        if (d) atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]), (unsigned long long)d);
+    }
+    const long long dc = prev ? cnt - prev->cnt : cnt;
+    if (dc) atomicAdd(&out->nplus, (unsigned long long)dc);
+    if (rec) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rec->sum[b] = cur[b];
+        rec->cnt = cnt;
+    }
+}
+
+// Workgroup reduction of (NB sums, count, flips) and one atomic per value
+// (sums: as the change from `prev` when given, recorded in `rec`).
 template <int NB>
 __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB], int cnt, int flips, Bin *out,
-                                             float fix, bool with_sums) {
+                                             float fix, bool with_sums, const TileSum *prev = nullptr,
+                                             TileSum *rec = nullptr) {
     float S[NB];
     int C, F;
     block_reduce<NB>(s, acc, cnt, flips, with_sums, S, C, F);
     if (threadIdx.x == 0) {
         if (with_sums) {
+            long long v[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]),
-                          (unsigned long long)__float2ll_rn(S[b] * fix));
-            atomicAdd(&out->nplus, (unsigned long long)C);
+            for (int b = 0; b < NB; ++b) v[b] = __float2ll_rn(S[b] * fix);
+            commit_tile<NB>(v, (long long)C, prev, rec, out);
         }
         if (F) atomicAdd(&out->flips, (unsigned long long)F);
     }
@@ -527,6 +550,14 @@ struct FastGeom {
     // within a quarter of the CU's LDS for the common radii.
     static constexpr int smem_words = BH * kFWords + PH * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
 };
+
+// Whether the staged bits lo .. hi of a fast tile (bit 0 = column x0 - 32)
+// reach outside the image: only then do taps over them need the
+// zero-padding correction, and only otherwise may a uniform window take the
+// constant interior value.
+__device__ __forceinline__ bool span_outside(int x0, int W, int lo, int hi) {
+    return x0 - 32 + lo < 0 || x0 - 32 + hi > W - 1;
+}
 
 template <int NCH>
 __device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, int (&lut)[NCH]) {
@@ -641,6 +672,9 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
     const int ox = chunk * 64 + lane;
     const int x = x0 + ox;
     const bool colok = ox < kFX && x < W;
+    // The window of this chunk's columns (bits of code_rows_owned) reaches
+    // outside the image only next to the left or right edge.
+    border = border && span_outside(x0, W, chunk == 0 ? 32 - R : 96 - R, chunk == 0 ? 96 + R : 128 + R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.f;
     cnt = 0;
@@ -750,40 +784,72 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
-// Tile of workgroup j in heavy-first order, computed by one wave: the j-th
-// tile whose bit is set in `mask` (the tiles that were heavy, not quiet, in
-// the previous iteration), then, for j >= H = number of set bits, the
-// (j - H)-th tile whose bit is clear.  Long tiles thus start first and spread
-// over the XCDs.  Returns -1 for j >= ntiles.
-__device__ __forceinline__ int heavy_first_tile(const uint32_t *__restrict__ mask, int ntiles, int j) {
+// 32 bits of the heavy-tile record starting at tile index `base` (may lie
+// outside [0, ntiles): those bits are zero).
+__device__ __forceinline__ uint32_t heavy_bits(const uint32_t *__restrict__ heavy, int nw, int base) {
+    const int wq = base >> 5, sh = base & 31;  // floor division (arithmetic shift)
+    const uint32_t lo = (wq >= 0 && wq < nw) ? heavy[wq] : 0u;
+    if (sh == 0) return lo;
+    const uint32_t hi = (wq + 1 >= 0 && wq + 1 < nw) ? heavy[wq + 1] : 0u;
+    return (lo >> sh) | (hi << (32 - sh));
+}
+
+// Active tiles of word w: a tile is active when it or one of its eight
+// neighbours (in a grid of ntx tiles per row) was heavy.
+__device__ __forceinline__ uint32_t active_word(const uint32_t *__restrict__ heavy, int nw, int ntx, int w) {
+    const int base = 32 * w;
+    // Tiles of this word in the first / last column of the tile grid.
+    uint32_t first_col = 0u, last_col = 0u;
+    const int c0 = base % ntx;
+    for (int i = (ntx - c0) % ntx; i < 32; i += ntx) first_col |= 1u << i;
+    for (int i = ntx - 1 - c0; i < 32; i += ntx) last_col |= 1u << i;
+    uint32_t a = 0u;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int b = base + dy * ntx;
+        a |= heavy_bits(heavy, nw, b) | (heavy_bits(heavy, nw, b - 1) & ~first_col) |
+             (heavy_bits(heavy, nw, b + 1) & ~last_col);
+    }
+    return a;
+}
+
+// Tile of workgroup j of a single-image launch without a visit list,
+// computed by one wave from the previous iteration's record of heavy tiles
+// (the order of build_plan: heavy tiles, then their other neighbours).
+// Returns -1 for j >= the number of active tiles.  Every workgroup scans the
+// whole record, so this serves small tile counts only.
+__device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ heavy, int ntiles, int ntx, int j) {
     const int lane = (int)threadIdx.x & 63;
     if (j >= ntiles) return -1;
     const int nw = (ntiles + 31) >> 5;
     const int per = (nw + 63) >> 6;  // words per lane
     const int w0 = lane * per;
-    int ones = 0, tiles = 0;
+    int nh = 0, na = 0;              // heavy tiles; other active tiles
     for (int i = 0; i < per; ++i) {
         const int w = w0 + i;
         if (w < nw) {
             const int valid = min(32, ntiles - 32 * w);
-            ones += __popc(mask[w] & (valid >= 32 ? ~0u : ((1u << valid) - 1u)));
-            tiles += valid;
+            const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+            const uint32_t h = heavy[w] & vm;
+            nh += __popc(h);
+            na += __popc(active_word(heavy, nw, ntx, w) & vm & ~h);
         }
     }
-    int inc1 = ones, inc0 = tiles - ones;
+    int inch = nh, inca = na;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int v1 = __shfl_up(inc1, d, 64), v0 = __shfl_up(inc0, d, 64);
+        const int vh = __shfl_up(inch, d, 64), va = __shfl_up(inca, d, 64);
         if (lane >= d) {
-            inc1 += v1;
-            inc0 += v0;
+            inch += vh;
+            inca += va;
         }
     }
-    const int H = __shfl(inc1, 63, 64);
-    const bool heavy = j < H;
-    const int r = heavy ? j : j - H;
-    const int lo = heavy ? inc1 - ones : inc0 - (tiles - ones);
-    const int hi = heavy ? inc1 : inc0;
+    const int NH = __shfl(inch, 63, 64), NA = __shfl(inca, 63, 64);
+    if (j >= NH + NA) return -1;
+    const bool first = j < NH;
+    const int r = first ? j : j - NH;
+    const int lo = first ? inch - nh : inca - na;
+    const int hi = first ? inch : inca;
     const unsigned long long owner = __ballot(lo <= r && r < hi);
     const int src = __ffsll((long long)owner) - 1;
     int t = -1;
@@ -793,7 +859,8 @@ __device__ __forceinline__ int heavy_first_tile(const uint32_t *__restrict__ mas
             const int w = w0 + i;
             const int valid = min(32, ntiles - 32 * w);
             const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-            const uint32_t bits = (heavy ? mask[w] : ~mask[w]) & vm;
+            const uint32_t h = heavy[w] & vm;
+            const uint32_t bits = first ? h : (active_word(heavy, nw, ntx, w) & vm & ~h);
             const int c = __popc(bits);
             if (left < c) {
                 uint32_t b = bits;
@@ -805,6 +872,73 @@ __device__ __forceinline__ int heavy_first_tile(const uint32_t *__restrict__ mas
         }
     }
     return __shfl(t, src < 0 ? 0 : src, 64);
+}
+
+// Visit list of the single-image step of iteration n: the tiles that
+// iteration n - 1 recorded as heavy (not quiet), in index order, then the
+// other tiles within one tile of a heavy one.  Every other tile is settled:
+// it and its neighbours were quiet, so its bit window is still uniform, both
+// bit buffers already hold its value and its region sums are unchanged.
+// All NT threads of one workgroup call it; thread i takes a contiguous run
+// of mask words.  s_tot: 2 x NT / 64 ints of LDS.
+template <int NT>
+__device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
+    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
+    const uint32_t *heavy = E.sched_mask + (size_t)(n % 3) * nw;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (nw + NT - 1) / NT;
+    const int w0 = tid * per;
+    auto word_masks = [&](int w, uint32_t &h, uint32_t &a) {
+        const int valid = min(32, ntiles - 32 * w);
+        const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+        h = heavy[w] & vm;
+        a = active_word(heavy, nw, ntx, w) & vm & ~h;
+    };
+    int nh = 0, na = 0;
+    for (int i = 0; i < per; ++i) {
+        const int w = w0 + i;
+        if (w < nw) {
+            uint32_t h, a;
+            word_masks(w, h, a);
+            nh += __popc(h);
+            na += __popc(a);
+        }
+    }
+    // Exclusive scan over the workgroup: within the wave, then over waves.
+    int ih = nh, ia = na;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int vh = __shfl_up(ih, d, 64), va = __shfl_up(ia, d, 64);
+        if (lane >= d) {
+            ih += vh;
+            ia += va;
+        }
+    }
+    if (lane == 63) {
+        s_tot[wave] = ih;
+        s_tot[NT / 64 + wave] = ia;
+    }
+    __syncthreads();
+    int bh = 0, ba = 0, NH = 0, NA = 0;
+    for (int v = 0; v < NT / 64; ++v) {
+        if (v < wave) {
+            bh += s_tot[v];
+            ba += s_tot[NT / 64 + v];
+        }
+        NH += s_tot[v];
+        NA += s_tot[NT / 64 + v];
+    }
+    int oh = 1 + bh + ih - nh, oa = 1 + NH + ba + ia - na;
+    for (int i = 0; i < per; ++i) {
+        const int w = w0 + i;
+        if (w < nw) {
+            uint32_t h, a;
+            word_masks(w, h, a);
+            for (; h; h &= h - 1u) E.plan[oh++] = 32 * w + (__ffs((int)h) - 1);
+            for (; a; a &= a - 1u) E.plan[oa++] = 32 * w + (__ffs((int)a) - 1);
+        }
+    }
+    if (tid == 0) E.plan[0] = NH + NA;
 }
 
 // ---------------------------------------------------------------- launchers

@@ -1,12 +1,35 @@
 // Internal declarations shared by the HIP kernels and the C ABI layer.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/lse.h"
 
 namespace lse {
+
+// Kernel timing for lse_profile: when armed, the next launch of the step path
+// passes the event pair into its own dispatch packet, so the events hold that
+// kernel's start and end (no marker packets or queue gaps around it), and the
+// pair is disarmed.  Unarmed launches are plain launches.
+struct LaunchTiming {
+    hipEvent_t start, stop;
+};
+LaunchTiming &launch_timing();  // the calling host thread's
+
+template <typename F, typename... A>
+hipError_t launch_timed(F kernel, dim3 grid, dim3 block, uint32_t smem, hipStream_t s, A... args) {
+    LaunchTiming &t = launch_timing();
+    if (t.start) {
+        const LaunchTiming e = t;
+        t = LaunchTiming{nullptr, nullptr};
+        hipExtLaunchKernelGGL(kernel, grid, block, smem, s, e.start, e.stop, 0u, args...);
+    } else {
+        kernel<<<grid, block, smem, s>>>(args...);
+    }
+    return hipGetLastError();
+}
 
 constexpr int kMaxBands = 4;
 constexpr int kMaxRadius = 15;   // template side TS <= 31
@@ -63,8 +86,9 @@ struct DevState {
     unsigned long long acc_steps;   // profiling: steps counted into acc_needed
 };
 
-// Region sums of one step tile when all of its pixels are on the + side:
-// the fixed-point value the step kernel's own reduction would produce.
+// Fixed-point region sums and count of one step tile: the all-inside case
+// (the value the step kernel's own reduction would produce when every pixel
+// is on the + side), or a tile's latest contribution to the totals.
 struct alignas(64) TileSum {
     long long sum[4];
     long long cnt;
@@ -105,6 +129,7 @@ struct StepArgs {
     int order;                // lse_order
     int reinit;               // this iteration binarises (Table I step 3)
     int phi_binary;           // phi^n is the binary function in bits_in (sign of the stored field)
+    TileSum *tilelast;        // region, fast path: initial statistics record each step tile's sums here
 };
 
 // Device-resident arguments of one image for the step and normaliser
@@ -125,11 +150,19 @@ struct alignas(16) ImgArgs {
     int n0;                   // iteration index of launch k = 0
     int mgroups;              // workgroups of the normaliser pass (B > 1)
     const TileSum *tilesum;   // region term: per-tile sums of the all-inside case
-    uint32_t *sched_mask;     // 3 x ceil(tiles / 32) words: tiles that were heavy (not quiet), by
-                              // iteration n % 3 (fast path)
+    TileSum *tilelast;        // region term: each tile's latest contribution to the totals
+    uint32_t *sched_mask;     // fast path, 3 x ceil(tiles / 32) words: [n % 3] tiles that were heavy
+                              // (not quiet) in iteration n - 1, all of them after a restart
+    int *plan;                // fast path, single image, 1 + tiles: [0] tiles the next step visits,
+                              // [1 ..] those tiles, heavy ones first (null: each workgroup finds its
+                              // tile in sched_mask)
 };
 
 constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare workgroup
+// A single-image step without a normaliser pass finds its tiles in the heavy
+// record itself up to this many tiles (two mask words per lane of one wave);
+// larger images get a visit list from a separate pass.
+constexpr int kPlanMinTiles = 4096;
 
 // Kernels whose code depends on the storage type T of the resident image
 // (float, __half or __hip_bfloat16).  The member functions are defined in
@@ -193,6 +226,7 @@ hipError_t launch_mpass(const ImgArgs *args, const uint32_t *map, int unit_bits,
                         int NB, int storage, hipStream_t s);
 hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s);
 hipError_t launch_sched_reset(const ImgArgs *host_args, hipStream_t s);
+hipError_t launch_plan(const ImgArgs *dev_args, int k, hipStream_t s);
 hipError_t launch_tile_sums(const ImgArgs *args, int tiles, int r, int NB, int storage, TileSum *out, hipStream_t s);
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W,
                            int WW, hipStream_t s);

@@ -32,6 +32,11 @@
 
 namespace lse {
 
+LaunchTiming &launch_timing() {
+    static thread_local LaunchTiming t{nullptr, nullptr};
+    return t;
+}
+
 // ------------------------------------------------------------- init kernels
 
 // Zero the statistics lines (and, unless keep_image_stats, the image lines and
@@ -291,16 +296,38 @@ __global__ void reset_profile_kernel(DevState *st) {
 
 // Schedule masks: no tile recorded as heavy (the first iteration takes the
 // tiles in order).
-__global__ void sched_reset_kernel(uint32_t *mask, int nwords) {
+// Schedule record for a restart at iteration 0: every tile counts as heavy
+// in slot 0 (so every tile is visited), the other slots clear.
+__global__ void sched_reset_kernel(uint32_t *mask, int nw, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nwords) mask[i] = 0u;
+    if (i >= 3 * nw) return;
+    uint32_t v = 0u;
+    if (i < nw) {
+        const int valid = ntiles - 32 * i;
+        v = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+    }
+    mask[i] = v;
 }
 
 hipError_t launch_sched_reset(const ImgArgs *a, hipStream_t s) {
     if (!a->sched_mask) return hipSuccess;
-    const int nwords = 3 * ((a->tiles + 31) >> 5);
-    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s, a->sched_mask,
-                       nwords);
+    const int nw = (a->tiles + 31) >> 5;
+    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((3 * nw + 255) / 256)), dim3(256), 0, s, a->sched_mask,
+                       nw, a->tiles);
+    return hipGetLastError();
+}
+
+constexpr int kPlanThreads = 1024;
+
+// Visit list of the single-image step (build_plan), for the terms without a
+// normaliser pass to carry it.
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const ImgArgs *__restrict__ args, int k) {
+    __shared__ int s_tot[2 * (kPlanThreads / 64)];
+    build_plan<kPlanThreads>(args[0], args[0].n0 + k, s_tot);
+}
+
+hipError_t launch_plan(const ImgArgs *dev_args, int k, hipStream_t s) {
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_args, k);
     return hipGetLastError();
 }
 

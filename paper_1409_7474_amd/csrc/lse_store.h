@@ -220,6 +220,12 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restri
     const ImgArgs &A = args[ii];
     const int n = A.n0 + k;
     if (n >= A.target) return;
+    if (!map && grp >= A.mgroups) {
+        // One extra workgroup of a single-image launch builds the step's visit list.
+        __shared__ int s_tot[2 * (kThreads / 64)];
+        if (A.plan) build_plan<kThreads>(A, n, s_tot);
+        return;
+    }
     DevState *st = A.st;
     const int sl = n % 3;
     __shared__ Totals tot;
@@ -492,10 +498,13 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     __shared__ Totals tot;
     __shared__ float red[kThreads / 64 * 8];
     __shared__ int s_tile;
+    __shared__ TileSum s_prev, s_all;  // region: the tile's latest contribution; its all-inside sums
     int ii, t;
     if (!batch_unit(map, unit_bits, ii, t)) return;
     const ImgArgs &E = args[ii];
-    // Single image: heavy-first order from the previous iteration's record.
+    // Single image: the active tiles, heavy ones first, from the visit list
+    // (build_plan) or, for small tile counts, from the record itself;
+    // settled tiles have nothing to do.
     const bool dyn = map == nullptr && E.sched_mask != nullptr;
     if (!map && !dyn) t = tile_of(E.tiles);
     const int n = E.n0 + k;
@@ -503,9 +512,27 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     if (dyn ? (int)blockIdx.x >= E.tiles : t < 0) return;
     const int nw = (E.tiles + 31) >> 5;                  // words of one schedule mask
     const int sbn = (n + 1) % 3, sbr = (n + 2) % 3;     // masks written / cleared by this iteration
-    if (dyn && (threadIdx.x >> 6) == 3) {
-        const int tt = heavy_first_tile(E.sched_mask + (size_t)(n % 3) * nw, E.tiles, (int)blockIdx.x);
-        if ((threadIdx.x & 63) == 0) s_tile = tt;
+    // Tables do not depend on the tile: their loads overlap the schedule's.
+    int lut[G::NCH];
+    load_luts<G::NCH>(E.taps, lut);
+    float kk[TS];
+#pragma unroll
+    for (int i = 0; i < TS; ++i) kk[i] = E.taps->k[i];
+    const float *cum = E.taps->cum;
+    if (dyn) {
+        if (E.plan) {
+            if (threadIdx.x == 0) {
+                const int cnt = E.plan[0], tt = E.plan[1 + blockIdx.x];
+                s_tile = (int)blockIdx.x < cnt ? tt : -1;
+            }
+        } else if ((threadIdx.x >> 6) == 0) {
+            const int tt = active_first_tile(E.sched_mask + (size_t)(n % 3) * nw, E.tiles, (E.W + kFX - 1) / kFX,
+                                             (int)blockIdx.x);
+            if (threadIdx.x == 0) s_tile = tt;
+        }
+        __syncthreads();
+        t = s_tile;
+        if (t < 0) return;
     }
     StepArgs A;
     A.img = E.img;
@@ -537,7 +564,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
         py0 = y0 - G::RU - 1;
         border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > W;
     };
-    if (!dyn) set_tile(t);
+    set_tile(t);
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem);
     float *s_phi = smem + G::BH * kFWords;
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(s_phi + G::PH * G::PS);
@@ -545,37 +572,45 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
     int *s_pcode = s_codes + G::BH * 2;                                  // [PHP][2]: phi row uniformity
     uint32_t *s_const = reinterpret_cast<uint32_t *>(s_pcode + G::PHP * 2);  // all-ones / all-zeros rows
 
-    // A: b^{n-1} on the tile + 2R+1 halo.  Issued before the statistics
-    // loads so that the two memory round trips overlap (batch; a single
-    // image learns its tile together with the statistics).
-    if (!dyn) stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    // A: b^{n-1} on the tile + 2R+1 halo, and (region) the tile's previous
+    // record and all-inside sums, issued before the statistics loads so that
+    // the memory round trips overlap.
+    const bool track = !EDGE && E.tilelast != nullptr;
+    long long rec_w = 0, all_w = 0;
+    if (!EDGE && tid < 8) {
+        if (track) rec_w = reinterpret_cast<const long long *>(&E.tilelast[t])[tid];
+        all_w = reinterpret_cast<const long long *>(&E.tilesum[t])[tid];
+    }
+    stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
     if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
-    // Tables do not depend on the statistics either: load them before the
-    // statistics barrier (one memory round trip for the whole set-up).
-    int lut[G::NCH];
-    load_luts<G::NCH>(A.taps, lut);
-    float kk[TS];
-#pragma unroll
-    for (int i = 0; i < TS; ++i) kk[i] = A.taps->k[i];
-    const float *cum = A.taps->cum;
+    if (!EDGE && tid < 8) {
+        reinterpret_cast<long long *>(&s_prev)[tid] = rec_w;
+        reinterpret_cast<long long *>(&s_all)[tid] = all_w;
+    }
     load_totals(st, sl, !EDGE, &tot);
+    const bool lead_block = t == 0;
+    const bool lead = lead_block && threadIdx.x == 0;
     {
         int done = tot.done | tot.bad;
         if (!done && A.stop && tot.flips == 0) done = 1;
         if (done) {
-            if ((dyn ? blockIdx.x == 0 : t == 0) && threadIdx.x == 0 && !tot.bad) st->done = 1;
+            if (lead && !tot.bad) st->done = 1;
             return;
         }
     }
     const bool raw = tot.raw && n == 0;
-    if (dyn) {
-        t = s_tile;
-        set_tile(t);
-        stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
-        __syncthreads();
+    if constexpr (!EDGE) {
+        // The totals of iteration n carry into n + 1; each visited tile adds
+        // the change of its own sums.
+        if (lead && track) {
+            Bin *o = &st->slot[sbn][blockIdx.x % kBins];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (tot.sum[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&o->sum[b]),
+                                          (unsigned long long)tot.sum[b]);
+            if (tot.nplus) atomicAdd(&o->nplus, tot.nplus);
+        }
     }
-    const bool lead_block = t == 0;
-    const bool lead = lead_block && threadIdx.x == 0;
 
     float a[NB], m[NB], w = 0.f;
     float cp[NB], cm[NB], M = 0.f;
@@ -641,7 +676,8 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
             all0 = __syncthreads_and(all0);
             quiet = all1 ? 1 : (all0 ? 0 : -1);
         }
-        // Record heavy tiles for the next iteration's order.
+        // Record heavy tiles: the next iteration visits them and their
+        // neighbours (whose bit windows reach their pixels).
         if (tid == 0 && quiet < 0 && E.sched_mask)
             atomicOr(&E.sched_mask[(size_t)sbn * nw + (t >> 5)], 1u << (t & 31));
         if (quiet >= 0) {
@@ -650,14 +686,13 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                 A.bits_out[(size_t)(y0 + row) * A.WW + (x0 >> 5) + k] = quiet ? ~0u : 0u;
             }
             if constexpr (!EDGE) {
-                if (quiet && tid == 0) {
-                    const TileSum &ts = E.tilesum[t];
-                    Bin *out = &st->slot[(A.n + 1) % 3][blockIdx.x % kBins];
+                // All or nothing: the all-inside sums, or zero.
+                if (tid == 0) {
+                    long long cur[NB];
 #pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&out->sum[b]),
-                                  (unsigned long long)ts.sum[b]);
-                    atomicAdd(&out->nplus, (unsigned long long)ts.cnt);
+                    for (int b = 0; b < NB; ++b) cur[b] = quiet ? s_all.sum[b] : 0;
+                    commit_tile<NB>(cur, quiet ? s_all.cnt : 0, track ? &s_prev : nullptr,
+                                    track ? &E.tilelast[t] : nullptr, &st->slot[sbn][blockIdx.x % kBins]);
                 }
             }
         } else {
@@ -668,6 +703,10 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                 const int x = px0 + p;
                 const int xb = x - x0 + 32;
                 const bool colok = p < G::PW && x >= 0 && x < W;
+                // Only in border tiles, and there only in the chunk next to
+                // the edge, do the taps reach outside the image.
+                const bool cborder = border && span_outside(x0, W, chunk == 0 ? 31 - G::RU - R : 95 - G::RU - R,
+                                                            chunk == 0 ? 95 - G::RU + R : 129 + G::RU + R);
                 if (raw) {
                     for (int j = 0; j < G::SEG; ++j) {
                         const int q = seg * G::SEG + j, y = py0 + q;
@@ -688,7 +727,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                     for (int blk = 0; blk < G::NBLK; ++blk) {
                         const int rb = brow0 + blk * kSB;
                         int uni = -1;
-                        if (!border && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
+                        if (!cborder && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
                             uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
                         if (uni >= 0) {
                             const float v = uni ? phi_one : phi_zero;
@@ -706,7 +745,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                             for (int t2 = 0; t2 < 2 * R; ++t2) {
                                 const int y = by0 + rb + t2;
                                 const float v =
-                                    hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, border, lut, cum);
+                                    hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, cborder, lut, cum);
                                 win[t2] = (y >= 0 && y < H) ? v : 0.f;
                             }
                         }
@@ -714,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
                         for (int t2 = 0; t2 < kSB; ++t2) {
                             const int brow = rb + 2 * R + t2;
                             const int y = by0 + brow;
-                            const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, border, lut, cum);
+                            const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, cborder, lut, cum);
                             win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
                         }
     #pragma unroll
@@ -881,7 +920,8 @@ __global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__re
             }
             TileSmem rs;
             rs.red = red;
-            reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[(A.n + 1) % 3][blockIdx.x % kBins], A.fix, !EDGE);
+            reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[sbn][blockIdx.x % kBins], A.fix, !EDGE,
+                              track ? &s_prev : nullptr, track ? &E.tilelast[t] : nullptr);
         }
     }
     if (lead_block) {
@@ -971,7 +1011,8 @@ __global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int ra
                           lut, kk, A.taps->cum, acc, cnt);
     TileSmem rs;
     rs.red = red;
-    reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
+    reduce_commit<NB>(rs, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true, nullptr,
+                      A.tilelast ? &A.tilelast[blockIdx.y * gridDim.x + blockIdx.x] : nullptr);
 }
 
 // ------------------------------------------------------ continuous LSF
@@ -1273,9 +1314,8 @@ static hipError_t launch_step_fast_t(const ImgArgs *args, const uint32_t *map, i
     const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
     const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE, ST>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((step_fast_kernel<R, NB, EDGE, ST>), dim3(grid), dim3(kThreads), sm, s, args, map, unit_bits,
-                       k, stop);
-    return hipGetLastError();
+    return launch_timed(step_fast_kernel<R, NB, EDGE, ST>, dim3(grid), dim3(kThreads), (uint32_t)sm, s, args, map,
+                        unit_bits, k, stop);
 }
 
 template <int R, typename ST>
@@ -1322,8 +1362,7 @@ static hipError_t launch_step_generic_t(const StepArgs &a, hipStream_t s) {
     const size_t sm = tile_smem_bytes(a.r, a.nch, EDGE ? 1 : 0);
     const hipError_t e = ensure_lds(step_kernel<NB, EDGE, ST>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((step_kernel<NB, EDGE, ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a);
-    return hipGetLastError();
+    return launch_timed(step_kernel<NB, EDGE, ST>, tile_grid(a.H, a.W), dim3(kThreads), (uint32_t)sm, s, a);
 }
 
 template <typename ST>
@@ -1419,16 +1458,10 @@ template <typename ST>
 hipError_t Store<ST>::mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                             int NB, hipStream_t s) {
     switch (NB) {
-        case 2:
-            hipLaunchKernelGGL((mpass_kernel<2, ST>), dim3(grid), dim3(kThreads), 0, s, args, map, unit_bits, k, stop);
-            break;
-        case 4:
-            hipLaunchKernelGGL((mpass_kernel<4, ST>), dim3(grid), dim3(kThreads), 0, s, args, map, unit_bits, k, stop);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 2: return launch_timed(mpass_kernel<2, ST>, dim3(grid), dim3(kThreads), 0u, s, args, map, unit_bits, k, stop);
+        case 4: return launch_timed(mpass_kernel<4, ST>, dim3(grid), dim3(kThreads), 0u, s, args, map, unit_bits, k, stop);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <int NB, bool EDGE, typename ST>
@@ -1436,8 +1469,7 @@ static hipError_t launch_dense_t(const StepArgs &a, hipStream_t s) {
     const size_t sm = dense_smem_words(a.r) * 4;
     const hipError_t e = ensure_lds(dense_step_kernel<NB, EDGE, ST>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((dense_step_kernel<NB, EDGE, ST>), tile_grid(a.H, a.W), dim3(kThreads), sm, s, a);
-    return hipGetLastError();
+    return launch_timed(dense_step_kernel<NB, EDGE, ST>, tile_grid(a.H, a.W), dim3(kThreads), (uint32_t)sm, s, a);
 }
 
 template <typename ST>

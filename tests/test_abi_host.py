@@ -93,13 +93,14 @@ def test_16bit_storage_allows_larger_images():
 def test_variant_modes_are_valid():
     # listing order, reinitialisation schedules and the intensity-only term
     # are implemented; they keep a continuous LSF plane in the workspace
-    # (the binary-state path instead keeps 64 bytes of all-inside region sums
-    # per 96 x 64 step tile and three one-bit-per-tile schedule masks, one
-    # tile here: two 256-byte pieces)
+    # (the binary-state path instead keeps, per 96 x 48 step tile, 64 bytes
+    # of all-inside region sums and 64 bytes of the tile's latest
+    # contribution, three one-bit-per-tile schedule masks and a visit list of
+    # 1 + tiles ints; two tiles here: four 256-byte pieces)
     base = lse.lse_workspace_bytes(lse.make_params(64, 64, 4))
     for kw in ({"order": "listing"}, {"reinit_every": 0}, {"reinit_every": 3}):
         n = lse.lse_workspace_bytes(lse.make_params(64, 64, 4, **kw))
-        assert n == base - 2 * 256 + 2 * 64 * 64 * 4, kw
+        assert n == base - 4 * 256 + 2 * 64 * 64 * 4, kw
     gray = lse.lse_workspace_bytes(lse.make_params(64, 64, 4, term="region_intensity"))
     assert gray < base  # one stored value per pixel, no normaliser boxes
 

@@ -174,6 +174,38 @@ def test_batch_equals_alone(dev, graph):
     batch.close()
 
 
+@pytest.mark.parametrize("term", ["region", "region_intensity", "edge"])
+def test_single_image_skipping_equals_batch(dev, term):
+    """A single image visits only the tiles near the front: a visit list from
+    the normaliser pass (region, B = 4) or from its own pass (the other terms,
+    more than 4096 tiles here), or each workgroup's own scan of the heavy
+    record (small images: every other test).  A batch of one visits every
+    tile; both must agree bit for bit after 40 iterations, and after a
+    restart from a new mask."""
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_multiband(11, size=4160, bands=4, n_roofs=30, n_roads=3, height=4160, width=6240)
+    img = _img(dev, sc.image)
+    init = sc.init_edge if term == "edge" else sc.init_region
+    kw = dict(term=term, sigma=1.5, ksize=11)
+    solo = _make(dev, img, init, **kw)
+    solo.run(40)
+    want = _state(solo)
+    other = _make(dev, img, init, **kw)
+    batch = lse.Batch([other])
+    batch.run(40)
+    _assert_same(_state(other), want, term)
+    assert want[2]["iters_done"] == 40
+    m = torch.tensor(sc.init_region, device=dev)
+    solo.set_mask(m, smoothed=False)
+    other.set_mask(m, smoothed=False)
+    solo.run(12)
+    batch.run(12)
+    _assert_same(_state(other), _state(solo), term + " after set_mask")
+    batch.close()
+    solo.close()
+    other.close()
+
+
 def test_batch_interleaves_with_single_steps(dev):
     """Batch runs, solo steps of one member and lse_set_mask between them keep
     every image identical to its solo history."""

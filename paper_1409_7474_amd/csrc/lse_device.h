@@ -695,10 +695,12 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
         for (int blk = 0; blk < G::SEGD / kSB; ++blk) {
             const int rb = urow0 + blk * kSB;
             const int yb = y0 - R + rb;  // image row of U row rb
-            int uni = -1;
-            if (!border && yb >= 0 && yb + kSB + 2 * R <= H) uni = block_code(codes, rb, kSB + 2 * R, chunk);
+            // Uniform block: every pixel has the sign of the constant.  Only
+            // the sign is needed, so this holds at the image edges too: bits
+            // outside the image are zero, so an all-ones window lies inside
+            // the image, and an all-zeros one gives minus a positive sum.
+            const int uni = block_code(codes, rb, kSB + 2 * R, chunk);
             if (uni >= 0) {
-                // Uniform block: every pixel has the sign of the constant.
                 if (uni == 1) inmask |= ((1u << kSB) - 1u) << (blk * kSB);
                 have_win = false;
                 continue;

@@ -489,7 +489,9 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
 // n = n0 + k of every image it covers (one image when map is null; else the
 // workgroup map names image and tile).
 template <int R, int NB, bool EDGE, typename ST>
-__global__ __launch_bounds__(kThreads) void step_fast_kernel(const ImgArgs *__restrict__ args,
+// At least 4 waves per SIMD: the B = 4 region kernels of the larger radii
+// otherwise take 129-134 VGPRs and drop to 3 (R = 6: 128, no spill).
+__global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *__restrict__ args,
                                                               const uint32_t *__restrict__ map, int unit_bits, int k,
                                                               int stop) {
     using G = FastGeom<R, EDGE>;

@@ -819,23 +819,28 @@ __device__ __forceinline__ uint32_t active_word(const uint32_t *__restrict__ hea
 // computed by one wave from the previous iteration's record of heavy tiles
 // (the order of build_plan: heavy tiles, then their other neighbours).
 // Returns -1 for j >= the number of active tiles.  Every workgroup scans the
-// whole record, so this serves small tile counts only.
+// whole record, so this serves small tile counts only (ntiles <=
+// kPlanMinTiles: two record words per lane, kept in registers).
 __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ heavy, int ntiles, int ntx, int j) {
     const int lane = (int)threadIdx.x & 63;
     if (j >= ntiles) return -1;
+    constexpr int kPer = kPlanMinTiles / 32 / 64;  // words per lane (the caller keeps ntiles <= kPlanMinTiles)
     const int nw = (ntiles + 31) >> 5;
-    const int per = (nw + 63) >> 6;  // words per lane
-    const int w0 = lane * per;
-    int nh = 0, na = 0;              // heavy tiles; other active tiles
-    for (int i = 0; i < per; ++i) {
+    const int w0 = lane * kPer;
+    uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
+    int nh = 0, na = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
         const int w = w0 + i;
+        hw[i] = aw[i] = 0u;
         if (w < nw) {
             const int valid = min(32, ntiles - 32 * w);
             const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-            const uint32_t h = heavy[w] & vm;
-            nh += __popc(h);
-            na += __popc(active_word(heavy, nw, ntx, w) & vm & ~h);
+            hw[i] = heavy[w] & vm;
+            aw[i] = active_word(heavy, nw, ntx, w) & vm & ~hw[i];
         }
+        nh += __popc(hw[i]);
+        na += __popc(aw[i]);
     }
     int inch = nh, inca = na;
 #pragma unroll
@@ -857,18 +862,15 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
     int t = -1;
     if (lane == src) {
         int left = r - lo;
-        for (int i = 0; i < per && t < 0; ++i) {
-            const int w = w0 + i;
-            const int valid = min(32, ntiles - 32 * w);
-            const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-            const uint32_t h = heavy[w] & vm;
-            const uint32_t bits = first ? h : (active_word(heavy, nw, ntx, w) & vm & ~h);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint32_t bits = first ? hw[i] : aw[i];
             const int c = __popc(bits);
-            if (left < c) {
+            if (t < 0 && left < c) {
                 uint32_t b = bits;
                 for (int q = 0; q < left; ++q) b &= b - 1u;  // drop the lowest set bits
-                t = 32 * w + (__ffs((int)b) - 1);
-            } else {
+                t = 32 * (w0 + i) + (__ffs((int)b) - 1);
+            } else if (t < 0) {
                 left -= c;
             }
         }

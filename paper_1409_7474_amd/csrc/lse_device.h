@@ -509,6 +509,24 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
 
 constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 8;
 
+// One thread of a step's lead workgroup: the image values of the pixel that
+// maximised |D| for this iteration (key `mkey`, from its statistics slot
+// `sl`), kept in that slot's spare words for the next normaliser pass, whose
+// lower bound they give without a dependent load.  The slot is cleared only
+// by the step after that pass.
+template <int NB, typename ST>
+__device__ __forceinline__ void record_max_pixel(DevState *st, int sl, unsigned long long mkey, const void *img,
+                                                 long long hw) {
+    const unsigned int pix = 0xffffffffu - (unsigned int)(mkey & 0xffffffffu);
+    if (mkey == 0ull || (long long)pix >= hw) return;
+    const Px<NB> v = load_px<ST, NB>(static_cast<const ST *>(img), pix);
+    Bin &b0 = st->slot[sl][0];
+    float *pf = reinterpret_cast<float *>(&b0.pad[0]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pf[b] = v.v[b];
+    b0.pad[2] = (unsigned long long)pix + 1ull;
+}
+
 __device__ __forceinline__ unsigned long long mkey_of(float absd, unsigned int pix) {
     return ((unsigned long long)__float_as_uint(absd) << 32) | (unsigned long long)(0xffffffffu - pix);
 }
@@ -786,19 +804,20 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
-// 32 bits of the heavy-tile record starting at tile index `base` (may lie
-// outside [0, ntiles): those bits are zero).
-__device__ __forceinline__ uint32_t heavy_bits(const uint32_t *__restrict__ heavy, int nw, int base) {
+// 32 bits of the heavy-tile record (buffer resource over its nw words)
+// starting at tile index `base`; bits outside [0, ntiles) are zero.  Buffer
+// loads return zero for words outside the record, so the loads need no
+// branches and all of them can be in flight together.
+__device__ __forceinline__ uint32_t heavy_bits(__amdgpu_buffer_rsrc_t heavy, int base) {
     const int wq = base >> 5, sh = base & 31;  // floor division (arithmetic shift)
-    const uint32_t lo = (wq >= 0 && wq < nw) ? heavy[wq] : 0u;
-    if (sh == 0) return lo;
-    const uint32_t hi = (wq + 1 >= 0 && wq + 1 < nw) ? heavy[wq + 1] : 0u;
-    return (lo >> sh) | (hi << (32 - sh));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)wq * 4u, 0, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)(wq + 1) * 4u, 0, 0);
+    return sh == 0 ? lo : (lo >> sh) | (hi << (32 - sh));
 }
 
 // Active tiles of word w: a tile is active when it or one of its eight
 // neighbours (in a grid of ntx tiles per row) was heavy.
-__device__ __forceinline__ uint32_t active_word(const uint32_t *__restrict__ heavy, int nw, int ntx, int w) {
+__device__ __forceinline__ uint32_t active_word(__amdgpu_buffer_rsrc_t heavy, int ntx, int w) {
     const int base = 32 * w;
     // Tiles of this word in the first / last column of the tile grid.
     uint32_t first_col = 0u, last_col = 0u;
@@ -809,8 +828,7 @@ __device__ __forceinline__ uint32_t active_word(const uint32_t *__restrict__ hea
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
         const int b = base + dy * ntx;
-        a |= heavy_bits(heavy, nw, b) | (heavy_bits(heavy, nw, b - 1) & ~first_col) |
-             (heavy_bits(heavy, nw, b + 1) & ~last_col);
+        a |= heavy_bits(heavy, b) | (heavy_bits(heavy, b - 1) & ~first_col) | (heavy_bits(heavy, b + 1) & ~last_col);
     }
     return a;
 }
@@ -828,6 +846,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
     const int nw = (ntiles + 31) >> 5;
     const int w0 = lane * kPer;
     uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
+    const __amdgpu_buffer_rsrc_t hr = image_rsrc(heavy, (uint32_t)nw * 4u);
     int nh = 0, na = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
@@ -837,7 +856,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
             const int valid = min(32, ntiles - 32 * w);
             const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
             hw[i] = heavy[w] & vm;
-            aw[i] = active_word(heavy, nw, ntx, w) & vm & ~hw[i];
+            aw[i] = active_word(hr, ntx, w) & vm & ~hw[i];
         }
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
@@ -889,6 +908,7 @@ template <int NT>
 __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
     const uint32_t *heavy = E.sched_mask + (size_t)(n % 3) * nw;
+    const __amdgpu_buffer_rsrc_t hr = image_rsrc(heavy, (uint32_t)nw * 4u);
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (nw + NT - 1) / NT;
     const int w0 = tid * per;
@@ -896,7 +916,7 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         h = heavy[w] & vm;
-        a = active_word(heavy, nw, ntx, w) & vm & ~h;
+        a = active_word(hr, ntx, w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {

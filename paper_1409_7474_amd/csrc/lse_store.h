@@ -229,13 +229,20 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restri
     DevState *st = A.st;
     const int sl = n % 3;
     __shared__ Totals tot;
-    __shared__ unsigned long long prev_key, wkey[kThreads / 64];
+    __shared__ unsigned long long wkey[kThreads / 64];
     __shared__ int scan_list[kMBlocksPerWG];
     __shared__ int nscan;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (wave == 2) {  // previous iteration's maximum (slot n - 1 == (n + 2) % 3)
-        const unsigned long long pk = wave_max_u64(st->slot[(n + 2) % 3][lane].mkey);
-        if (lane == 0) prev_key = pk;
+    __shared__ float prev_px[NB];  // image values of the previous iteration's maximising pixel
+    __shared__ int prev_ok;
+    if (wave == 2 && lane == 0) {
+        // Recorded by the step of iteration n - 1 in its statistics slot
+        // ((n + 2) % 3, cleared only by the step of iteration n).
+        const Bin &b0 = st->slot[(n + 2) % 3][0];
+        const float *pf = reinterpret_cast<const float *>(&b0.pad[0]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) prev_px[b] = pf[b];
+        prev_ok = b0.pad[2] != 0ull;
     }
     // This workgroup's block boxes (lane k < kMBlocksPerWG of wave 0) do not
     // depend on the statistics: load them before the statistics barrier.
@@ -259,9 +266,14 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restri
         a[b] = cp[b] - cm[b];
         m[b] = cp[b] + cm[b];
     }
-    const ST *img = static_cast<const ST *>(A.img);
-    const unsigned int ppix = 0xffffffffu - (unsigned int)(prev_key & 0xffffffffu);
-    const float lb = (long long)ppix < A.hw ? fabsf(region_D<NB>(load_px<ST, NB>(img, ppix), a, m)) : 0.f;
+    const __amdgpu_buffer_rsrc_t img_rs = image_rsrc(A.img, (uint32_t)(A.hw * (long long)(NB * sizeof(ST))));
+    float lb = 0.f;
+    if (prev_ok) {
+        Px<NB> pv;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) pv.v[b] = prev_px[b];
+        lb = fabsf(region_D<NB>(pv, a, m));
+    }
 
     if (wave == 0) {
         const int blk = myblk;
@@ -291,12 +303,23 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restri
         const int blk = scan_list[q];
         const int bx = blk % nbx, by = blk / nbx;
         const int x = bx * kMBX + lane;
-        for (int r = wave; r < kMBY; r += kThreads / 64) {
-            const int y = by * kMBY + r;
+        // Every row load of this wave in flight at once (buffer loads: no
+        // branches; outside the image they return zeros), then the keys.
+        constexpr int RW = kMBY / (kThreads / 64);
+        Px<NB> v[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int y = by * kMBY + wave + i * (kThreads / 64);
+            const bool ok = x < A.W && y < A.H;
+            v[i] = buffer_px<ST, NB>(img_rs, ok ? (uint32_t)((long long)y * A.W + x) * (uint32_t)(NB * sizeof(ST))
+                                                : kNoLoad);
+        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int y = by * kMBY + wave + i * (kThreads / 64);
             if (x < A.W && y < A.H) {
                 const unsigned int pix = (unsigned int)((long long)y * A.W + x);
-                const float d = fabsf(region_D<NB>(load_px<ST, NB>(img, pix), a, m));
-                const unsigned long long key = mkey_of(d, pix);
+                const unsigned long long key = mkey_of(fabsf(region_D<NB>(v[i], a, m)), pix);
                 best = key > best ? key : best;
             }
         }
@@ -471,6 +494,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
     }
+    if constexpr (!EDGE && NB > 1)
+        if (lead) record_max_pixel<NB, ST>(st, sl, tot.mkey, A.img, A.hw);
     if (lead) {
         st->iters += 1;
         if constexpr (!EDGE) {
@@ -934,6 +959,8 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
         if (E.sched_mask)
             for (int i = threadIdx.x; i < nw; i += kThreads) E.sched_mask[(size_t)sbr * nw + i] = 0u;
     }
+    if constexpr (!EDGE && NB > 1)
+        if (lead) record_max_pixel<NB, ST>(st, sl, tot.mkey, A.img, A.hw);
     if (lead) {
         st->iters += 1;
         if constexpr (!EDGE) {
@@ -1223,6 +1250,8 @@ __global__ __launch_bounds__(kThreads) void dense_step_kernel(StepArgs A) {
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
     }
+    if constexpr (!EDGE && NB > 1)
+        if (lead) record_max_pixel<NB, ST>(st, sl, tot.mkey, A.img, A.hw);
     if (lead) {
         st->iters += 1;
         if constexpr (!EDGE) {

@@ -87,48 +87,87 @@ struct Totals {
     unsigned int imin_key[4], imax_key[4];
 };
 
-__device__ __forceinline__ void load_totals(const DevState *st, int sl, bool want_img, Totals *t) {
+// The statistics lines of one slot, in two halves so that a caller can put
+// other loads in flight between them: totals_issue loads this wave's lines
+// into registers (wave 0: the statistics bins, lane i = bin i; wave 1: the
+// image bins; wave 2: the flags), totals_commit reduces them and writes
+// `t` (the caller then synchronises the workgroup).
+struct TotalsRegs {
+    long long v[4], np, fl;
+    unsigned long long mk;
+    unsigned int lo[4], hi[4];
+    int done, bad, raw;
+};
+
+__device__ __forceinline__ void totals_issue(const DevState *st, int sl, bool want_img, TotalsRegs &r) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (wave == 0) {
         const Bin &b = st->slot[sl][lane];
-        long long v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = wave_sum_ll(b.sum[k]);
-        const long long np = wave_sum_ll((long long)b.nplus);
-        const long long fl = wave_sum_ll((long long)b.flips);
-        const unsigned long long mk = wave_max_u64(b.mkey);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) t->sum[k] = v[k];
-            t->nplus = (unsigned long long)np;
-            t->flips = (unsigned long long)fl;
-            t->mkey = mk;
-        }
+        for (int k = 0; k < 4; ++k) r.v[k] = b.sum[k];
+        r.np = (long long)b.nplus;
+        r.fl = (long long)b.flips;
+        r.mk = b.mkey;
     } else if (wave == 2) {
         if (lane == 0) {
-            t->done = st->done;
-            t->bad = st->bad;
-            t->raw = st->raw;
+            r.done = st->done;
+            r.bad = st->bad;
+            r.raw = st->raw;
         }
     } else if (wave == 1 && want_img) {
         const ImgBin &b = st->img[lane];
-        long long v[4];
-        unsigned int lo[4], hi[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            v[k] = wave_sum_ll(b.total[k]);
-            lo[k] = wave_min_u(b.imin_key[k]);
-            hi[k] = wave_max_u(b.imax_key[k]);
+            r.v[k] = b.total[k];
+            r.lo[k] = b.imin_key[k];
+            r.hi[k] = b.imax_key[k];
+        }
+    }
+}
+
+__device__ __forceinline__ void totals_commit(bool want_img, TotalsRegs &r, Totals *t) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r.v[k] = wave_sum_ll(r.v[k]);
+        r.np = wave_sum_ll(r.np);
+        r.fl = wave_sum_ll(r.fl);
+        r.mk = wave_max_u64(r.mk);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t->sum[k] = r.v[k];
+            t->nplus = (unsigned long long)r.np;
+            t->flips = (unsigned long long)r.fl;
+            t->mkey = r.mk;
+        }
+    } else if (wave == 2) {
+        if (lane == 0) {
+            t->done = r.done;
+            t->bad = r.bad;
+            t->raw = r.raw;
+        }
+    } else if (wave == 1 && want_img) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r.v[k] = wave_sum_ll(r.v[k]);
+            r.lo[k] = wave_min_u(r.lo[k]);
+            r.hi[k] = wave_max_u(r.hi[k]);
         }
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                t->total[k] = v[k];
-                t->imin_key[k] = lo[k];
-                t->imax_key[k] = hi[k];
+                t->total[k] = r.v[k];
+                t->imin_key[k] = r.lo[k];
+                t->imax_key[k] = r.hi[k];
             }
         }
     }
+}
+
+__device__ __forceinline__ void load_totals(const DevState *st, int sl, bool want_img, Totals *t) {
+    TotalsRegs r;
+    totals_issue(st, sl, want_img, r);
+    totals_commit(want_img, r, t);
     __syncthreads();
 }
 
@@ -648,16 +687,31 @@ __device__ __forceinline__ int block_code(const int *codes, int row0, int n, int
     return -1;
 }
 
-// Stage bit rows [row0, row0 + nrows) of global words x0/32 - 1 .. x0/32 + 4.
-__device__ __forceinline__ void stage_bits_fast(uint32_t *dst, const uint32_t *__restrict__ bits, int row0,
-                                                int nrows, int x0, int H, int WW) {
+// Stage NROWS rows of kFWords bit words (global words x0/32 - 1 .. x0/32 + 4;
+// the last one is padding) starting at image row row0 into LDS; words
+// outside the image are zero.  Buffer loads (zero outside their range) keep
+// the loads branch-free: every load of a thread is in flight before its
+// first LDS store.
+template <int NROWS>
+__device__ __forceinline__ void stage_bits_fast(uint32_t *dst, const uint32_t *__restrict__ bits, int row0, int x0,
+                                                int H, int WW) {
+    constexpr int N = NROWS * kFWords;
+    constexpr int NIT = (N + kThreads - 1) / kThreads;
+    const __amdgpu_buffer_rsrc_t rs = image_rsrc(bits, (uint32_t)((long long)H * WW * 4));
     const int wb0 = (x0 >> 5) - 1;
-    for (int i = threadIdx.x; i < nrows * kFWords; i += kThreads) {
+    uint32_t v[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int i = (int)threadIdx.x + k * kThreads;
         const int row = i / kFWords, wc = i - row * kFWords;
         const int y = row0 + row, gw = wb0 + wc;
-        uint32_t v = 0;
-        if (wc < kFWords - 1 && y >= 0 && y < H && gw >= 0 && gw < WW) v = bits[(size_t)y * WW + gw];
-        dst[i] = v;
+        const bool ok = i < N && wc < kFWords - 1 && y >= 0 && y < H && gw >= 0 && gw < WW;
+        v[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, ok ? (uint32_t)(y * WW + gw) * 4u : kNoLoad, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int i = (int)threadIdx.x + k * kThreads;
+        if (i < N) dst[i] = v[k];
     }
 }
 
@@ -804,21 +858,21 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
-// 32 bits of the heavy-tile record (buffer resource over its nw words)
-// starting at tile index `base`; bits outside [0, ntiles) are zero.  Buffer
-// loads return zero for words outside the record, so the loads need no
-// branches and all of them can be in flight together.
-__device__ __forceinline__ uint32_t heavy_bits(__amdgpu_buffer_rsrc_t heavy, int base) {
-    const int wq = base >> 5, sh = base & 31;  // floor division (arithmetic shift)
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)wq * 4u, 0, 0);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)(wq + 1) * 4u, 0, 0);
-    return sh == 0 ? lo : (lo >> sh) | (hi << (32 - sh));
-}
-
-// Active tiles of word w: a tile is active when it or one of its eight
-// neighbours (in a grid of ntx tiles per row) was heavy.
+// Active tiles of word w of the heavy-tile record (buffer resource over its
+// words): a tile is active when it or one of its eight neighbours (in a grid
+// of ntx tiles per row) was heavy.  The record bits at tile offsets
+// dy * ntx + dx around the word are read as funnel shifts of word pairs;
+// buffer loads return zero outside the record, so all eighteen loads are
+// issued straight away (no branches), then combined.
 __device__ __forceinline__ uint32_t active_word(__amdgpu_buffer_rsrc_t heavy, int ntx, int w) {
     const int base = 32 * w;
+    uint32_t lo[9], hi[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int wq = (base + (k / 3 - 1) * ntx + (k % 3 - 1)) >> 5;  // floor division (arithmetic shift)
+        lo[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)wq * 4u, 0, 0);
+        hi[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(heavy, (uint32_t)(wq + 1) * 4u, 0, 0);
+    }
     // Tiles of this word in the first / last column of the tile grid.
     uint32_t first_col = 0u, last_col = 0u;
     const int c0 = base % ntx;
@@ -826,9 +880,12 @@ __device__ __forceinline__ uint32_t active_word(__amdgpu_buffer_rsrc_t heavy, in
     for (int i = ntx - 1 - c0; i < 32; i += ntx) last_col |= 1u << i;
     uint32_t a = 0u;
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int b = base + dy * ntx;
-        a |= heavy_bits(heavy, b) | (heavy_bits(heavy, b - 1) & ~first_col) | (heavy_bits(heavy, b + 1) & ~last_col);
+    for (int k = 0; k < 9; ++k) {
+        const int sh = (base + (k / 3 - 1) * ntx + (k % 3 - 1)) & 31;
+        uint32_t v = sh == 0 ? lo[k] : (lo[k] >> sh) | (hi[k] << (32 - sh));
+        if (k % 3 == 0) v &= ~first_col;  // left neighbour: not for tiles in the first column
+        if (k % 3 == 2) v &= ~last_col;   // right neighbour: not for tiles in the last column
+        a |= v;
     }
     return a;
 }
@@ -851,13 +908,10 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const int w = w0 + i;
-        hw[i] = aw[i] = 0u;
-        if (w < nw) {
-            const int valid = min(32, ntiles - 32 * w);
-            const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-            hw[i] = heavy[w] & vm;
-            aw[i] = active_word(hr, ntx, w) & vm & ~hw[i];
-        }
+        const int valid = max(0, min(32, ntiles - 32 * w));  // 0 past the record
+        const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+        hw[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(hr, (uint32_t)w * 4u, 0, 0) & vm;
+        aw[i] = active_word(hr, ntx, w) & vm & ~hw[i];
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
     }
@@ -915,7 +969,7 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
     auto word_masks = [&](int w, uint32_t &h, uint32_t &a) {
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        h = heavy[w] & vm;
+        h = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(hr, (uint32_t)w * 4u, 0, 0) & vm;
         a = active_word(hr, ntx, w) & vm & ~h;
     };
     int nh = 0, na = 0;

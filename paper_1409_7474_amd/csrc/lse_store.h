@@ -603,18 +603,21 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
     // record and all-inside sums, issued before the statistics loads so that
     // the memory round trips overlap.
     const bool track = !EDGE && E.tilelast != nullptr;
+    TotalsRegs tregs;
+    totals_issue(st, sl, !EDGE, tregs);
     long long rec_w = 0, all_w = 0;
     if (!EDGE && tid < 8) {
         if (track) rec_w = reinterpret_cast<const long long *>(&E.tilelast[t])[tid];
         all_w = reinterpret_cast<const long long *>(&E.tilesum[t])[tid];
     }
-    stage_bits_fast(s_bits, A.bits_in, by0, G::BH, x0, H, A.WW);
+    stage_bits_fast<G::BH>(s_bits, A.bits_in, by0, x0, H, A.WW);
     if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
     if (!EDGE && tid < 8) {
         reinterpret_cast<long long *>(&s_prev)[tid] = rec_w;
         reinterpret_cast<long long *>(&s_all)[tid] = all_w;
     }
-    load_totals(st, sl, !EDGE, &tot);
+    totals_commit(!EDGE, tregs, &tot);
+    __syncthreads();
     const bool lead_block = t == 0;
     const bool lead = lead_block && threadIdx.x == 0;
     {
@@ -1030,7 +1033,7 @@ __global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int ra
 #pragma unroll
     for (int i = 0; i < 2 * R + 1; ++i) kk[i] = A.taps->k[i];
     int *s_codes = reinterpret_cast<int *>(s_bn + G::UH * kFWords);
-    stage_bits_fast(s_bn, A.bits_in, y0 - R, G::UH, x0, A.H, A.WW);
+    stage_bits_fast<G::UH>(s_bn, A.bits_in, y0 - R, x0, A.H, A.WW);
     __syncthreads();
     code_rows_owned<R>(s_bn, G::UH, s_codes);
     __syncthreads();

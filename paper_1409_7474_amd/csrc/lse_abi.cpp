@@ -60,6 +60,8 @@ struct lse_batch {
         int step_bits, mpass_bits;    // unit bits of the map entries
         size_t step_map, mpass_map;   // offsets (entries) into the map
         unsigned step_grid, mpass_grid;
+        bool visit_list;              // step map rebuilt per launch (batch_plan_kernel) at step_map:
+        size_t wbase_map;             // count + 1 heavy-record word offsets
     };
     std::vector<lse_ctx *> cs;        // in table order
     std::vector<int> target;
@@ -348,8 +350,8 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     } else if (fast_radius(c->r)) {
         if (c->host_args.plan && !(region && c->NB > 1)) e = launch_plan(c->dargs, c->n, s);
         if (e == hipSuccess)
-            e = launch_step(c->dargs, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
-                            region ? 0 : 1, storage, s);
+            e = launch_step(c->dargs, nullptr, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r,
+                            c->NB, region ? 0 : 1, storage, s);
     } else {
         e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
     }
@@ -706,21 +708,36 @@ size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
         g.mpass_bits = bits_for(maxm);
         const int ubits = std::max(g.step_bits, g.mpass_bits);
         if (ubits >= 31 || (long long)g.count >= (1ll << (32 - ubits)) - 1) return 0;
-        // Step map: workgroup w runs on XCD w % 8; XCD x takes the x-th
-        // eighth of the concatenated tiles.
         const long long grid = (total + 7) & ~7ll;
         if (grid > 0x7fffffffll) return 0;
-        g.step_map = b->hmap.size();
         g.step_grid = (unsigned)grid;
-        b->hmap.resize(b->hmap.size() + grid, kNoTile);
-        const long long per = grid / 8;
-        for (long long w = 0; w < grid; ++w) {
-            const long long x = w & 7, slot = w >> 3;
-            const long long lo = total * x / 8, hi = total * (x + 1) / 8;
-            const long long t = lo + slot;
-            if (slot >= per || t >= hi) continue;
-            const long long im = std::upper_bound(prefix.begin(), prefix.end(), t) - prefix.begin() - 1;
-            b->hmap[g.step_map + w] = ((uint32_t)im << g.step_bits) | (uint32_t)(t - prefix[im]);
+        g.visit_list = g.count <= kBatchPlanImages;
+        if (g.visit_list) {
+            // Visit list, rebuilt on the device for every launch: the active
+            // tiles of every image (heavy first); settled tiles are skipped.
+            g.wbase_map = b->hmap.size();
+            uint32_t words = 0;
+            for (int q = 0; q < g.count; ++q) {
+                b->hmap.push_back(words);
+                words += (uint32_t)((b->cs[g.first + q]->host_args.tiles + 31) / 32);
+            }
+            b->hmap.push_back(words);
+            g.step_map = b->hmap.size();
+            b->hmap.resize(b->hmap.size() + 1 + total, 0u);
+        } else {
+            // Static step map over every tile: workgroup w runs on XCD w % 8;
+            // XCD x takes the x-th eighth of the concatenated tiles.
+            g.step_map = b->hmap.size();
+            b->hmap.resize(b->hmap.size() + grid, kNoTile);
+            const long long per = grid / 8;
+            for (long long w = 0; w < grid; ++w) {
+                const long long x = w & 7, slot = w >> 3;
+                const long long lo = total * x / 8, hi = total * (x + 1) / 8;
+                const long long t = lo + slot;
+                if (slot >= per || t >= hi) continue;
+                const long long im = std::upper_bound(prefix.begin(), prefix.end(), t) - prefix.begin() - 1;
+                b->hmap[g.step_map + w] = ((uint32_t)im << g.step_bits) | (uint32_t)(t - prefix[im]);
+            }
         }
         // Normaliser map (B > 1 region images): image-major block groups.
         g.mpass_map = b->hmap.size();
@@ -815,12 +832,19 @@ hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
     hipError_t e = launch_batch_prepare(b->dargs, (int)b->cs.size(), s);
     for (int k = 0; k < iters && e == hipSuccess; ++k) {
         for (const auto &g : b->groups) {
-            if (g.mpass_grid)
+            uint32_t *map = b->dmap + g.step_map;
+            const int *nmap = nullptr;
+            if (g.visit_list) {
+                e = launch_batch_plan(b->dargs + g.first, b->dmap + g.wbase_map, g.count, g.step_bits, k, map, s);
+                nmap = reinterpret_cast<const int *>(map);
+                map += 1;
+            }
+            if (e == hipSuccess && g.mpass_grid)
                 e = launch_mpass(b->dargs + g.first, b->dmap + g.mpass_map, g.mpass_bits, g.mpass_grid, k, stop, g.NB,
                                  g.storage, s);
             if (e == hipSuccess)
-                e = launch_step(b->dargs + g.first, b->dmap + g.step_map, g.step_bits, g.step_grid, k, stop, g.r,
-                                g.NB, g.edge, g.storage, s);
+                e = launch_step(b->dargs + g.first, map, nmap, g.step_bits, g.step_grid, k, stop, g.r, g.NB, g.edge,
+                                g.storage, s);
             if (e != hipSuccess) break;
         }
     }

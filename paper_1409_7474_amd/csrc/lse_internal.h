@@ -174,8 +174,8 @@ struct Store {
     static hipError_t edge_g(const float *Is, void *g, int H, int W, hipStream_t s);
     static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
-    static hipError_t step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
-                           int r, int NB, int edge, hipStream_t s);
+    static hipError_t step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
+                           int k, int stop, int r, int NB, int edge, hipStream_t s);
     static hipError_t step_generic(const StepArgs &a, int NB, int edge, hipStream_t s);
     static hipError_t mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                             int NB, hipStream_t s);
@@ -211,10 +211,17 @@ size_t mbox_floats(int H, int W, int NB);
 hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float *boxes, hipStream_t s);
 // Step / normaliser launches over ImgArgs: map == nullptr runs image args[0]
 // (grid = step_launch_grid / mpass_groups); else map[blockIdx.x] holds
-// (image << unit_bits) | unit, or kNoTile.
+// (image << unit_bits) | unit, or kNoTile.  A step map built on the device
+// (batch visit list) has *nmap entries; workgroups past them have no work.
 unsigned step_launch_grid(int tiles);
-hipError_t launch_step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop, int r,
-                       int NB, int edge, int storage, hipStream_t s);
+hipError_t launch_step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid, int k,
+                       int stop, int r, int NB, int edge, int storage, hipStream_t s);
+// Batch visit list of one group for launch k: list[0] entries, then
+// (image << unit_bits) | tile, heavy tiles first.  wbase: nimg + 1 prefix
+// offsets of the images' heavy-record words.
+constexpr int kBatchPlanImages = 4096;
+hipError_t launch_batch_plan(const ImgArgs *args, const uint32_t *wbase, int nimg, int unit_bits, int k,
+                             uint32_t *list, hipStream_t s);
 hipError_t launch_step_generic(const StepArgs &a, int NB, int edge, int storage, hipStream_t s);
 hipError_t launch_dense_step(const StepArgs &a, int NB, int edge, int storage, hipStream_t s);
 hipError_t launch_plane_fill(const StepArgs &a, const uint32_t *bits, int raw, void *plane, int storage,

@@ -326,6 +326,97 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const ImgArgs *__res
     build_plan<kPlanThreads>(args[0], args[0].n0 + k, s_tot);
 }
 
+// Batch visit list of one group: the words of every image's heavy record,
+// concatenated (image i from wbase[i]), split over the threads; each word
+// gives the image's heavy tiles and their other neighbours for that image's
+// own iteration n0 + k (none once the image reached its target).  All heavy
+// tiles of the group come first, then the others, as in build_plan.
+__global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const ImgArgs *__restrict__ args,
+                                                                  const uint32_t *__restrict__ wbase, int nimg,
+                                                                  int unit_bits, int k, uint32_t *__restrict__ list) {
+    __shared__ uint32_t s_wb[kBatchPlanImages + 1];
+    __shared__ int s_tot[2 * (kPlanThreads / 64)];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i <= nimg; i += kPlanThreads) s_wb[i] = wbase[i];
+    __syncthreads();
+    const int tw = (int)s_wb[nimg];
+    const int per = (tw + kPlanThreads - 1) / kPlanThreads;
+    const int g0 = tid * per;
+    // Heavy and other active tiles of concatenated word g; img = its image.
+    auto word_masks = [&](int g, uint32_t &h, uint32_t &a, int &img) {
+        int lo = 0, hi = nimg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int)s_wb[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        img = lo;
+        h = a = 0u;
+        const ImgArgs &E = args[img];
+        const int n = E.n0 + k;
+        if (n >= E.target) return;
+        const int nw = (E.tiles + 31) >> 5, w = g - (int)s_wb[img];
+        const int valid = min(32, E.tiles - 32 * w);
+        const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+        const uint32_t *heavy = E.sched_mask + (size_t)(n % 3) * nw;
+        h = record_word(heavy, nw, w) & vm;
+        a = active_word(heavy, nw, (E.W + kFX - 1) / kFX, w) & vm & ~h;
+    };
+    int nh = 0, na = 0;
+    for (int i = 0; i < per; ++i) {
+        const int g = g0 + i;
+        if (g < tw) {
+            uint32_t h, a;
+            int img;
+            word_masks(g, h, a, img);
+            nh += __popc(h);
+            na += __popc(a);
+        }
+    }
+    int ih = nh, ia = na;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int vh = __shfl_up(ih, d, 64), va = __shfl_up(ia, d, 64);
+        if (lane >= d) {
+            ih += vh;
+            ia += va;
+        }
+    }
+    if (lane == 63) {
+        s_tot[wave] = ih;
+        s_tot[kPlanThreads / 64 + wave] = ia;
+    }
+    __syncthreads();
+    int bh = 0, ba = 0, NH = 0, NA = 0;
+    for (int v = 0; v < kPlanThreads / 64; ++v) {
+        if (v < wave) {
+            bh += s_tot[v];
+            ba += s_tot[kPlanThreads / 64 + v];
+        }
+        NH += s_tot[v];
+        NA += s_tot[kPlanThreads / 64 + v];
+    }
+    int oh = 1 + bh + ih - nh, oa = 1 + NH + ba + ia - na;
+    for (int i = 0; i < per; ++i) {
+        const int g = g0 + i;
+        if (g < tw) {
+            uint32_t h, a;
+            int img;
+            word_masks(g, h, a, img);
+            const uint32_t base = ((uint32_t)img << unit_bits) | (uint32_t)(32 * (g - (int)s_wb[img]));
+            for (; h; h &= h - 1u) list[oh++] = base + (uint32_t)(__ffs((int)h) - 1);
+            for (; a; a &= a - 1u) list[oa++] = base + (uint32_t)(__ffs((int)a) - 1);
+        }
+    }
+    if (tid == 0) list[0] = (uint32_t)(NH + NA);
+}
+
+hipError_t launch_batch_plan(const ImgArgs *args, const uint32_t *wbase, int nimg, int unit_bits, int k,
+                             uint32_t *list, hipStream_t s) {
+    if (nimg < 1 || nimg > kBatchPlanImages) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, args, wbase, nimg, unit_bits, k, list);
+    return hipGetLastError();
+}
+
 hipError_t launch_plan(const ImgArgs *dev_args, int k, hipStream_t s) {
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_args, k);
     return hipGetLastError();
@@ -416,13 +507,13 @@ hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop, int r,
-                       int NB, int edge, int storage, hipStream_t s) {
+hipError_t launch_step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid, int k,
+                       int stop, int r, int NB, int edge, int storage, hipStream_t s) {
     if (grid == 0) return hipSuccess;
     switch (storage) {
-        case LSE_F32: return Store<float>::step(args, map, unit_bits, grid, k, stop, r, NB, edge, s);
-        case LSE_F16: return Store<__half>::step(args, map, unit_bits, grid, k, stop, r, NB, edge, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::step(args, map, unit_bits, grid, k, stop, r, NB, edge, s);
+        case LSE_F32: return Store<float>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
+        case LSE_F16: return Store<__half>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
     }
     return hipErrorInvalidValue;
 }

@@ -517,8 +517,9 @@ template <int R, int NB, bool EDGE, typename ST>
 // At least 4 waves per SIMD: the B = 4 region kernels of the larger radii
 // otherwise take 129-134 VGPRs and drop to 3 (R = 6: 128, no spill).
 __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *__restrict__ args,
-                                                              const uint32_t *__restrict__ map, int unit_bits, int k,
-                                                              int stop) {
+                                                                 const uint32_t *__restrict__ map,
+                                                                 const int *__restrict__ nmap, int unit_bits, int k,
+                                                                 int stop) {
     using G = FastGeom<R, EDGE>;
     constexpr int TS = G::TS;
     extern __shared__ float smem[];
@@ -527,6 +528,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
     __shared__ int s_tile;
     __shared__ TileSum s_prev, s_all;  // region: the tile's latest contribution; its all-inside sums
     int ii, t;
+    if (nmap && (int)blockIdx.x >= *nmap) return;  // past the end of a batch visit list
     if (!batch_unit(map, unit_bits, ii, t)) return;
     const ImgArgs &E = args[ii];
     // Single image: the active tiles, heavy ones first, from the visit list
@@ -1343,23 +1345,23 @@ __global__ void plane_out_kernel(const ST *__restrict__ p0, const ST *__restrict
 // ---------------------------------------------------------------- launchers
 
 template <int R, int NB, bool EDGE, typename ST>
-static hipError_t launch_step_fast_t(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k,
-                                     int stop, hipStream_t s) {
+static hipError_t launch_step_fast_t(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits,
+                                     unsigned grid, int k, int stop, hipStream_t s) {
     const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
     const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE, ST>, sm);
     if (e != hipSuccess) return e;
     return launch_timed(step_fast_kernel<R, NB, EDGE, ST>, dim3(grid), dim3(kThreads), (uint32_t)sm, s, args, map,
-                        unit_bits, k, stop);
+                        nmap, unit_bits, k, stop);
 }
 
 template <int R, typename ST>
-static hipError_t launch_step_fast_r(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k,
-                                     int stop, int NB, int edge, hipStream_t s) {
-    if (edge) return launch_step_fast_t<R, 1, true, ST>(args, map, unit_bits, grid, k, stop, s);
+static hipError_t launch_step_fast_r(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits,
+                                     unsigned grid, int k, int stop, int NB, int edge, hipStream_t s) {
+    if (edge) return launch_step_fast_t<R, 1, true, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
     switch (NB) {
-        case 1: return launch_step_fast_t<R, 1, false, ST>(args, map, unit_bits, grid, k, stop, s);
-        case 2: return launch_step_fast_t<R, 2, false, ST>(args, map, unit_bits, grid, k, stop, s);
-        case 4: return launch_step_fast_t<R, 4, false, ST>(args, map, unit_bits, grid, k, stop, s);
+        case 1: return launch_step_fast_t<R, 1, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
+        case 2: return launch_step_fast_t<R, 2, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
+        case 4: return launch_step_fast_t<R, 4, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1465,14 +1467,14 @@ hipError_t Store<ST>::stats(const StepArgs &a, int NB, int raw, int slot, hipStr
 }
 
 template <typename ST>
-hipError_t Store<ST>::step(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
-                           int r, int NB, int edge, hipStream_t s) {
+hipError_t Store<ST>::step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
+                           int k, int stop, int r, int NB, int edge, hipStream_t s) {
     switch (r) {
-        case 3: return launch_step_fast_r<3, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
-        case 4: return launch_step_fast_r<4, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
-        case 5: return launch_step_fast_r<5, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
-        case 6: return launch_step_fast_r<6, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
-        case 7: return launch_step_fast_r<7, ST>(args, map, unit_bits, grid, k, stop, NB, edge, s);
+        case 3: return launch_step_fast_r<3, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
+        case 4: return launch_step_fast_r<4, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
+        case 5: return launch_step_fast_r<5, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
+        case 6: return launch_step_fast_r<6, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
+        case 7: return launch_step_fast_r<7, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
     }
     return hipErrorInvalidValue;
 }

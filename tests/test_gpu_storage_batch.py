@@ -176,12 +176,13 @@ def test_batch_equals_alone(dev, graph):
 
 @pytest.mark.parametrize("term", ["region", "region_intensity", "edge"])
 def test_single_image_skipping_equals_batch(dev, term):
-    """A single image visits only the tiles near the front: a visit list from
-    the normaliser pass (region, B = 4) or from its own pass (the other terms,
-    more than 4096 tiles here), or each workgroup's own scan of the heavy
-    record (small images: every other test).  A batch of one visits every
-    tile; both must agree bit for bit after 40 iterations, and after a
-    restart from a new mask."""
+    """A single image visits only the tiles near the front, from a visit
+    list built by the normaliser pass (region, B = 4) or by its own pass (the
+    other terms, more than 4096 tiles here); small images let each workgroup
+    scan the heavy record itself (every other test).  A batch of one builds
+    its list in a separate pass over the whole group.  The independent
+    builders must agree bit for bit after 40 iterations, and after a restart
+    from a new mask."""
     from paper_1409_7474_amd import lse
     sc = synth.scene_multiband(11, size=4160, bands=4, n_roofs=30, n_roads=3, height=4160, width=6240)
     img = _img(dev, sc.image)
@@ -204,6 +205,44 @@ def test_single_image_skipping_equals_batch(dev, term):
     batch.close()
     solo.close()
     other.close()
+
+
+@pytest.mark.parametrize("image,at", [(8, 25), (10, 65)])
+def test_uneven_image_late_step_parity(dev, image, at):
+    """Images of the batched workload (4 bands, 7 x 7) whose visited tiles
+    once missed neighbours of the image's top tile row (the heavy-record words
+    next to the record's ends read as zero): one-step parity with the FP64
+    oracle at the iteration where that first changed the result."""
+    shapes = synth.batch_shapes(0, n=64)
+    sc = synth.scene_batch_image(0, image, *shapes[image])
+    job = _make(dev, _img(dev, sc.image), sc.init_region, sigma=1.0, ksize=7)
+    job.run(at)
+    x = np.asarray(sc.image, np.float32).astype(np.float64)
+    for _ in range(2):
+        err, _, _ = one_step(job, x, sigma=1.0, ts=7)
+        assert err <= LSF_TOL
+
+
+@pytest.mark.parametrize("term", ["region", "edge"])
+def test_uneven_images_alone_equal_batch(dev, term):
+    """Eight uneven images of the batched workload, 150 iterations: each
+    image's single-image run (visit list from the normaliser pass, or each
+    workgroup's own scan of the heavy record) equals the batch (visit list
+    over the group) bit for bit."""
+    from paper_1409_7474_amd import lse
+    shapes = synth.batch_shapes(0, n=64)
+    pick = [8, 10, 12, 13, 17, 18, 19, 22]
+    scs = [synth.scene_batch_image(0, i, *shapes[i]) for i in pick]
+    init = [sc.init_region if term == "region" else sc.init_edge for sc in scs]
+    alone = [_make(dev, _img(dev, sc.image), m, term=term, sigma=1.0, ksize=7) for sc, m in zip(scs, init)]
+    for j in alone:
+        j.run(150)
+    jobs = [_make(dev, _img(dev, sc.image), m, term=term, sigma=1.0, ksize=7) for sc, m in zip(scs, init)]
+    batch = lse.Batch(jobs)
+    batch.run(150)
+    for i in range(len(pick)):
+        _assert_same(_state(jobs[i]), _state(alone[i]), f"image {pick[i]}")
+    batch.close()
 
 
 def test_batch_interleaves_with_single_steps(dev):

@@ -858,13 +858,15 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
-// Word w of a record of nw words, or zero outside it.  The address is
-// clamped and the range applied in ALU code: two adjacent word loads may be
-// merged into one multi-word load, and a buffer load that lies partly outside
-// its range returns zeros for all of its words.
-__device__ __forceinline__ uint32_t record_word(const uint32_t *__restrict__ rec, int nw, int w) {
-    const uint32_t v = rec[min(max(w, 0), nw - 1)];
-    return (w >= 0 && w < nw) ? v : 0u;
+// Word w of a record (buffer resource over its words), or zero outside it:
+// single-word buffer loads return zero outside their range.  The offset
+// passes through an empty asm statement so that the compiler cannot merge
+// loads of neighbouring words into one multi-word load, which would return
+// zeros for all of its words when one of them lies outside.
+__device__ __forceinline__ uint32_t record_word(__amdgpu_buffer_rsrc_t rec, int w) {
+    uint32_t off = (uint32_t)w * 4u;
+    asm volatile("" : "+v"(off));
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rec, off, 0, 0);
 }
 
 // Active tiles of word w of the heavy-tile record (nw words): a tile is
@@ -872,14 +874,14 @@ __device__ __forceinline__ uint32_t record_word(const uint32_t *__restrict__ rec
 // row) was heavy.  The record bits at tile offsets dy * ntx + dx around the
 // word are read as funnel shifts of word pairs; all eighteen loads are
 // issued straight away (no branches), then combined.
-__device__ __forceinline__ uint32_t active_word(const uint32_t *__restrict__ heavy, int nw, int ntx, int w) {
+__device__ __forceinline__ uint32_t active_word(__amdgpu_buffer_rsrc_t heavy, int nw, int ntx, int w) {
     const int base = 32 * w;
     uint32_t lo[9], hi[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int wq = (base + (k / 3 - 1) * ntx + (k % 3 - 1)) >> 5;  // floor division (arithmetic shift)
-        lo[k] = record_word(heavy, nw, wq);
-        hi[k] = record_word(heavy, nw, wq + 1);
+        lo[k] = record_word(heavy, wq);
+        hi[k] = record_word(heavy, wq + 1);
     }
     // Tiles of this word in the first / last column of the tile grid.
     uint32_t first_col = 0u, last_col = 0u;
@@ -911,14 +913,15 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
     const int nw = (ntiles + 31) >> 5;
     const int w0 = lane * kPer;
     uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
+    const __amdgpu_buffer_rsrc_t hr = image_rsrc(heavy, (uint32_t)nw * 4u);
     int nh = 0, na = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const int w = w0 + i;
         const int valid = max(0, min(32, ntiles - 32 * w));  // 0 past the record
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        hw[i] = record_word(heavy, nw, w) & vm;
-        aw[i] = active_word(heavy, nw, ntx, w) & vm & ~hw[i];
+        hw[i] = record_word(hr, w) & vm;
+        aw[i] = active_word(hr, nw, ntx, w) & vm & ~hw[i];
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
     }
@@ -968,15 +971,15 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
 template <int NT>
 __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
-    const uint32_t *heavy = E.sched_mask + (size_t)(n % 3) * nw;
+    const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (nw + NT - 1) / NT;
     const int w0 = tid * per;
     auto word_masks = [&](int w, uint32_t &h, uint32_t &a) {
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        h = record_word(heavy, nw, w) & vm;
-        a = active_word(heavy, nw, ntx, w) & vm & ~h;
+        h = record_word(hr, w) & vm;
+        a = active_word(hr, nw, ntx, w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {

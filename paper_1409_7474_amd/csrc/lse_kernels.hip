@@ -357,9 +357,9 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const ImgArgs 
         const int nw = (E.tiles + 31) >> 5, w = g - (int)s_wb[img];
         const int valid = min(32, E.tiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        const uint32_t *heavy = E.sched_mask + (size_t)(n % 3) * nw;
-        h = record_word(heavy, nw, w) & vm;
-        a = active_word(heavy, nw, (E.W + kFX - 1) / kFX, w) & vm & ~h;
+        const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
+        h = record_word(hr, w) & vm;
+        a = active_word(hr, nw, (E.W + kFX - 1) / kFX, w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {

@@ -207,19 +207,23 @@ def test_single_image_skipping_equals_batch(dev, term):
     other.close()
 
 
-@pytest.mark.parametrize("image,at", [(8, 25), (10, 65)])
-def test_uneven_image_late_step_parity(dev, image, at):
-    """Images of the batched workload (4 bands, 7 x 7) whose visited tiles
-    once missed neighbours of the image's top tile row (the heavy-record words
-    next to the record's ends read as zero): one-step parity with the FP64
-    oracle at the iteration where that first changed the result."""
+@pytest.mark.parametrize("term,image,at", [("region", 8, 25), ("region", 10, 65), ("edge", 8, 40),
+                                           ("edge", 12, 60)])
+def test_uneven_image_late_step_parity(dev, term, image, at):
+    """Images of the batched workload (4 bands, 7 x 7), deep into the run,
+    where most tiles are settled and skipped: one-step parity with the FP64
+    oracle, which evaluates every pixel.  The region cases are where the
+    visited tiles once missed neighbours of the image's top tile row (record
+    words next to the record's ends read as zero)."""
     shapes = synth.batch_shapes(0, n=64)
     sc = synth.scene_batch_image(0, image, *shapes[image])
-    job = _make(dev, _img(dev, sc.image), sc.init_region, sigma=1.0, ksize=7)
+    init = sc.init_region if term == "region" else sc.init_edge
+    job = _make(dev, _img(dev, sc.image), init, term=term, sigma=1.0, ksize=7)
     job.run(at)
     x = np.asarray(sc.image, np.float32).astype(np.float64)
+    g = oracle.edge_map(x, 1.0, 9, 255.0) if term == "edge" else None
     for _ in range(2):
-        err, _, _ = one_step(job, x, sigma=1.0, ts=7)
+        err, _, _ = one_step(job, x, term=term, sigma=1.0, ts=7, g=g)
         assert err <= LSF_TOL
 
 

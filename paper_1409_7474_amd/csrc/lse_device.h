@@ -546,7 +546,7 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
 }
 
 
-constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 8;
+constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 32;
 
 // One thread of a step's lead workgroup: the image values of the pixel that
 // maximised |D| for this iteration (key `mkey`, from its statistics slot

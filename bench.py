@@ -9,8 +9,9 @@ region-term iterations, then lse_init + 200 edge-term iterations, with the
 image already resident in HBM.  `value` = pixel-iterations per second over
 the K timed steps (2 x 200 x 4096^2 per step).  The line also carries
   * roofline -- algorithmic HBM bytes of the fused region step kernel per
-    launch / its mean launch time (HIP events on the launch stream, over the
-    timed region), against the MI355X HBM peak of 8 TB/s;
+    launch / its mean launch time (HIP events carried by the dispatch of one
+    launch in 8 on the launch stream, over the timed region), against the
+    MI355X HBM peak of 8 TB/s;
   * cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same job
     (a few iterations of each term on the full image), on this host's cores;
   * batched -- 64 uneven images (sides 512-2048, 4 bands, sigma 1 / 7 x 7,
@@ -356,7 +357,11 @@ def main():
     ws_ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
     mask_out = torch.empty((h, w), dtype=torch.uint8, device=dev)
 
-    def job(profile_into=None, flags=lse.PROFILE_TIMING):
+    # Kernel durations come from events carried by the dispatch of one step
+    # and normaliser launch in 8 (iterations 7, 15, ...): the events of a
+    # timed launch cost the device a few microseconds, so timing every launch
+    # would lower the throughput being measured.
+    def job(profile_into=None, flags=lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(3)):
         for t in terms:
             ctx = lse.lse_init(params[t], img.data_ptr(), masks[t].data_ptr(), ws_ptr, nbytes, s)
             if profile_into is not None:

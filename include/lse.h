@@ -128,8 +128,12 @@ typedef struct {
     int64_t counted_steps;
 } lse_profile_t;
 
-/* lse_profile flags. */
+/* lse_profile flags.  LSE_PROFILE_SAMPLE(k), k = 0..15, or-ed with
+ * LSE_PROFILE_TIMING, times one launch in 2^k of each kernel (launches
+ * 2^k - 1, 2 * 2^k - 1, ...): the events of a timed launch cost the device a
+ * few microseconds, so a sample keeps them out of the throughput. */
 enum { LSE_PROFILE_TIMING = 1, LSE_PROFILE_COUNT = 2 };
+#define LSE_PROFILE_SAMPLE(k) ((int32_t)(k) << 8)
 
 typedef struct lse_ctx lse_ctx; /* opaque, host-side */
 
@@ -180,7 +184,9 @@ lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream);
 lse_status lse_check(const lse_ctx *c, void *stream);
 
 /* Profiling of this context; `flags` (0 = off) resets the totals.
- * LSE_PROFILE_TIMING: HIP events around every kernel launch.
+ * LSE_PROFILE_TIMING: HIP events carried by the dispatch of every step and
+ *   normaliser launch (or of one in 2^k with LSE_PROFILE_SAMPLE(k)): the
+ *   kernel's own start and end.
  * LSE_PROFILE_COUNT: after every step, an extra kernel counts the pixels whose
  *   image value that step needed (the + side of the new LSF for the region
  *   sums, and pixels with |grad phi| != 0 for the update) -- the algorithmic

@@ -48,6 +48,7 @@ struct lse_ctx {
     std::vector<Ev> pending, pool;
     double prof_ms[2];
     long long prof_n[2];
+    long long prof_seen[2];  // launches of each kind since profiling was enabled (sampling)
 };
 
 // A set of contexts advanced together: one step launch (and, for B > 1, one
@@ -274,6 +275,8 @@ lse_status dev_status(hipError_t e) { return e == hipSuccess ? LSE_OK : LSE_ERR_
 
 void prof_begin(lse_ctx *c, int kind, hipStream_t s, lse_ctx::Ev *ev) {
     if (!(c->prof & LSE_PROFILE_TIMING)) return;
+    const long long period = 1ll << ((c->prof >> 8) & 15);
+    if (++c->prof_seen[kind] % period != 0) return;
     if (c->pool.empty()) {
         lse_ctx::Ev e;
         if (hipEventCreate(&e.a) != hipSuccess) return;
@@ -445,6 +448,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     c->prof = 0;
     c->prof_ms[0] = c->prof_ms[1] = 0.0;
     c->prof_n[0] = c->prof_n[1] = 0;
+    c->prof_seen[0] = c->prof_seen[1] = 0;
     build_taps(c->host_taps, p->sigma, c->ts, p->sigma_img, c->ts1);
     {
         ImgArgs &A = c->host_args;
@@ -587,12 +591,13 @@ lse_status lse_check(const lse_ctx *c, void *stream) {
 }
 
 lse_status lse_profile(lse_ctx *c, int32_t flags) {
-    if (!c || (flags & ~(LSE_PROFILE_TIMING | LSE_PROFILE_COUNT))) return LSE_ERR_INVALID_ARG;
+    if (!c || (flags & ~(LSE_PROFILE_TIMING | LSE_PROFILE_COUNT | LSE_PROFILE_SAMPLE(15)))) return LSE_ERR_INVALID_ARG;
     if (flags) {
         for (auto &e : c->pending) c->pool.push_back(e);
         c->pending.clear();
         c->prof_ms[0] = c->prof_ms[1] = 0.0;
         c->prof_n[0] = c->prof_n[1] = 0;
+        c->prof_seen[0] = c->prof_seen[1] = 0;
         if (launch_reset_profile(c->st, c->last_stream) != hipSuccess) return LSE_ERR_DEVICE;
     }
     c->prof = flags;

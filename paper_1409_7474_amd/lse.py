@@ -66,6 +66,11 @@ class lse_profile_t(ctypes.Structure):
 
 PROFILE_TIMING = 1
 PROFILE_COUNT = 2
+
+
+def PROFILE_SAMPLE(k: int) -> int:
+    """With PROFILE_TIMING: time one launch in 2**k of each kernel."""
+    return (int(k) & 15) << 8
 BATCH_GRAPH = 1
 
 
@@ -192,7 +197,8 @@ def lse_check(ctx, stream: int = 0) -> int:
 
 
 def lse_profile(ctx, flags: int) -> None:
-    """flags: 0 off, PROFILE_TIMING (1), PROFILE_COUNT (2), or both."""
+    """flags: 0 off, PROFILE_TIMING (1), PROFILE_COUNT (2), or both; with
+    PROFILE_TIMING, PROFILE_SAMPLE(k) times one launch in 2**k."""
     _check(load().lse_profile(ctx, int(flags)), "lse_profile")
 
 

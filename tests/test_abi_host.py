@@ -138,6 +138,7 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lse_stats(None, None, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_profile(None, 1) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_profile(None, 8) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_profile(None, 1 | (3 << 8)) == lse.LSE_ERR_INVALID_ARG  # valid flags, no context
     assert lib.lse_step_bytes_per_pixel(None) == 0.0
     lib.lse_destroy(None)
 

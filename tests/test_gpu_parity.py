@@ -267,3 +267,18 @@ def test_profile_counts_needed_pixels(dev):
         assert p["counted_steps"] == 3 and p["needed_pixels"] == expect, (term, p, expect)
         if term == "region":
             assert quiet_px > 0  # the case is exercised
+
+
+def test_profile_timing_samples(dev):
+    """LSE_PROFILE_SAMPLE(k): one launch in 2^k of each kernel carries timing
+    events (launches 2^k - 1, 2 * 2^k - 1, ...); every launch with k = 0."""
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_tiny(1)
+    img = torch.tensor(np.asarray(sc.image, np.float32), device=dev)
+    for flags, want in ((lse.PROFILE_TIMING, 12), (lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(2), 3)):
+        job = _make(dev, img, sc.init_region)
+        job.profile(flags)
+        job.run(12)
+        p = job.profile_read()
+        assert p["step_launches"] == want and p["step_ms"] > 0.0, p
+        job.close()

@@ -238,13 +238,18 @@ lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *target
 
 /* Up to `iters` iterations of every context of the batch (each stops at its
  * target, and with stop_when_unchanged at its Step-5 fixed point), enqueued
- * on `stream` without synchronising.  LSE_BATCH_GRAPH: the launch sequence is
- * captured once into a HIP graph (re-captured when iters or the stop flag
- * change) and launched as one graph; needs a non-default stream. */
+ * on `stream` without synchronising.  With more than one kernel family, each
+ * family's launches go to a stream of the batch's own (created with it, at
+ * the default priority), forked from `stream` and joined back to it, so the
+ * families overlap on the device; work enqueued on `stream` afterwards
+ * starts after all of them.  LSE_BATCH_GRAPH: the launch sequence is captured
+ * once into a HIP graph (re-captured when iters or the stop flag change) and
+ * launched as one graph; needs a non-default stream. */
 lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchanged, int32_t flags, void *stream);
 
-/* Release the batch (synchronises the stream of its last graph launch, if
- * any).  The table memory and the contexts stay the caller's. */
+/* Release the batch (synchronises the stream of its last run when it used a
+ * graph or streams of its own).  The table memory and the contexts stay the
+ * caller's. */
 void lse_batch_destroy(lse_batch *b);
 
 /* Human-readable name of a status code. */

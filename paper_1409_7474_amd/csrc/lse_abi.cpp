@@ -74,6 +74,17 @@ struct lse_batch {
     hipStream_t last_stream;
     hipGraphExec_t exec;
     int exec_iters, exec_stop;
+    // Several kernel families: each group runs on a stream of its own
+    // (default priority), forked from and joined to the caller's stream, so
+    // that the groups' latency-bound launches overlap on the device.
+    std::vector<hipStream_t> gstream;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    ~lse_batch() {
+        for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : join) (void)hipEventDestroy(ev);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace {
@@ -817,6 +828,26 @@ lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *target
     b->exec = nullptr;
     b->exec_iters = -1;
     b->exec_stop = -1;
+    if (b->groups.size() > 1) {
+        if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+            delete b;
+            return LSE_ERR_DEVICE;
+        }
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                delete b;
+                return LSE_ERR_DEVICE;
+            }
+            b->gstream.push_back(st);
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                delete b;
+                return LSE_ERR_DEVICE;
+            }
+            b->join.push_back(ev);
+        }
+    }
     const hipStream_t s = as_stream(stream);
     b->last_stream = s;
     hipError_t e = hipMemcpyAsync(b->dargs, b->hargs.data(), b->hargs.size() * sizeof(ImgArgs),
@@ -835,22 +866,42 @@ namespace {
 
 hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
     hipError_t e = launch_batch_prepare(b->dargs, (int)b->cs.size(), s);
+    // Several groups: fork their streams from `s` after the prepare kernel
+    // and join them back at the end (inside a graph capture, these event
+    // records and waits make the group streams part of the captured graph).
+    const bool multi = !b->gstream.empty();
+    if (multi) {
+        if (e == hipSuccess) e = hipEventRecord(b->fork, s);
+        for (size_t gi = 0; gi < b->gstream.size() && e == hipSuccess; ++gi)
+            e = hipStreamWaitEvent(b->gstream[gi], b->fork, 0);
+    }
     for (int k = 0; k < iters && e == hipSuccess; ++k) {
-        for (const auto &g : b->groups) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            const auto &g = b->groups[gi];
+            const hipStream_t gs = multi ? b->gstream[gi] : s;
             uint32_t *map = b->dmap + g.step_map;
             const int *nmap = nullptr;
             if (g.visit_list) {
-                e = launch_batch_plan(b->dargs + g.first, b->dmap + g.wbase_map, g.count, g.step_bits, k, map, s);
+                e = launch_batch_plan(b->dargs + g.first, b->dmap + g.wbase_map, g.count, g.step_bits, k, map, gs);
                 nmap = reinterpret_cast<const int *>(map);
                 map += 1;
             }
             if (e == hipSuccess && g.mpass_grid)
                 e = launch_mpass(b->dargs + g.first, b->dmap + g.mpass_map, g.mpass_bits, g.mpass_grid, k, stop, g.NB,
-                                 g.storage, s);
+                                 g.storage, gs);
             if (e == hipSuccess)
                 e = launch_step(b->dargs + g.first, map, nmap, g.step_bits, g.step_grid, k, stop, g.r, g.NB, g.edge,
-                                g.storage, s);
+                                g.storage, gs);
             if (e != hipSuccess) break;
+        }
+    }
+    if (multi) {
+        for (size_t gi = 0; gi < b->gstream.size(); ++gi) {
+            // Join even after an error, so that no group stream is left
+            // forked (or a capture left open on it).
+            const hipError_t r = hipEventRecord(b->join[gi], b->gstream[gi]);
+            const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(s, b->join[gi], 0) : r;
+            if (e == hipSuccess) e = w;
         }
     }
     return e;
@@ -909,10 +960,9 @@ lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchange
 
 void lse_batch_destroy(lse_batch *b) {
     if (!b) return;
-    if (b->exec) {
-        (void)hipStreamSynchronize(b->last_stream);
-        (void)hipGraphExecDestroy(b->exec);
-    }
+    // The caller's stream joins the group streams: once it is idle, so are they.
+    if (b->exec || !b->gstream.empty()) (void)hipStreamSynchronize(b->last_stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
     delete b;
 }
 

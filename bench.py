@@ -5,9 +5,12 @@
 
 One step = one whole job on the 4096 x 4096 x 4 multiband scene (40 roofs,
 6 roads, noise 0.03; sigma 1.5, 11 x 11 template, dt 15): lse_init + 200
-region-term iterations, then lse_init + 200 edge-term iterations, with the
-image already resident in HBM.  `value` = pixel-iterations per second over
-the K timed steps (2 x 200 x 4096^2 per step).  The line also carries
+region-term iterations and lse_init + 200 edge-term iterations, with the
+image already resident in HBM.  The two solves are independent and run on two
+HIP streams at once (their latency-bound steps overlap on the device);
+`sequential` times the same job with one solve after the other on one
+stream.  `value` = pixel-iterations per second over the K timed steps
+(2 x 200 x 4096^2 per step).  The line also carries
   * roofline -- algorithmic HBM bytes of the fused region step kernel per
     launch / its mean launch time (HIP events carried by the dispatch of one
     launch in 8 on the launch stream, over the timed region), against the
@@ -344,32 +347,48 @@ def main():
     scene = make_scene(args.workload)
     h, w, b = scene.image.shape
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    s = int(stream.cuda_stream)
     img = torch.tensor(scene.image, dtype=torch.float32, device=dev)
     masks = {"region": torch.tensor(scene.init_region, device=dev),
              "edge": torch.tensor(scene.init_edge, device=dev)}
     params = {t: lse.make_params(h, w, b, term=t, sigma=sigma, ksize=ksize) for t in terms}
     for p in params.values():
         p.image_dtype = 0
-    nbytes = max(lse.lse_workspace_bytes(p) for p in params.values())
-    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-    ws_ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
-    mask_out = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    # The solves of the two terms are independent: each has its own workspace
+    # and HIP stream (default priority), so their latency-bound steps overlap
+    # on the device.  A sequential pass on one stream is timed as well.
+    streams = {t: torch.cuda.Stream(dev) for t in terms}
+    ws, ws_ptr, nbytes = {}, {}, {}
+    for t in terms:
+        nbytes[t] = lse.lse_workspace_bytes(params[t])
+        ws[t] = torch.empty(nbytes[t] + 256, dtype=torch.uint8, device=dev)
+        ws_ptr[t] = ws[t].data_ptr() + ((-ws[t].data_ptr()) % 256)
+    mask_out = {t: torch.empty((h, w), dtype=torch.uint8, device=dev) for t in terms}
+    chunk = 20  # iterations enqueued per term in turn, so both streams start at once
 
     # Kernel durations come from events carried by the dispatch of one step
     # and normaliser launch in 8 (iterations 7, 15, ...): the events of a
     # timed launch cost the device a few microseconds, so timing every launch
     # would lower the throughput being measured.
-    def job(profile_into=None, flags=lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(3)):
+    def job(profile_into=None, flags=lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(3), concurrent=True):
+        one = int(streams[terms[0]].cuda_stream)
+        sid = {t: (int(streams[t].cuda_stream) if concurrent else one) for t in terms}
+        ctx = {}
         for t in terms:
-            ctx = lse.lse_init(params[t], img.data_ptr(), masks[t].data_ptr(), ws_ptr, nbytes, s)
+            ctx[t] = lse.lse_init(params[t], img.data_ptr(), masks[t].data_ptr(), ws_ptr[t], nbytes[t], sid[t])
             if profile_into is not None:
-                lse.lse_profile(ctx, flags)
-            lse.lse_run(ctx, iters, False, s)
-            lse.lse_mask(ctx, mask_out.data_ptr(), s)
+                lse.lse_profile(ctx[t], flags)
+        if concurrent:
+            for k0 in range(0, iters, chunk):
+                for t in terms:
+                    lse.lse_run(ctx[t], min(chunk, iters - k0), False, sid[t])
+        else:
+            for t in terms:
+                lse.lse_run(ctx[t], iters, False, sid[t])
+        for t in terms:
+            lse.lse_mask(ctx[t], mask_out[t].data_ptr(), sid[t])
+        for t in terms:
             if profile_into is not None:
-                p = lse.lse_profile_read(ctx)
+                p = lse.lse_profile_read(ctx[t])
                 acc = profile_into.setdefault(t, {"step_ms": 0.0, "step_n": 0, "mpass_ms": 0.0, "mpass_n": 0,
                                                   "needed_px": 0, "counted": 0})
                 acc["step_ms"] += p.step_ms
@@ -378,8 +397,10 @@ def main():
                 acc["mpass_n"] += p.mpass_launches
                 acc["needed_px"] += p.needed_pixels
                 acc["counted"] += p.counted_steps
-                acc["dense_bytes_per_px"] = lse.lse_step_bytes_per_pixel(ctx)
-            lse.lse_destroy(ctx)
+                acc["dense_bytes_per_px"] = lse.lse_step_bytes_per_pixel(ctx[t])
+        torch.cuda.synchronize()
+        for t in terms:
+            lse.lse_destroy(ctx[t])
 
     for _ in range(args.warmup):
         job()
@@ -393,7 +414,18 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     px_it = h * w * iters * len(terms) * args.steps
     value = px_it / elapsed / 1e6
-    inside = float(mask_out.float().mean().item())
+    inside = {t: round(float(mask_out[t].float().mean().item()), 4) for t in terms}
+    concurrent_masks = {t: mask_out[t].clone() for t in terms}
+    # The same job with the two solves one after the other on one stream.
+    prof_seq = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        job(prof_seq, concurrent=False)
+    torch.cuda.synchronize()
+    seq_elapsed = time.perf_counter() - t0
+    sequential = {"ms_per_step": round(seq_elapsed * 1e3 / args.steps, 3),
+                  "value": round(px_it / seq_elapsed / 1e6, 1),
+                  "masks_equal_to_concurrent": all(torch.equal(concurrent_masks[t], mask_out[t]) for t in terms)}
 
     # Algorithmic bytes of the step kernel: an untimed replay of the same
     # (deterministic) job counts, per step, the pixels whose image value the
@@ -409,19 +441,27 @@ def main():
         return per_px * c["needed_px"] / max(c["counted"], 1) + 2.0 * h * w / 8.0
 
     dom = "region" if "region" in prof else terms[0]
-    pr = prof[dom]
-    step_ms = pr["step_ms"] / max(pr["step_n"], 1)
-    alg = step_bytes(dom)
-    achieved = alg / (step_ms * 1e-3) / 1e9
     kname = f"lse::step_fast_kernel<{ksize // 2}, {(4 if b == 3 else b) if dom == 'region' else 1}, " \
             f"{'false' if dom == 'region' else 'true'}, float>"
     traffic, traffic_src = measured_traffic(kname)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+
+    def roofline_of(pf):
+        pr = pf[dom]
+        step_ms = pr["step_ms"] / max(pr["step_n"], 1)
+        alg = step_bytes(dom)
+        achieved = alg / (step_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "kernel": f"step_fast_kernel ({dom} term, B={b})", "mean_launch_us": round(step_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": int(alg),
                 "needed_pixel_fraction": round(counted[dom]["needed_px"] / max(counted[dom]["counted"], 1) / (h * w),
                                                4)}
+
+    # roofline: the region step as it runs in the timed (concurrent) job,
+    # sharing the device with the edge solve; roofline_alone: the same kernel
+    # in the timed sequential pass, with the device to itself.
+    roofline = roofline_of(prof)
+    roofline_alone = roofline_of(prof_seq)
     per_term = {}
     for t, pr_t in prof.items():
         ms_t = pr_t["step_ms"] / max(pr_t["step_n"], 1)
@@ -440,9 +480,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{h}x{w}x{b} multiband scene ({args.workload}), "
                                f"{'+'.join(terms)} terms, {iters} iterations each, "
-                               f"sigma {sigma}, {ksize}x{ksize} template, dt 15, image resident in HBM",
+                               f"sigma {sigma}, {ksize}x{ksize} template, dt 15, image resident in HBM; "
+                               f"the {len(terms)} independent solves on concurrent HIP streams",
                    "global_batch": 1, "parallelism": "single GPU"},
-        "roofline": roofline, "per_term": per_term, "final_mask_inside_fraction": round(inside, 4),
+        "sequential": sequential,
+        "roofline": roofline, "roofline_alone": roofline_alone, "per_term": per_term, "final_mask_inside_fraction": inside,
         "gpu": torch.cuda.get_device_name(0),
     }
     if not args.no_cpu_baseline:

@@ -1,7 +1,8 @@
 """Throughput benchmark of the fast level set evolution on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
-                    [--sections batched,precision]
+                    [--job both|concurrent|sequential]
+                    [--sections batched,precision,serving]
 
 One step = one whole job on the 4096 x 4096 x 4 multiband scene (40 roofs,
 6 roads, noise 0.03; sigma 1.5, 11 x 11 template, dt 15): lse_init + 200
@@ -9,7 +10,8 @@ region-term iterations and lse_init + 200 edge-term iterations, with the
 image already resident in HBM.  The two solves are independent and run on two
 HIP streams at once (their latency-bound steps overlap on the device);
 `sequential` times the same job with one solve after the other on one
-stream.  `value` = pixel-iterations per second over the K timed steps
+stream (--job concurrent or --job sequential times one of the two only;
+a kernel trace of one of them has one launch configuration).  `value` = pixel-iterations per second over the K timed steps
 (2 x 200 x 4096^2 per step).  The line also carries
   * roofline -- algorithmic HBM bytes of the fused region step kernel per
     launch / its mean launch time (HIP events carried by the dispatch of one
@@ -57,6 +59,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--job", default="both", choices=["both", "concurrent", "sequential"],
+                    help="timed job: solves on concurrent streams (both: and a timed sequential pass after it), "
+                         "or one after the other on one stream")
     ap.add_argument("--sections", default="batched,precision,serving",
                     help="extra sections after the headline job: batched, precision, serving (comma-separated; "
                          "empty for none)")
@@ -402,13 +407,14 @@ def main():
         for t in terms:
             lse.lse_destroy(ctx[t])
 
+    conc = args.job != "sequential"
     for _ in range(args.warmup):
-        job()
+        job(concurrent=conc)
     torch.cuda.synchronize()
     prof = {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        job(prof)
+        job(prof, concurrent=conc)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
@@ -417,22 +423,24 @@ def main():
     inside = {t: round(float(mask_out[t].float().mean().item()), 4) for t in terms}
     concurrent_masks = {t: mask_out[t].clone() for t in terms}
     # The same job with the two solves one after the other on one stream.
-    prof_seq = {}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        job(prof_seq, concurrent=False)
-    torch.cuda.synchronize()
-    seq_elapsed = time.perf_counter() - t0
-    sequential = {"ms_per_step": round(seq_elapsed * 1e3 / args.steps, 3),
-                  "value": round(px_it / seq_elapsed / 1e6, 1),
-                  "masks_equal_to_concurrent": all(torch.equal(concurrent_masks[t], mask_out[t]) for t in terms)}
+    prof_seq, sequential = prof, None
+    if args.job == "both":
+        prof_seq = {}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            job(prof_seq, concurrent=False)
+        torch.cuda.synchronize()
+        seq_elapsed = time.perf_counter() - t0
+        sequential = {"ms_per_step": round(seq_elapsed * 1e3 / args.steps, 3),
+                      "value": round(px_it / seq_elapsed / 1e6, 1),
+                      "masks_equal_to_concurrent": all(torch.equal(concurrent_masks[t], mask_out[t]) for t in terms)}
 
     # Algorithmic bytes of the step kernel: an untimed replay of the same
     # (deterministic) job counts, per step, the pixels whose image value the
     # step needs; each costs one pixel of image (region: B x 4 bytes) or edge
     # map (4 bytes); the binary state adds one bit read and one bit written.
     counted = {}
-    job(counted, lse.PROFILE_COUNT)
+    job(counted, lse.PROFILE_COUNT, concurrent=conc)
     torch.cuda.synchronize()
 
     def step_bytes(t):
@@ -457,11 +465,11 @@ def main():
                 "needed_pixel_fraction": round(counted[dom]["needed_px"] / max(counted[dom]["counted"], 1) / (h * w),
                                                4)}
 
-    # roofline: the region step as it runs in the timed (concurrent) job,
-    # sharing the device with the edge solve; roofline_alone: the same kernel
-    # in the timed sequential pass, with the device to itself.
+    # roofline: the region step as it runs in the timed job (with concurrent
+    # solves it shares the device with the edge solve); roofline_alone: the
+    # same kernel in a sequential pass, with the device to itself.
     roofline = roofline_of(prof)
-    roofline_alone = roofline_of(prof_seq)
+    roofline_alone = roofline_of(prof_seq) if prof_seq else None
     per_term = {}
     for t, pr_t in prof.items():
         ms_t = pr_t["step_ms"] / max(pr_t["step_n"], 1)
@@ -481,7 +489,8 @@ def main():
         "config": {"workload": f"{h}x{w}x{b} multiband scene ({args.workload}), "
                                f"{'+'.join(terms)} terms, {iters} iterations each, "
                                f"sigma {sigma}, {ksize}x{ksize} template, dt 15, image resident in HBM; "
-                               f"the {len(terms)} independent solves on concurrent HIP streams",
+                               + (f"the {len(terms)} independent solves on concurrent HIP streams" if conc
+                                  else f"the {len(terms)} solves one after the other on one HIP stream"),
                    "global_batch": 1, "parallelism": "single GPU"},
         "sequential": sequential,
         "roofline": roofline, "roofline_alone": roofline_alone, "per_term": per_term, "final_mask_inside_fraction": inside,

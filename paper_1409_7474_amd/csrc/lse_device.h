@@ -623,37 +623,53 @@ __device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, int (&l
     for (int c = 0; c < NCH; ++c) lut[c] = __float_as_int(taps->lut[c][lane]);
 }
 
-// Horizontal Gaussian of a binary row, as hconv_bits; must be called with all
-// 64 lanes active (ds_bpermute).  `border` (uniform) enables the zero-padding
-// correction, needed only by tiles that touch the left or right image edge.
-template <int R, int NCH>
-__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, int x, int W, bool border,
-                                            const int (&lut)[NCH], const float *__restrict__ cum) {
+// Zero padding of the horizontal taps at image column x (only where the
+// taps reach outside the image, `border`): the window bits outside the image
+// are set, as if they were inside, and their weight is subtracted.  It depends
+// on the column alone, so a caller computes it once for its lane.
+struct HPad {
+    uint32_t orm;  // window bits forced to one
+    float corr;    // weight of those bits
+};
+
+template <int R>
+__device__ __forceinline__ HPad hpad_of(int x, int W, bool border, const float *__restrict__ cum) {
     constexpr int TS = 2 * R + 1;
     constexpr uint32_t FULL = (1u << TS) - 1u;
-    const int ws = xb - R;
-    const int wi = ws >> 5;
-    uint32_t win = __builtin_amdgcn_alignbit(row[wi + 1], row[wi], (uint32_t)(ws & 31)) & FULL;
-    float corr = 0.f;
+    HPad p{0u, 0.f};
     if (border) {
         const int left = min(R - x, TS);
         const int right = min(x + R - (W - 1), TS);
         if (left > 0) {
-            win |= (1u << left) - 1u;
-            corr = cum[left];
+            p.orm |= (1u << left) - 1u;
+            p.corr = cum[left];
         }
         if (right > 0) {
-            win |= FULL & ~((1u << (TS - right)) - 1u);
-            corr += cum[right];
+            p.orm |= FULL & ~((1u << (TS - right)) - 1u);
+            p.corr += cum[right];
         }
     }
+    return p;
+}
+
+// Horizontal Gaussian of a binary row, as hconv_bits; must be called with all
+// 64 lanes active (ds_bpermute).  `pad` is the lane's zero-padding correction
+// (hpad_of; all zero away from the left and right image edges).
+template <int R, int NCH>
+__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, HPad pad, const int (&lut)[NCH]) {
+    constexpr int TS = 2 * R + 1;
+    constexpr uint32_t FULL = (1u << TS) - 1u;
+    const int ws = xb - R;
+    const int wi = ws >> 5;
+    const uint32_t win =
+        (__builtin_amdgcn_alignbit(row[wi + 1], row[wi], (uint32_t)(ws & 31)) & FULL) | pad.orm;
     float h = 0.f;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int idx = (int)((win >> (6 * c)) & 63u);
         h += __int_as_float(__builtin_amdgcn_ds_bpermute(idx << 2, lut[c]));
     }
-    return h - corr;
+    return h - pad.corr;
 }
 
 __device__ __forceinline__ uint32_t bits_extract(unsigned long long m, int off, int k) {
@@ -777,11 +793,14 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
                 have_win = false;
                 continue;
             }
+            // The padding is taken per row here: kept for the whole loop it
+            // makes the R >= 6 step kernels spill.
             if (!have_win) {
 #pragma unroll
                 for (int t = 0; t < 2 * R; ++t) {
                     const int y = yb + t;
-                    const float v = hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, x, W, border, lut, cum);
+                    const float v =
+                        hconv_fast<R, G::NCH>(bn + (rb + t) * kFWords, ox + 32, hpad_of<R>(x, W, border, cum), lut);
                     win[t] = (y >= 0 && y < H) ? v : 0.f;
                 }
             }
@@ -789,7 +808,8 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
             for (int t = 0; t < kSB; ++t) {
                 const int urow = rb + 2 * R + t;
                 const int y = y0 - R + urow;
-                const float v = hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, x, W, border, lut, cum);
+                const float v =
+                    hconv_fast<R, G::NCH>(bn + urow * kFWords, ox + 32, hpad_of<R>(x, W, border, cum), lut);
                 win[2 * R + t] = (y >= 0 && y < H) ? v : 0.f;
             }
 #pragma unroll

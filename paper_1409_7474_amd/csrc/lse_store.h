@@ -666,8 +666,8 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
     // LSF value of an all-ones / all-zeros window (same arithmetic as any pixel).
     float phi_one = 0.f, phi_zero = 0.f;
     {
-        const float h1 = hconv_fast<R, G::NCH>(s_const, 64, 64, 1 << 30, false, lut, cum);
-        const float h0 = hconv_fast<R, G::NCH>(s_const + 8, 64, 64, 1 << 30, false, lut, cum);
+        const float h1 = hconv_fast<R, G::NCH>(s_const, 64, HPad{0u, 0.f}, lut);
+        const float h0 = hconv_fast<R, G::NCH>(s_const + 8, 64, HPad{0u, 0.f}, lut);
 #pragma unroll
         for (int i = 0; i < TS; ++i) {
             phi_one = fmaf(kk[i], h1, phi_one);
@@ -754,6 +754,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                     constexpr int NW = 2 * R + kSB;
                     float win[NW];
                     const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
+                    const HPad pad = hpad_of<R>(x, W, cborder, cum);
                     bool have_win = false;
     #pragma unroll 1
                     for (int blk = 0; blk < G::NBLK; ++blk) {
@@ -777,7 +778,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                             for (int t2 = 0; t2 < 2 * R; ++t2) {
                                 const int y = by0 + rb + t2;
                                 const float v =
-                                    hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, x, W, cborder, lut, cum);
+                                    hconv_fast<R, G::NCH>(s_bits + (rb + t2) * kFWords, xb, pad, lut);
                                 win[t2] = (y >= 0 && y < H) ? v : 0.f;
                             }
                         }
@@ -785,7 +786,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                         for (int t2 = 0; t2 < kSB; ++t2) {
                             const int brow = rb + 2 * R + t2;
                             const int y = by0 + brow;
-                            const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, x, W, cborder, lut, cum);
+                            const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, pad, lut);
                             win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
                         }
     #pragma unroll
@@ -870,31 +871,26 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                             pred[i][c] = false;
                             phv[i][c] = 0.f;
                             gmv[i][c] = 0.f;
-                            int pix = 0;
-                            if (rowok && xb < 128 + G::RU && x >= 0 && x < W) {
-                                const int p = c * 64 + lane + 1;
-                                const float *cc = s_phi + (uy + 1) * G::PS + p;
-                                float gx, gy;
-                                if (x == 0)
-                                    gx = cc[1] - cc[0];
-                                else if (x == W - 1)
-                                    gx = cc[0] - cc[-1];
-                                else
-                                    gx = 0.5f * (cc[1] - cc[-1]);
-                                if (y == 0)
-                                    gy = cc[G::PS] - cc[0];
-                                else if (y == H - 1)
-                                    gy = cc[0] - cc[-G::PS];
-                                else
-                                    gy = 0.5f * (cc[G::PS] - cc[-G::PS]);
-                                phv[i][c] = cc[0];
-                                pred[i][c] = cc[0] >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                                if (!(gx == 0.f && gy == 0.f)) {
-                                    need[i][c] = true;
-                                    gmv[i][c] = sqrtf(gx * gx + gy * gy);
-                                    pix = y * W + x;
-                                }
+                            const bool ok = rowok && xb < 128 + G::RU && x >= 0 && x < W;
+                            {
+                                // All five values are read and the border case
+                                // (one-sided differences on the image's first and
+                                // last row and column) is a select: branches here
+                                // would wait for each read in turn.  Lanes outside
+                                // U read pixel (0, 32 - RU), inside phi.
+                                const int uyc = ok ? uy : 0, xbc = ok ? xb : 32 - G::RU;
+                                const int xc = x0 - 32 + xbc, yc = y0 - G::RU + uyc;
+                                const float *cc = s_phi + (uyc + 1) * G::PS + (xbc - 32 + G::RU + 1);
+                                const float c0 = cc[0], cl = cc[-1], cr = cc[1], cu = cc[-G::PS], cd = cc[G::PS];
+                                const float gxc = 0.5f * (cr - cl), gyc = 0.5f * (cd - cu);
+                                const float gx = xc == 0 ? cr - c0 : (xc == W - 1 ? c0 - cl : gxc);
+                                const float gy = yc == 0 ? cd - c0 : (yc == H - 1 ? c0 - cu : gyc);
+                                phv[i][c] = ok ? c0 : 0.f;
+                                pred[i][c] = ok && c0 >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                                need[i][c] = ok && !(gx == 0.f && gy == 0.f);
+                                gmv[i][c] = sqrtf(gx * gx + gy * gy);
                             }
+                            const int pix = y * W + x;
                             pixv[i][c] = pix;
                             if constexpr (!EDGE)
                                 v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pix * PB : kNoLoad);

@@ -681,10 +681,13 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
     const unsigned long long ones1 = (32 + 2 * G::RU >= 64) ? ~0ull : ((1ull << (32 + 2 * G::RU)) - 1ull);
 
     {
-        // Codes of the staged rows over each chunk's window span.
+        // Codes of the staged rows over each chunk's window span: the bits
+        // that phi^n of the chunk's columns reads, and (edge term) for chunk 0
+        // also those of the first two phi columns of chunk 1, which the
+        // gradient of its last pixels reads.
         for (int i = tid; i < G::BH * 2; i += kThreads) {
             const int row = i >> 1, c = i & 1;
-            s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, 95 - G::RU + R)
+            s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, (EDGE ? 97 : 95) - G::RU + R)
                                 : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
         }
         __syncthreads();
@@ -738,7 +741,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                 // Only in border tiles, and there only in the chunk next to
                 // the edge, do the taps reach outside the image.
                 const bool cborder = border && span_outside(x0, W, chunk == 0 ? 31 - G::RU - R : 95 - G::RU - R,
-                                                            chunk == 0 ? 95 - G::RU + R : 129 + G::RU + R);
+                                                            chunk == 0 ? (EDGE ? 97 : 95) - G::RU + R : 129 + G::RU + R);
                 if (raw) {
                     for (int j = 0; j < G::SEG; ++j) {
                         const int q = seg * G::SEG + j, y = py0 + q;
@@ -815,15 +818,23 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
             for (int bi = wave; bi < NBC; bi += kThreads / 64) {
                 const int u0 = bi * kSB;
                 const int nr = min(kSB, G::UH - u0);
-                int rc = -1;
-                if (!border) {
-                    const int ncode = (nr + 2) * 2;  // phi rows u0 .. u0 + nr + 1, both chunks
+                // Per chunk: whether phi rows u0 .. u0 + nr + 1 are one constant
+                // over the chunk's phi columns (then |grad phi| = 0 there and
+                // b = sign(phi), eq. (18)).  Both chunks alike, away from the
+                // left and right image edges: the whole block at once.  The
+                // edge term also takes one uniform chunk on its own (its codes
+                // cover the gradient's extra columns); in the region kernel
+                // that measured slower alone.
+                int rc = -1, ucs[2];
+                {
+                    const int ncode = (nr + 2) * 2;  // entries (row, chunk)
                     const int c = lane < ncode ? s_pcode[u0 * 2 + lane] : -1;
                     const unsigned long long full = (1ull << ncode) - 1ull;
-                    if (__ballot(c == 1) == full)
-                        rc = 1;
-                    else if (__ballot(c == 0) == full)
-                        rc = 0;
+                    const unsigned long long ev = full & 0x5555555555555555ull, od = full & 0xAAAAAAAAAAAAAAAAull;
+                    const unsigned long long b1 = __ballot(c == 1), b0 = __ballot(c == 0);
+                    ucs[0] = (b1 & ev) == ev ? 1 : ((b0 & ev) == ev ? 0 : -1);
+                    ucs[1] = (b1 & od) == od ? 1 : ((b0 & od) == od ? 0 : -1);
+                    if (!border && ucs[0] >= 0 && ucs[0] == ucs[1]) rc = ucs[0];
                 }
                 if (rc >= 0) {
                     if (lane < nr * kFWords) {
@@ -872,7 +883,12 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
                             phv[i][c] = 0.f;
                             gmv[i][c] = 0.f;
                             const bool ok = rowok && xb < 128 + G::RU && x >= 0 && x < W;
-                            {
+                            if (EDGE && ucs[c] >= 0) {  // constant phi over this chunk's gradients
+                                phv[i][c] = 0.f;
+                                pred[i][c] = ok && ucs[c] == 1;
+                                need[i][c] = false;
+                                gmv[i][c] = 0.f;
+                            } else {
                                 // All five values are read and the border case
                                 // (one-sided differences on the image's first and
                                 // last row and column) is a select: branches here

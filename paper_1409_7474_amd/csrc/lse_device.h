@@ -606,6 +606,8 @@ struct FastGeom {
     // PHP rows; the extra ones are not kept), which keeps the step kernel
     // within a quarter of the CU's LDS for the common radii.
     static constexpr int smem_words = BH * kFWords + PH * PS + UH * kFWords + BH * 2 + PHP * 2 + 16;
+    // A quiet tile writes its owned words with one thread each.
+    static_assert(FY * 3 <= kThreads, "owned bit words of a tile exceed the workgroup");
 };
 
 // Whether the staged bits lo .. hi of a fast tile (bit 0 = column x0 - 32)

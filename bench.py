@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of batched capacity")
     ap.add_argument("--batch-images", type=int, default=64)
-    ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations per term in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=24, help="oracle iterations per term in the CPU sample (~10-15 s)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="instead of the benchmark, run a plain device copy of this many MiB (reads and writes "
                          "that many bytes) so that profiler byte counters can be scaled against a known size")

@@ -123,12 +123,17 @@ def measured_traffic(kernel_name):
     return None, None
 
 
+def _hip():
+    import ctypes
+    return ctypes.CDLL("libamdhip64.so")
+
+
 def cu_masked_stream(ncu, first, count):
     """A HIP stream (default priority) whose kernels run only on CUs first ..
     first + count - 1 (hipExtStreamCreateWithCUMask); raises if the runtime
-    refuses the mask."""
+    refuses the mask.  Release it with destroy_stream."""
     import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
+    hip = _hip()
     words = (ncu + 31) // 32
     mask = (ctypes.c_uint32 * words)()
     for i in range(first, min(first + count, ncu)):
@@ -138,6 +143,11 @@ def cu_masked_stream(ncu, first, count):
     if rc != 0:
         raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({rc}) for CUs {first}..{first + count - 1}")
     return s.value
+
+
+def destroy_stream(s):
+    import ctypes
+    _hip().hipStreamDestroy(ctypes.c_void_p(s))
 
 
 def make_scene(name):
@@ -468,6 +478,8 @@ def main():
     counted = {}
     job(counted, lse.PROFILE_COUNT, concurrent=conc)
     torch.cuda.synchronize()
+    if sids.get("edge") not in (None, int(streams["edge"].cuda_stream)):
+        destroy_stream(sids["edge"])
 
     def step_bytes(t):
         c = counted[t]

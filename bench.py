@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of batched capacity")
     ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=24, help="oracle iterations per term in the CPU sample (~10-15 s)")
+    ap.add_argument("--profile-summary", default="",
+                    help="print the markdown summary of the rocprofv3 runs under this directory and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="instead of the benchmark, run a plain device copy of this many MiB (reads and writes "
                          "that many bytes) so that profiler byte counters can be scaled against a known size")
@@ -150,6 +152,95 @@ def cu_masked_stream(ncu, first, count):
 def destroy_stream(s):
     import ctypes
     _hip().hipStreamDestroy(ctypes.c_void_p(s))
+
+
+PROFILE_COMMANDS = [
+    "rocprofv3 --kernel-trace --stats -d OUT/trace_concurrent -o run -- python3 $R/bench.py --steps 2 --warmup 1 "
+    "--no-cpu-baseline --sections '' --job concurrent",
+    "rocprofv3 --kernel-trace --stats -d OUT/trace_sequential -o run -- python3 $R/bench.py --steps 2 --warmup 1 "
+    "--no-cpu-baseline --sections '' --job sequential",
+    "rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/FETCH_SIZE -o run -- python3 $R/bench.py --steps 1 "
+    "--warmup 0 --no-cpu-baseline --sections '' --job sequential",
+    "rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/WRITE_SIZE -o run -- python3 $R/bench.py --steps 1 "
+    "--warmup 0 --no-cpu-baseline --sections '' --job sequential",
+    "rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/cal_FETCH_SIZE -o run -- python3 $R/bench.py "
+    "--calibrate-copy-mib 256",
+    "rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/cal_WRITE_SIZE -o run -- python3 $R/bench.py "
+    "--calibrate-copy-mib 256",
+    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY "
+    "SQ_INSTS_VMEM_RD --kernel-trace --stats -d OUT/sq -o run -- python3 $R/bench.py --steps 1 --warmup 0 "
+    "--no-cpu-baseline --sections '' --job sequential",
+]
+
+
+def profile_summary(base):
+    """Markdown summary of the rocprofv3 runs of PROFILE_COMMANDS under `base`
+    (one directory per run, each holding run_results.db): kernel-trace
+    statistics of both job configurations, per-dispatch byte counters scaled
+    by the copy calibration, SQ counters of the step kernels, and the
+    per-launch traffic that measured_traffic reads back."""
+    import sqlite3
+
+    def q(db, sql):
+        return list(sqlite3.connect(db).execute(sql))
+
+    def counters(run):
+        rows = q(os.path.join(base, run, "run_results.db"),
+                 "select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                 "group by kernel_name, counter_name")
+        return {(k, c): v for k, c, v, n in rows}
+
+    def short(k):
+        return k.split("(")[0].replace("void ", "")
+
+    sha = kernel_source_digest()
+    f, w = counters("FETCH_SIZE"), counters("WRITE_SIZE")
+    cal_f = [v for (k, c), v in counters("cal_FETCH_SIZE").items() if "copyBuffer" in k][0]
+    cal_w = [v for (k, c), v in counters("cal_WRITE_SIZE").items() if "copyBuffer" in k][0]
+    copy_kib = 256 * 1024
+    fac_f, fac_w = copy_kib / cal_f, copy_kib / cal_w
+    out = ["# rocprofv3: fast LSE step on 4096x4096x4 (region + edge, sigma 1.5, 11x11, 200 iterations each)\n",
+           "Workload: `bench.py` default (the 4096 x 4096 x 4 multiband scene; one step = one region job of 200 "
+           "iterations + one edge job of 200 iterations).\n",
+           f"Kernel sources: `paper_1409_7474_amd/csrc/*.hip, *.h` (bench.kernel_source_digest) sha256 `{sha}`.\n",
+           "## Commands (run from /tmp with TMPDIR=/tmp, repo at $R)\n", "```", *PROFILE_COMMANDS,
+           "python3 $R/bench.py --profile-summary OUT", "```\n",
+           "The step timing in the PMC runs includes the untimed counting replay of bench.py (count_needed_kernel); "
+           "the trace runs are the reference for durations.  Every run traces the warm-up, the timed steps and the "
+           "counting replay, all in the one launch configuration that --job names.\n"]
+    for j in ("concurrent", "sequential"):
+        what = ("the region and edge solves on two concurrent streams, the edge one on 7/8 of the CUs (the timed "
+                "job of bench.py; its `roofline_concurrent`)" if j == "concurrent"
+                else "the two solves one after the other on one stream (bench.py's timed `sequential` pass; its "
+                     "`roofline`)")
+        out.append(f"## Kernel trace (--stats), --job {j}: {what}\n")
+        out.append("| kernel | calls | mean (us) | % of GPU time |\n|---|---:|---:|---:|")
+        for n, c, t, a, p in q(os.path.join(base, f"trace_{j}", "run_results.db"),
+                               "select name,total_calls,total_duration,average,percentage from top_kernels limit 14"):
+            out.append(f"| `{short(n)}` | {c} | {a:.2f} | {p:.1f} |")
+        out.append("")
+    out.append("## Byte counters (per dispatch, scaled)\n")
+    out.append(f"Calibration: a plain 256 MiB device copy reads FETCH_SIZE = {cal_f:.0f} KiB and WRITE_SIZE = "
+               f"{cal_w:.0f} KiB per dispatch, so FETCH_SIZE is scaled by {fac_f:.3f} and WRITE_SIZE by {fac_w:.3f}.\n")
+    out.append("| kernel | FETCH_SIZE (KiB, raw) | read (MB, scaled) | WRITE_SIZE (KiB, raw) | written (MB, scaled) |"
+               "\n|---|---:|---:|---:|---:|")
+    traffic = {}
+    for (k, c), v in sorted(f.items()):
+        if "lse::" not in k:
+            continue
+        wv = w.get((k, "WRITE_SIZE"), 0)
+        out.append(f"| `{short(k)}` | {v:.1f} | {v * 1024 * fac_f / 1e6:.2f} | {wv:.1f} | {wv * 1024 * fac_w / 1e6:.2f} |")
+        traffic[short(k)] = {"read_bytes": int(v * 1024 * fac_f), "write_bytes": int(wv * 1024 * fac_w)}
+    out.append("\n## SQ counters (per dispatch)\n")
+    out.append("| kernel | counter | value |\n|---|---|---:|")
+    for (k, c), v in sorted(counters("sq").items()):
+        if "step_fast" in k or "mpass" in k:
+            out.append(f"| `{short(k)}` | {c} | {v:.0f} |")
+    out.append("\n## Machine-readable traffic (read by bench.py when the kernel source hash matches)\n")
+    out.append("```json")
+    out.append(json.dumps({"kernel_source_sha256": sha, "per_launch_traffic": traffic}))
+    out.append("```")
+    return "\n".join(out)
 
 
 def make_scene(name):
@@ -364,6 +455,9 @@ def section_serving(args):
 
 def main():
     args = parse()
+    if args.profile_summary:
+        print(profile_summary(args.profile_summary))
+        return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
         return

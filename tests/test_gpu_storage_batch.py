@@ -145,15 +145,21 @@ def _assert_same(a, b, what):
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_equals_alone(dev, graph):
     """Seven uneven images (both terms, B = 1..4, three storage types, two
-    template sizes), per-image iteration targets: the batch reproduces every
-    image's solo run bit for bit, also when its launches replay from a graph
-    (two graph launches with host reads in between)."""
+    template sizes; five kernel families, each on a stream of the batch's
+    own), per-image iteration targets: the batch reproduces every image's
+    solo run bit for bit, also when its launches replay from a graph.  The
+    graph is replayed three times with host reads in between, and every
+    image is checked after each replay (the third one is past every target
+    and must change nothing)."""
     from paper_1409_7474_amd import lse
     spec = _jobs_spec()
     targets = [23, 17, 30, 23, 11, 30, 5]
     alone = _build(dev, spec)
+    want15 = []
     for j, t in zip(alone, targets):
-        j.run(t)
+        j.run(min(15, t))
+        want15.append(_state(j))
+        j.run(t - min(15, t))
     want = [_state(j) for j in alone]
 
     stream = torch.cuda.Stream(dev)  # graphs need a non-default stream
@@ -162,15 +168,13 @@ def test_batch_equals_alone(dev, graph):
         for j in jobs:
             j.stream = stream
         batch = lse.Batch(jobs, targets=targets, stream=stream)
-        batch.run(15, graph=graph)
-        mid = jobs[0].stats()
-        assert mid["iters_done"] == 15
-        batch.run(15, graph=graph)
-        stream.synchronize()
-    for i, (j, t) in enumerate(zip(jobs, targets)):
-        got = _state(j)
-        assert got[2]["iters_done"] == t, (i, got[2]["iters_done"], t)
-        _assert_same(got, want[i], f"image {i}")
+        for replay, expect in enumerate((want15, want, want)):
+            batch.run(15, graph=graph)
+            stream.synchronize()
+            for i, (j, t) in enumerate(zip(jobs, targets)):
+                got = _state(j)
+                assert got[2]["iters_done"] == min(15 * (replay + 1), t), (replay, i, got[2]["iters_done"])
+                _assert_same(got, expect[i], f"run {replay}, image {i}")
     batch.close()
 
 

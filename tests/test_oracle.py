@@ -319,8 +319,10 @@ def test_edge_update_is_monotone():
     assert np.all(s.u >= phi)
 
 
-def _brute_step(phi, img, dt, K, order):
-    """Independent tiny-input step: explicit loops over pixels and taps."""
+def _brute_step(phi, img, dt, K, order, reinit=True, parts=False):
+    """Independent tiny-input step: explicit loops over pixels and taps.
+    parts=True returns (u, psi, phi_next) with psi = G * u (listing order) or
+    None."""
     h, w = phi.shape
     nb = img.shape[2]
     ts = K.shape[0]
@@ -362,8 +364,11 @@ def _brute_step(phi, img, dt, K, order):
         return out
 
     if order == "table1":
-        return smooth(np.where(u >= 0, 1.0, -1.0))
-    return np.where(smooth(u) >= 0, 1.0, -1.0)
+        nxt = smooth(np.where(u >= 0, 1.0, -1.0) if reinit else u)
+        return (u, None, nxt) if parts else nxt
+    psi = smooth(u)
+    nxt = np.where(psi >= 0, 1.0, -1.0) if reinit else psi
+    return (u, psi, nxt) if parts else nxt
 
 
 @pytest.mark.parametrize("order", ["table1", "listing"])
@@ -417,3 +422,95 @@ def test_run_with_zero_iterations_returns_initial_mask():
     r = oracle.run(sc.image, sc.init_region, iters=0)
     np.testing.assert_array_equal(r.mask, sc.init_region)
     np.testing.assert_array_equal(r.phi, np.where(sc.init_region > 0, 1.0, -1.0))
+
+
+# ------------------------------------------- variant branches (Table I step 3)
+
+@pytest.mark.parametrize("order", ["table1", "listing"])
+def test_step_without_reinit_brute_force_tiny(order):
+    """Table I step 3 is optional ("if necessary"; Sec. III-D Step 3 binarises
+    only periodically): without it the smoothed field is the update itself,
+    G * u, in both orders, and the binary result is its sign."""
+    rng = np.random.default_rng(21)
+    img = rng.random((7, 9, 2))
+    phi = rng.normal(size=(7, 9)) * 0.4
+    K = oracle.template2d(0.8, 3)
+    s = oracle.step(phi, img, order=order, reinit=False, dt=15.0, sigma=0.8, ts=3)
+    u, psi, nxt = _brute_step(phi, img, 15.0, K, order, reinit=False, parts=True)
+    np.testing.assert_allclose(s.u, u, atol=1e-13)
+    np.testing.assert_allclose(s.phi, nxt, atol=1e-13)
+    # not binarised: the LSF is continuous and leaves [-1, 1] at Delta t = 15
+    assert np.abs(s.phi).max() > 1.0
+    np.testing.assert_array_equal(s.b, np.where(nxt >= 0, 1, -1).astype(np.int8))
+    if order == "listing":
+        np.testing.assert_allclose(s.psi, psi, atol=1e-13)
+        np.testing.assert_array_equal(s.phi, s.psi)
+
+
+def test_listing_psi_is_the_smoothed_update():
+    """Listing order (appendix code: update, smooth, binarise): the field that
+    is binarised is psi = G * u, element by element, and the new LSF and the
+    binary result are its sign (ties to +1)."""
+    rng = np.random.default_rng(22)
+    img = rng.random((8, 7, 3))
+    phi = rng.normal(size=(8, 7)) * 0.5
+    K = oracle.template2d(1.0, 5)
+    s = oracle.step(phi, img, order="listing", dt=15.0, sigma=1.0, ts=5)
+    u, psi, nxt = _brute_step(phi, img, 15.0, K, "listing", parts=True)
+    np.testing.assert_allclose(s.u, u, atol=1e-13)
+    np.testing.assert_allclose(s.psi, psi, atol=1e-13)
+    np.testing.assert_array_equal(s.phi, nxt)
+    np.testing.assert_array_equal(s.b, np.where(psi >= 0, 1, -1).astype(np.int8))
+
+
+# Iterations (0-based) that binarise in a 7-iteration run, written out by hand
+# for the reading of "periodically" taken here: every k-th iteration counting
+# from the first, so k = 1 is the every-iteration default and a run of m * k
+# iterations ends on a binarised LSF.
+_REINIT_SCHEDULE_7 = {
+    1: [True, True, True, True, True, True, True],
+    2: [False, True, False, True, False, True, False],
+    3: [False, False, True, False, False, True, False],
+    0: [False, False, False, False, False, False, False],
+}
+
+
+@pytest.mark.parametrize("order", ["table1", "listing"])
+@pytest.mark.parametrize("every", [1, 2, 3, 0])
+def test_run_reinit_schedule(order, every):
+    """run(reinit_every=k) equals single steps with the hand-written schedule
+    above, iteration by iteration: phi, the binary result and every flip
+    count.  An off-by-one in the schedule changes which iterations leave a
+    binary (Table I) or continuous LSF and fails here."""
+    sc = synth.scene_tiny(3, size=24, n_rects=1)
+    img = sc.image
+    mask = synth.centred_square(24, 24, 12, 12)
+    sched = _REINIT_SCHEDULE_7[every]
+    r = oracle.run(img, mask, order=order, reinit_every=every, iters=7, sigma=1.0, ts=5)
+    phi = np.where(mask > 0, 1.0, -1.0)
+    b_prev = np.where(mask > 0, 1, -1).astype(np.int8)
+    for n, rein in enumerate(sched):
+        s = oracle.step(phi, img, order=order, reinit=rein, sigma=1.0, ts=5)
+        assert r.flips[n] == int((s.b != b_prev).sum()), n
+        phi, b_prev = s.phi, s.b
+    assert r.iters_done == 7
+    np.testing.assert_array_equal(r.phi, phi)
+    np.testing.assert_array_equal(r.b, b_prev)
+
+
+def test_reinit_schedule_leaves_binary_or_continuous_lsf():
+    """Which iterations binarise shows in the LSF itself: in Table I order a
+    binarised iteration stores G * b, bounded by 1 in magnitude; at Delta t =
+    15 an iteration without binarisation stores G * u, which exceeds 1.  In
+    listing order a binarised iteration stores exactly +-1."""
+    sc = synth.scene_tiny(4, size=24, n_rects=1)
+    mask = synth.centred_square(24, 24, 12, 12)
+    for n_it, sched in enumerate(_REINIT_SCHEDULE_7[3], start=1):
+        t1 = oracle.run(sc.image, mask, order="table1", reinit_every=3, iters=n_it, sigma=1.0, ts=5)
+        lst = oracle.run(sc.image, mask, order="listing", reinit_every=3, iters=n_it, sigma=1.0, ts=5)
+        if sched:
+            assert np.abs(t1.phi).max() <= 1.0 + 1e-12, n_it
+            assert set(np.unique(lst.phi)) <= {-1.0, 1.0}, n_it
+        else:
+            assert np.abs(t1.phi).max() > 1.0, n_it
+            assert np.abs(lst.phi).max() > 1.0, n_it

@@ -105,7 +105,9 @@ void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t ba
 typedef struct {
     uint64_t n_plus;     /* #{phi >= 0} of the current LSF                    */
     uint64_t flips;      /* pixels whose binary result changed in the last iteration */
-    int32_t iters_done;  /* iterations executed since lse_init / lse_set_mask */
+    int32_t iters_done;  /* iteration index: iterations run since lse_init, or
+                            since lse_set_mask / lse_set_lsf plus their
+                            `iteration` argument                            */
     int32_t converged;   /* 1 once an iteration changed no pixel (Step 5)     */
     int32_t bad_value;   /* 1 if lse_init found a non-finite / out-of-range value */
     int32_t lsf_overflow;/* 1 if a continuous LSF (no binarisation in some
@@ -137,7 +139,12 @@ enum { LSE_PROFILE_TIMING = 1, LSE_PROFILE_COUNT = 2 };
 
 typedef struct lse_ctx lse_ctx; /* opaque, host-side */
 
-/* Bytes of device workspace lse_init needs for *p; 0 if *p is invalid. */
+/* Bytes of device workspace lse_init needs for *p; 0 if *p is invalid.  The
+ * workspace holds the whole state of the iteration of Table I: the resident
+ * image (region term, eq. (17)) or edge map g (edge term, eq. (14)) in the
+ * storage type, the LSF as its binary function of Table I step 3 (two bit
+ * planes, b^(n-1) and b^n), the region statistics of eq. (15) and, in the
+ * continuous-LSF modes, two LSF planes of the storage type. */
 size_t lse_workspace_bytes(const lse_params *p);
 
 /* Table I step 1.  Copies/converts the image (H x W x B, p->image_dtype) into
@@ -165,18 +172,54 @@ lse_status lse_run(lse_ctx *c, int32_t max_iters, int32_t stop_when_unchanged, v
 /* Step 6: the binary result (1 = inside, phi >= 0) as H x W uint8. */
 lse_status lse_mask(const lse_ctx *c, uint8_t *mask_dev, void *stream);
 
-/* The current LSF as H x W float32: the Gaussian-smoothed binary function
- * after at least one iteration, the binary initial LSF before the first. */
+/* The current LSF as H x W float32 (lsf_dev 4-byte aligned, caller-owned):
+ * the result of Table I step 4, G_sigma * b, after at least one iteration, the
+ * binary initial LSF of eq. (13) before the first.  Continuous-LSF modes: the
+ * stored plane (G_sigma * u after an iteration without binarisation; in
+ * listing order after a binarising iteration the smoothed update psi whose
+ * sign is the LSF). */
 lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream);
 
-/* Load a state (checkpoint / resume): mask_dev (H x W uint8) becomes the
+/* Load a state whose LSF is a function of a binary mask (checkpoint / resume,
+ * Table I steps 1 and 4): mask_dev (H x W uint8, nonzero = +1) becomes the
  * binary function; smoothed = 0 makes it the initial LSF of eq. (13),
  * smoothed = 1 makes the LSF its Gaussian smoothing (the state after an
- * iteration).  Region statistics are recomputed; the iteration counter and
- * the converged flag are reset. */
-lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, void *stream);
+ * iteration of Table I order with binarisation).  `iteration` (>= 0) is the
+ * number of iterations the state has already run (lse_stats().iters_done of
+ * the checkpoint): the next iteration has that index, so a periodic
+ * reinitialisation schedule continues where it stopped, and iters_done counts
+ * on from it.  Region statistics are recomputed; the converged flag is reset.
+ * In the continuous-LSF modes use lse_set_lsf for a state between
+ * binarisations. */
+lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, int32_t iteration, void *stream);
 
-/* Copy the state summary to *host_out; synchronises `stream`. */
+/* Load a continuous LSF (checkpoint / resume of the continuous-LSF modes:
+ * listing order or reinit_every != 1, where Table I step 3 does not run in
+ * every iteration).  lsf_dev: H x W float32 as lse_lsf returned it (rounded
+ * once to the storage type; a value that is not finite after the rounding is
+ * reported by lse_check as LSE_ERR_BAD_VALUE).  mask_dev: H x W uint8, the
+ * binary result of the last iteration as lse_mask returned it (flips of the
+ * next iteration are counted against it), or NULL for the sign of lsf_dev
+ * (>= 0 -> 1).  iteration: as for lse_set_mask; in listing order, when
+ * iteration - 1 was a binarising iteration, lsf_dev is the pre-sign field psi
+ * and the LSF is the binary function of mask_dev, as in the run that wrote
+ * them.  A checkpoint (lse_lsf, lse_mask, lse_stats().iters_done) loaded here
+ * continues bit for bit as the uninterrupted run.  Region statistics are
+ * recomputed.  LSE_ERR_UNSUPPORTED in the Table I binary-state mode
+ * (reinit_every = 1), whose LSF is always G_sigma * b: lse_set_mask with
+ * smoothed = 1 is the exact resume there. */
+lse_status lse_set_lsf(lse_ctx *c, const float *lsf_dev, const uint8_t *mask_dev, int32_t iteration, void *stream);
+
+/* The edge term's g of eq. (14) as the iterations read it (rounded once to the
+ * storage type), H x W float32, g_dev 4-byte aligned and caller-owned.
+ * LSE_ERR_STATE for the region terms. */
+lse_status lse_edge_map(const lse_ctx *c, float *g_dev, void *stream);
+
+/* Copy the state summary to *host_out (Table I step 5: the flip count of the
+ * last iteration and whether an iteration changed no pixel; the c+ / c- of
+ * eq. (15) and the normaliser M of eq. (17) it used); synchronises `stream`.
+ * iters_done is the iteration index: iterations run since lse_init, or since
+ * a resume plus its `iteration` argument. */
 lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream);
 
 /* Synchronise `stream`; LSE_ERR_BAD_VALUE if lse_init found a bad value or the
@@ -220,7 +263,7 @@ void lse_destroy(lse_ctx *c);
  * contexts must outlive the batch; while a batch exists its contexts may still
  * be stepped alone (lse_step / lse_run) on the same stream.  lse_set_mask on a
  * member context is allowed; targets count iterations since the last
- * lse_init / lse_set_mask. */
+ * lse_init / lse_set_mask (not the iteration index a resume starts from). */
 typedef struct lse_batch lse_batch; /* opaque, host-side */
 
 /* lse_batch_run flags. */

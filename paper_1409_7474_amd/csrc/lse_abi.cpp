@@ -26,7 +26,8 @@ struct lse_ctx {
     int WW;             // bit words per row
     long long hw;
     float fix, inv_fix;
-    int n;              // iterations enqueued since init / set_mask
+    int n;              // iterations enqueued since init / set_mask / set_lsf (device slots count from there)
+    int n_base;         // iteration index of the method at that restart (kept across resume)
     int raw_next;       // next iteration starts from the binary LSF itself
     DevState *st;
     Taps *taps;
@@ -354,7 +355,10 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     int next_binary = 0;
     if (c->dense) {
         const int every = c->p.reinit_every;
-        a.reinit = every > 0 && ((c->n + 1) % every) == 0;
+        // Table I step 3 "if necessary" / Sec. III-D Step 3 "periodically":
+        // iteration index i binarises iff (i + 1) % every == 0.
+        const long long idx = (long long)c->n_base + c->n;
+        a.reinit = every > 0 && ((idx + 1) % every) == 0;
         a.order = c->p.order;
         a.phi_binary = c->phi_binary;
         a.plane_in = c->plane[c->n & 1];
@@ -443,6 +447,7 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     c->fix = ldexpf(1.f, s);
     c->inv_fix = ldexpf(1.f, -s);
     c->n = 0;
+    c->n_base = 0;
     c->raw_next = 1;
     char *base = static_cast<char *>(workspace_dev);
     c->st = reinterpret_cast<DevState *>(base + L.state);
@@ -554,17 +559,53 @@ lse_status lse_lsf(const lse_ctx *c, float *lsf_dev, void *stream) {
     return dev_status(launch_lsf_out(a, b, c->raw_next, lsf_dev, as_stream(stream)));
 }
 
-lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, void *stream) {
-    if (!c || !mask_dev) return LSE_ERR_INVALID_ARG;
+lse_status lse_set_mask(lse_ctx *c, const uint8_t *mask_dev, int32_t smoothed, int32_t iteration, void *stream) {
+    if (!c || !mask_dev || iteration < 0) return LSE_ERR_INVALID_ARG;
     const hipStream_t s = as_stream(stream);
     hipError_t e = launch_reset_state(c->st, smoothed ? 0 : 1, s);
     if (e == hipSuccess) e = launch_sched_reset(&c->host_args, s);
     if (e == hipSuccess) e = launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
     c->n = 0;
+    c->n_base = iteration;
     c->raw_next = smoothed ? 0 : 1;
     if (e == hipSuccess) e = load_lsf(c, c->raw_next, s);
     c->last_stream = s;
     return dev_status(e);
+}
+
+lse_status lse_set_lsf(lse_ctx *c, const float *lsf_dev, const uint8_t *mask_dev, int32_t iteration, void *stream) {
+    if (!c || !lsf_dev || (reinterpret_cast<uintptr_t>(lsf_dev) & 3) || iteration < 0) return LSE_ERR_INVALID_ARG;
+    if (!c->dense) return LSE_ERR_UNSUPPORTED;  // binary-state mode: the LSF is G * b (lse_set_mask, smoothed)
+    const hipStream_t s = as_stream(stream);
+    // In listing order a binarising iteration leaves the LSF sign(psi) and
+    // stores psi (what lse_lsf returns): the next iteration then reads the
+    // binary function from the bits.
+    const int every = c->p.reinit_every;
+    const int prev_binarised = iteration > 0 && every > 0 && (iteration % every) == 0;
+    hipError_t e = launch_reset_state(c->st, 0, s);
+    if (e == hipSuccess) e = launch_plane_load(lsf_dev, c->plane[0], c->hw, c->st, c->p.storage, s);
+    if (e == hipSuccess)
+        e = mask_dev ? launch_pack_mask(mask_dev, c->bits[0], c->p.height, c->p.width, c->WW, s)
+                     : launch_pack_sign(lsf_dev, c->bits[0], c->p.height, c->p.width, c->WW, s);
+    c->n = 0;
+    c->n_base = iteration;
+    c->raw_next = 0;
+    c->phi_binary = c->p.order == LSE_ORDER_LISTING && prev_binarised;
+    if (e == hipSuccess && c->region) {
+        StepArgs a = step_args(c);
+        a.bits_in = c->bits[0];
+        e = launch_plane_stats(a, c->plane[0], c->NB, c->p.storage, 0, s);
+    }
+    c->last_stream = s;
+    return dev_status(e);
+}
+
+lse_status lse_edge_map(const lse_ctx *c, float *g_dev, void *stream) {
+    if (!c || !g_dev || (reinterpret_cast<uintptr_t>(g_dev) & 3)) return LSE_ERR_INVALID_ARG;
+    if (c->p.term != LSE_TERM_EDGE) return LSE_ERR_STATE;
+    // The stored map is one plane of the storage type; iters' parity picks
+    // either pointer, both name it.
+    return dev_status(launch_plane_out(c->img, c->img, c->st, g_dev, c->hw, c->p.storage, as_stream(stream)));
 }
 
 lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream) {
@@ -581,7 +622,7 @@ lse_status lse_stats(const lse_ctx *c, lse_stats_t *host_out, void *stream) {
     }
     host_out->n_plus = nplus;
     host_out->flips = h.iters > 0 ? flips : 0;
-    host_out->iters_done = h.iters;
+    host_out->iters_done = c->n_base + h.iters;
     host_out->converged = h.done;
     host_out->bad_value = h.bad == kBadInput ? 1 : 0;
     host_out->lsf_overflow = h.bad == kBadOverflow ? 1 : 0;
@@ -966,6 +1007,6 @@ void lse_batch_destroy(lse_batch *b) {
     delete b;
 }
 
-int32_t lse_version(void) { return 101; }
+int32_t lse_version(void) { return 102; }
 
 }  // extern "C"

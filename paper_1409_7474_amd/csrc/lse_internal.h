@@ -187,6 +187,8 @@ struct Store {
     static hipError_t plane_stats(const StepArgs &a, const void *plane, int NB, int slot, hipStream_t s);
     static hipError_t plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n,
                                 hipStream_t s);
+    // A caller's FP32 LSF into a storage plane (resume of the continuous modes).
+    static hipError_t plane_load(const float *src, void *dst, long long n, DevState *st, hipStream_t s);
     // Per-tile region sums of the all-inside case (args[0], radius r).
     static hipError_t tile_sums(const ImgArgs *args, int tiles, int r, int NB, TileSum *out, hipStream_t s);
 };
@@ -204,6 +206,9 @@ hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);
 hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
                              DevState *st, float fix, int mode, float gray_scale, hipStream_t s);
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s);
+// Bits of sign(lsf) (lsf >= 0 -> 1), H x W float32.
+hipError_t launch_pack_sign(const float *lsf, uint32_t *bits, int H, int W, int WW, hipStream_t s);
+hipError_t launch_plane_load(const float *src, void *dst, long long n, DevState *st, int storage, hipStream_t s);
 hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slot, hipStream_t s);
 hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
                            void *g, int storage, hipStream_t s);

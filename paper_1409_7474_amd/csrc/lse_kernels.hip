@@ -77,6 +77,19 @@ __global__ void pack_mask_kernel(const uint8_t *__restrict__ mask, uint32_t *__r
     bits[i] = v;
 }
 
+// sign(lsf) -> bit words (lsf >= 0 -> 1, the tie rule of eq. (15)).
+__global__ void pack_sign_kernel(const float *__restrict__ lsf, uint32_t *__restrict__ bits, int H, int W, int WW) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)H * WW) return;
+    const int y = (int)(i / WW), w = (int)(i - (long long)y * WW);
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int x = w * 32 + b;
+        if (x < W && lsf[(size_t)y * W + x] >= 0.f) v |= 1u << b;
+    }
+    bits[i] = v;
+}
+
 // ------------------------------------------------------------ edge map init
 
 // out(y, x) = sum_j k[j] in(y, x + j - r)   (zero outside)
@@ -453,6 +466,21 @@ hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, i
     const long long n = (long long)H * WW;
     hipLaunchKernelGGL(pack_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mask, bits, H, W, WW);
     return hipGetLastError();
+}
+
+hipError_t launch_pack_sign(const float *lsf, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
+    const long long n = (long long)H * WW;
+    hipLaunchKernelGGL(pack_sign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lsf, bits, H, W, WW);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_load(const float *src, void *dst, long long n, DevState *st, int storage, hipStream_t s) {
+    switch (storage) {
+        case LSE_F32: return Store<float>::plane_load(src, dst, n, st, s);
+        case LSE_F16: return Store<__half>::plane_load(src, dst, n, st, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::plane_load(src, dst, n, st, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 size_t tile_smem_bytes(int r, int nch, int edge) { return tile_smem_words(r, nch, edge) * 4; }

@@ -1592,6 +1592,27 @@ hipError_t Store<ST>::tile_sums(const ImgArgs *args, int tiles, int r, int NB, T
     return hipErrorInvalidValue;
 }
 
+// A caller's FP32 LSF into a plane of the storage type (round to nearest); a
+// value that is not finite after the rounding marks the state as overflowed.
+template <typename ST>
+__global__ void plane_load_kernel(const float *__restrict__ src, ST *__restrict__ dst, long long n, DevState *st) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        const ST q = from_f32<ST>(src[i]);
+        dst[i] = q;
+        bad = !isfinite(to_f32<ST>(q));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) st->bad = kBadOverflow;
+}
+
+template <typename ST>
+hipError_t Store<ST>::plane_load(const float *src, void *dst, long long n, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL((plane_load_kernel<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                       static_cast<ST *>(dst), n, st);
+    return hipGetLastError();
+}
+
 template <typename ST>
 hipError_t Store<ST>::plane_out(const void *p0, const void *p1, const DevState *st, float *out, long long n,
                                 hipStream_t s) {

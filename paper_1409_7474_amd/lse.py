@@ -31,7 +31,7 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 # Every function the header declares; tests check that the library exports them.
 EXPORTS = (
     "lse_params_default", "lse_workspace_bytes", "lse_init", "lse_step", "lse_run", "lse_mask",
-    "lse_lsf", "lse_set_mask", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
+    "lse_lsf", "lse_set_mask", "lse_set_lsf", "lse_edge_map", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
     "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_run",
     "lse_batch_destroy", "lse_status_str", "lse_version",
 )
@@ -107,8 +107,12 @@ def load() -> ctypes.CDLL:
     lib.lse_mask.restype = st
     lib.lse_lsf.argtypes = [vp, vp, vp]
     lib.lse_lsf.restype = st
-    lib.lse_set_mask.argtypes = [vp, vp, i32, vp]
+    lib.lse_set_mask.argtypes = [vp, vp, i32, i32, vp]
     lib.lse_set_mask.restype = st
+    lib.lse_set_lsf.argtypes = [vp, vp, vp, i32, vp]
+    lib.lse_set_lsf.restype = st
+    lib.lse_edge_map.argtypes = [vp, vp, vp]
+    lib.lse_edge_map.restype = st
     lib.lse_stats.argtypes = [vp, P(lse_stats_t), vp]
     lib.lse_stats.restype = st
     lib.lse_check.argtypes = [vp, vp]
@@ -182,8 +186,16 @@ def lse_lsf(ctx, lsf_ptr: int, stream: int = 0) -> None:
     _check(load().lse_lsf(ctx, lsf_ptr, stream), "lse_lsf")
 
 
-def lse_set_mask(ctx, mask_ptr: int, smoothed: bool, stream: int = 0) -> None:
-    _check(load().lse_set_mask(ctx, mask_ptr, int(bool(smoothed)), stream), "lse_set_mask")
+def lse_set_mask(ctx, mask_ptr: int, smoothed: bool, iteration: int = 0, stream: int = 0) -> None:
+    _check(load().lse_set_mask(ctx, mask_ptr, int(bool(smoothed)), int(iteration), stream), "lse_set_mask")
+
+
+def lse_set_lsf(ctx, lsf_ptr: int, mask_ptr, iteration: int = 0, stream: int = 0) -> None:
+    _check(load().lse_set_lsf(ctx, lsf_ptr, mask_ptr, int(iteration), stream), "lse_set_lsf")
+
+
+def lse_edge_map(ctx, g_ptr: int, stream: int = 0) -> None:
+    _check(load().lse_edge_map(ctx, g_ptr, stream), "lse_edge_map")
 
 
 def lse_stats(ctx, stream: int = 0) -> lse_stats_t:
@@ -355,10 +367,34 @@ class LSE:
         lse_lsf(self.ctx, out.data_ptr(), self._s())
         return self._handoff(out)
 
-    def set_mask(self, mask, smoothed: bool) -> None:
+    def set_mask(self, mask, smoothed: bool, iteration: int = 0) -> None:
         mask = mask.to(_torch().uint8).contiguous()
         self._keep_mask = mask
-        lse_set_mask(self.ctx, mask.data_ptr(), smoothed, self._s())
+        lse_set_mask(self.ctx, mask.data_ptr(), smoothed, iteration, self._s())
+
+    def set_lsf(self, lsf, mask=None, iteration: int = 0) -> None:
+        """Continuous-LSF modes: load a checkpoint (lsf(), mask(), iters_done)."""
+        torch = _torch()
+        lsf = lsf.to(torch.float32).contiguous()
+        h, w, _ = self.shape
+        if tuple(lsf.shape) != (h, w) or not lsf.is_cuda:
+            raise ValueError("lsf must be an H x W GPU tensor")
+        mptr = None
+        if mask is not None:
+            mask = mask.to(torch.uint8).contiguous()
+            if tuple(mask.shape) != (h, w) or not mask.is_cuda:
+                raise ValueError("mask must be an H x W GPU tensor")
+            mptr = mask.data_ptr()
+        self._keep_state = (lsf, mask)
+        lse_set_lsf(self.ctx, lsf.data_ptr(), mptr, iteration, self._s())
+
+    def edge_map(self, out=None):
+        """The edge map g of eq. (14) as stored (edge term only)."""
+        torch = _torch()
+        h, w, _ = self.shape
+        out = out if out is not None else torch.empty((h, w), dtype=torch.float32, device=self.device)
+        lse_edge_map(self.ctx, out.data_ptr(), self._s())
+        return self._handoff(out)
 
     def stats(self) -> dict:
         s = lse_stats(self.ctx, self._s())

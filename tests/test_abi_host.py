@@ -134,7 +134,9 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lse_run(None, 3, 0, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_mask(None, 16, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_lsf(None, 16, None) == lse.LSE_ERR_INVALID_ARG
-    assert lib.lse_set_mask(None, 16, 0, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_set_mask(None, 16, 0, 0, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_set_lsf(None, 16, None, 0, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_edge_map(None, 16, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_stats(None, None, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_profile(None, 1) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_profile(None, 8) == lse.LSE_ERR_INVALID_ARG

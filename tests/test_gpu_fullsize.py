@@ -1,0 +1,133 @@
+"""Full-size FP64 parity deep into a run, and the edge map element by element.
+
+The precision workload (8192 x 8192 x 4 runway scene, sigma 2 / 13 x 13) and
+the large workload (4096 x 4096 x 4, sigma 1.5 / 11 x 11) run in the launch
+configuration the benchmark times.  After 60 iterations most step tiles are
+settled and not visited, so a step covers only the tiles near the front: the
+visit list is built by the normaliser pass (region term, B > 1) or by its own
+pass (edge term and one-band region term, over 4096 tiles).  One step from
+that GPU state must match the FP64 oracle on every pixel (bars as in
+test_gpu_parity.py: binary decisions equal outside the FP32 ambiguity band,
+the LSF within 1e-5 outside its footprint).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_7474_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from parity_helpers import LSF_TOL, _make, check_normaliser, one_step  # noqa: E402
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache.clear()
+            cache[name] = synth.scene_large(0) if name == "large" else synth.scene_precision(0)
+        return cache[name]
+    yield get
+    cache.clear()
+
+
+CASES = [
+    # (scene, term, bands, sigma, ts): bands 1 = the band mean as a one-band image
+    ("large", "region", 4, 1.5, 11),
+    ("large", "edge", 4, 1.5, 11),
+    ("precision", "region", 4, 2.0, 13),
+    ("precision", "region", 1, 2.0, 13),
+    ("precision", "edge", 4, 2.0, 13),
+]
+
+
+@pytest.mark.parametrize("name,term,bands,sigma,ts", CASES)
+def test_full_size_one_step_parity_after_60_iterations(dev, scenes, name, term, bands, sigma, ts):
+    sc = scenes(name)
+    f32 = np.asarray(sc.image, np.float32)
+    if bands == 1:
+        f32 = f32.mean(axis=2, dtype=np.float32)[..., None]
+    img = torch.tensor(f32, device=dev)
+    img64 = f32.astype(np.float64)
+    mask = sc.init_region if term == "region" else sc.init_edge
+    print(f"case {name} {term} B={bands} {f32.shape[0]}x{f32.shape[1]} ts {ts}", flush=True)
+    job = _make(dev, img, mask, term=term, sigma=sigma, ksize=ts)
+    job.run(60)
+    g = oracle.edge_map(img64, 1.0, 9, 255.0) if term == "edge" else None
+    err, amb, ref = one_step(job, img64, term=term, sigma=sigma, ts=ts, g=g)
+    assert err <= LSF_TOL, err
+    st = job.stats()
+    assert st["iters_done"] == 61 and not st["converged"]
+    if term == "region":
+        np.testing.assert_allclose(st["c_plus"], ref.c_plus, rtol=2e-6)
+        np.testing.assert_allclose(st["c_minus"], ref.c_minus, rtol=2e-6)
+        check_normaliser(st, img64, ref.M)
+    job.close()
+
+
+def _edge_tol(gray_max, ts1, storage):
+    """Relative bound on |g_gpu - g_oracle| / g_oracle.  The smoothed gray
+    image Is (values up to gray_max) is a sum of ts1 x ts1 positive terms taken
+    as two FP32 passes of ts1 taps, with FP32 taps: |dIs| <= (2 ts1 + 4) u Is.
+    The central difference carries that to |dG| <= (2 ts1 + 4) u gray_max for
+    each gradient component, and g = 1 / (1 + G^2) has
+    |dg| / g <= 2 |G| |dG| / (1 + G^2) <= |dG| per component, twice for two.
+    Storing g in 16 bits adds half an ulp of the storage type, relative."""
+    t = 2.0 * (2 * ts1 + 4) * U32 * gray_max + 4 * U32
+    if storage == "f16":
+        t += 2.0 ** -11
+    elif storage == "bf16":
+        t += 2.0 ** -8
+    return t
+
+
+@pytest.mark.parametrize("shape,bands,storage", [
+    ((64, 80), 4, "f32"), ((97, 130), 1, "f32"), ((33, 2), 3, "f32"), ((200, 333), 4, "f16"),
+    ((200, 333), 4, "bf16"), ((1000, 1200), 4, "f32"),
+])
+def test_edge_map_matches_oracle_elementwise(dev, shape, bands, storage):
+    """g of eq. (14) as the iterations read it, against the oracle's FP64 g of
+    the same FP32 image, pixel by pixel."""
+    h, w = shape
+    sc = synth.scene_multiband(5, size=max(h, w), bands=bands, n_roofs=10, n_roads=2, height=h, width=w)
+    f32 = np.asarray(sc.image, np.float32)
+    job = _make(dev, torch.tensor(f32, device=dev), sc.init_edge, term="edge", sigma=1.5, ksize=11,
+                storage=storage)
+    got = job.edge_map().cpu().double().numpy()
+    ref = oracle.edge_map(f32.astype(np.float64), 1.0, 9, 255.0)
+    rel = np.abs(got - ref) / ref
+    tol = _edge_tol(255.0 * float(f32.max()), 9, storage)
+    assert rel.max() <= tol, (rel.max(), tol)
+    assert np.all(got > 0) and np.all(got <= 1.0)
+    print(f"edge map {h}x{w} B={bands} {storage}: max rel err {rel.max():.3g} (bound {tol:.3g})", flush=True)
+
+
+@pytest.mark.parametrize("name", ["large", "precision"])
+def test_edge_map_full_size(dev, scenes, name):
+    sc = scenes(name)
+    f32 = np.asarray(sc.image, np.float32)
+    job = _make(dev, torch.tensor(f32, device=dev), sc.init_edge, term="edge",
+                sigma=1.5 if name == "large" else 2.0, ksize=11 if name == "large" else 13)
+    got = job.edge_map().cpu().double().numpy()
+    ref = oracle.edge_map(f32.astype(np.float64), 1.0, 9, 255.0)
+    rel = np.abs(got - ref) / ref
+    tol = _edge_tol(255.0 * float(f32.max()), 9, "f32")
+    print(f"edge map {name}: max rel err {rel.max():.3g} (bound {tol:.3g}), "
+          f"99.99th pct {np.quantile(rel, 0.9999):.3g}", flush=True)
+    assert rel.max() <= tol
+
+
+def test_edge_map_rejects_region_term(dev):
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_tiny(0, size=64, n_rects=1)
+    job = _make(dev, torch.tensor(np.asarray(sc.image, np.float32), device=dev), sc.init_region)
+    with pytest.raises(lse.LSEError) as e:
+        job.edge_map()
+    assert e.value.status == lse.LSE_ERR_STATE

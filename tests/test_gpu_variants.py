@@ -163,6 +163,84 @@ def test_dense_resume_is_bitwise(dev):
     assert a.stats() == b.stats()
 
 
+@pytest.mark.parametrize("order,every,storage,term", [
+    ("table1", 3, "f32", "region"), ("listing", 3, "f32", "region"), ("listing", 1, "f32", "region"),
+    ("table1", 0, "f32", "region"), ("table1", 2, "f16", "region"), ("listing", 3, "bf16", "region"),
+    ("table1", 3, "f32", "edge"), ("listing", 2, "f32", "edge"),
+])
+@pytest.mark.parametrize("at", [3, 4])
+def test_resume_mid_period_is_bitwise(dev, order, every, storage, term, at):
+    """A checkpoint (lse_lsf, lse_mask, iters_done) taken between two
+    binarisations and loaded with lse_set_lsf continues bit for bit as the
+    uninterrupted run: the iteration index is kept, so the reinitialisation
+    schedule (iteration i binarises iff (i + 1) % k == 0) goes on where it
+    stopped.  at = 3 with k = 3 resumes right after a binarising iteration (in
+    listing order the stored field is then psi and the LSF its sign)."""
+    sc = synth.scene_multiband(11, size=160, bands=4, n_roofs=6, n_roads=1, height=150, width=170)
+    img = _img(dev, sc.image)
+    mask = sc.init_region if term == "region" else sc.init_edge
+    kw = dict(order=order, reinit_every=every, storage=storage, term=term, sigma=1.5, ksize=11)
+    full = _make(dev, img, mask, **kw)
+    full.run(10)
+    part = _make(dev, img, mask, **kw)
+    part.run(at)
+    lsf, m, done = part.lsf().clone(), part.mask().clone(), part.stats()["iters_done"]
+    assert done == at
+    resumed = _make(dev, img, np.zeros_like(mask), **kw)
+    resumed.set_lsf(lsf, m, iteration=done)
+    resumed.run(10 - at)
+    assert torch.equal(resumed.lsf(), full.lsf()), (order, every, at)
+    assert torch.equal(resumed.mask(), full.mask())
+    a, b = resumed.stats(), full.stats()
+    assert a["iters_done"] == b["iters_done"] == 10
+    for k in ("n_plus", "flips", "c_plus", "c_minus", "M", "converged", "lsf_overflow"):
+        assert a[k] == b[k], k
+    # Without the iteration index the schedule restarts and the run differs.
+    if every > 1 and at % every:
+        other = _make(dev, img, np.zeros_like(mask), **kw)
+        other.set_lsf(lsf, m, iteration=0)
+        other.run(10 - at)
+        assert not torch.equal(other.lsf(), full.lsf())
+
+
+def test_set_lsf_without_mask_takes_its_sign_and_can_start_a_run(dev):
+    """lse_set_lsf at iteration 0 starts from any continuous LSF; without a
+    mask the previous binary result is sign(lsf) (ties to +1).  One step from
+    it matches the oracle."""
+    sc = synth.scene_tiny(2, size=96, n_rects=2)
+    img = _img(dev, sc.image)
+    img64 = np.asarray(sc.image, np.float32).astype(np.float64)
+    yy, xx = np.mgrid[0:96, 0:96]
+    phi0 = (30.0 - np.hypot(yy - 48.0, xx - 48.0)) / 10.0  # a cone: signed distance / 10
+    job = _make(dev, img, np.zeros((96, 96), np.uint8), reinit_every=2)
+    job.set_lsf(torch.tensor(phi0, dtype=torch.float32, device=dev), None, iteration=0)
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), (np.float32(phi0) >= 0).astype(np.uint8))
+    np.testing.assert_array_equal(job.lsf().cpu().numpy(), np.float32(phi0))
+    variant_step(job, img64, order="table1", reinit=False)
+
+
+def test_set_lsf_rejected_in_binary_state_mode_and_keeps_index_in_set_mask(dev):
+    """The Table I binary-state mode stores G * b only: lse_set_lsf is
+    unsupported there, and lse_set_mask(smoothed=1, iteration) is its exact
+    resume, iteration index included."""
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_tiny(1, size=128, n_rects=2)
+    img = _img(dev, sc.image)
+    full = _make(dev, img, sc.init_region)
+    full.run(9)
+    part = _make(dev, img, sc.init_region)
+    part.run(4)
+    ck = part.mask().clone()
+    with pytest.raises(lse.LSEError) as e:
+        part.set_lsf(part.lsf(), ck, iteration=4)
+    assert e.value.status == lse.LSE_ERR_UNSUPPORTED
+    res = _make(dev, img, sc.init_region)
+    res.set_mask(ck, smoothed=True, iteration=4)
+    res.run(5)
+    assert torch.equal(res.lsf(), full.lsf()) and torch.equal(res.mask(), full.mask())
+    assert res.stats()["iters_done"] == 9
+
+
 def test_batches_reject_continuous_modes(dev):
     from paper_1409_7474_amd import lse
     sc = synth.scene_tiny(0, size=64, n_rects=1)

@@ -295,6 +295,36 @@ lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchange
  * caller's. */
 void lse_batch_destroy(lse_batch *b);
 
+/* ------------------------------------------------- allocation-free solve
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * solve -- lse_init, lse_run(max_iters, stop_when_unchanged), lse_mask and,
+ * if lsf_dev is not NULL, lse_lsf -- enqueued on `stream` with the workspace
+ * taken from a library-owned device array of LSE_STATIC_WORKSPACE_BYTES per
+ * GPU (allocated when the library is loaded, held until the process ends)
+ * instead of a caller buffer.  The call allocates nothing (no hipMalloc,
+ * hipFree, pinned staging or host-to-device copy: the constant tables travel
+ * as kernel arguments) and returns without synchronising.  Results equal
+ * those of the workspace entry points bit for bit.
+ *
+ * image_dev / init_mask_dev: as for lse_init; mask_dev: H x W uint8 out (1 =
+ * inside); lsf_dev: H x W float32 out (4-byte aligned) or NULL.  The current
+ * HIP device must be the one the stream and buffers belong to.
+ * LSE_ERR_WORKSPACE when lse_workspace_bytes(p) exceeds
+ * LSE_STATIC_WORKSPACE_BYTES (e.g. a 4-band FP32 region image above about
+ * 4.1 Mpx, or an FP32 edge image above about 5.5 Mpx); other errors as
+ * lse_init.
+ *
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call rewrites every part of it it reads before
+ * reading it).  Calls that overlap on one GPU -- on two streams, or from two
+ * host threads without ordering -- race on it: serialise them. */
+#define LSE_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+lse_status lse_solve_static(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
+                            int32_t max_iters, int32_t stop_when_unchanged, uint8_t *mask_dev, float *lsf_dev,
+                            void *stream);
+
 /* Human-readable name of a status code. */
 const char *lse_status_str(lse_status s);
 

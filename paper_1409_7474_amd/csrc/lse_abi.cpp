@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <set>
 #include <tuple>
@@ -386,50 +387,27 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     return LSE_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t bands) {
-    if (!p) return;
-    memset(p, 0, sizeof(*p));
-    p->height = height;
-    p->width = width;
-    p->bands = bands;
-    p->term = LSE_TERM_REGION;
-    p->order = LSE_ORDER_TABLE1;
-    p->image_dtype = LSE_F32;
-    p->storage = LSE_F32;
-    p->dt = 15.f;
-    p->sigma = 1.f;
-    p->ksize = 7;
-    p->sigma_img = 1.f;
-    p->ksize_img = 9;
-    p->edge_scale = 255.f;
-    p->reinit_every = 1;
-}
-
-size_t lse_workspace_bytes(const lse_params *p) {
+// Host-side checks of lse_init's arguments (nothing enqueued).
+lse_status check_init_args(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
+                           const void *workspace_dev, size_t workspace_bytes) {
     const lse_status v = validate(p);
-    if (v != LSE_OK && v != LSE_ERR_UNSUPPORTED) return 0;
-    return layout_of(p).total;
-}
-
-lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,
-                    size_t workspace_bytes, void *stream, lse_ctx **out) {
-    if (!out) return LSE_ERR_INVALID_ARG;
-    *out = nullptr;
-    lse_status v = validate(p);
     if (v != LSE_OK) return v;
     if (!image_dev || !init_mask_dev) return LSE_ERR_INVALID_ARG;
     const size_t esz = p->image_dtype == LSE_F32 ? 4 : 2;
     if (reinterpret_cast<uintptr_t>(image_dev) % esz) return LSE_ERR_INVALID_ARG;
     if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign)) return LSE_ERR_WORKSPACE;
-    const Layout L = layout_of(p);
-    if (workspace_bytes < L.total) return LSE_ERR_WORKSPACE;
+    if (workspace_bytes < layout_of(p).total) return LSE_ERR_WORKSPACE;
+    return LSE_OK;
+}
 
-    lse_ctx *c = new (std::nothrow) lse_ctx();
-    if (!c) return LSE_ERR_INVALID_ARG;
+// Table I step 1 into the context *c (arguments already checked): lay out
+// the workspace, enqueue the image conversion, the edge map or initial
+// statistics and the binary initial LSF.  tables_by_kernel: the constant
+// tables and the image arguments reach the device as kernel arguments rather
+// than host-to-device copies.
+hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
+                    void *workspace_dev, hipStream_t st, bool tables_by_kernel) {
+    const Layout L = layout_of(p);
     c->p = *p;
     c->region = p->term != LSE_TERM_EDGE;
     c->NB = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
@@ -495,10 +473,15 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
         A.plan = L.plan && use_plan ? reinterpret_cast<int *>(base + L.plan) : nullptr;
     }
 
-    hipStream_t st = as_stream(stream);
     c->last_stream = st;
-    hipError_t e = hipMemcpyAsync(c->taps, &c->host_taps, sizeof(Taps), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->dargs, &c->host_args, sizeof(ImgArgs), hipMemcpyHostToDevice, st);
+    hipError_t e;
+    if (tables_by_kernel) {
+        e = launch_put_bytes(&c->host_taps, sizeof(Taps), c->taps, st);
+        if (e == hipSuccess) e = launch_put_bytes(&c->host_args, sizeof(ImgArgs), c->dargs, st);
+    } else {
+        e = hipMemcpyAsync(c->taps, &c->host_taps, sizeof(Taps), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->dargs, &c->host_args, sizeof(ImgArgs), hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess) e = launch_init_state(c->st, 1, st);
     if (e == hipSuccess) e = launch_sched_reset(&c->host_args, st);
     if (e == hipSuccess) {
@@ -520,7 +503,47 @@ lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *i
     }
     if (e == hipSuccess) e = launch_pack_mask(init_mask_dev, c->bits[0], p->height, p->width, c->WW, st);
     if (e == hipSuccess) e = load_lsf(c, 1, st);
-    if (e != hipSuccess) {
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lse_params_default(lse_params *p, int32_t height, int32_t width, int32_t bands) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->height = height;
+    p->width = width;
+    p->bands = bands;
+    p->term = LSE_TERM_REGION;
+    p->order = LSE_ORDER_TABLE1;
+    p->image_dtype = LSE_F32;
+    p->storage = LSE_F32;
+    p->dt = 15.f;
+    p->sigma = 1.f;
+    p->ksize = 7;
+    p->sigma_img = 1.f;
+    p->ksize_img = 9;
+    p->edge_scale = 255.f;
+    p->reinit_every = 1;
+}
+
+size_t lse_workspace_bytes(const lse_params *p) {
+    const lse_status v = validate(p);
+    if (v != LSE_OK && v != LSE_ERR_UNSUPPORTED) return 0;
+    return layout_of(p).total;
+}
+
+lse_status lse_init(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,
+                    size_t workspace_bytes, void *stream, lse_ctx **out) {
+    if (!out) return LSE_ERR_INVALID_ARG;
+    *out = nullptr;
+    const lse_status v = check_init_args(p, image_dev, init_mask_dev, workspace_dev, workspace_bytes);
+    if (v != LSE_OK) return v;
+    lse_ctx *c = new (std::nothrow) lse_ctx();
+    if (!c) return LSE_ERR_INVALID_ARG;
+    if (init_ctx(c, p, image_dev, init_mask_dev, workspace_dev, as_stream(stream), false) != hipSuccess) {
         delete c;
         return LSE_ERR_DEVICE;
     }
@@ -694,6 +717,66 @@ void lse_destroy(lse_ctx *c) {
         (void)hipEventDestroy(e.b);
     }
     delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free solve
+//
+// lse_solve_static's workspace: a file-scope device array, one copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory, so host code never passes it to a kernel or a
+// copy: set-up takes each GPU's own address with hipGetSymbolAddress (once per
+// device, that device current) and every use goes through that address.
+static __device__ __align__(256) unsigned char scratch[LSE_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch` (nullptr on a HIP error).
+void *static_workspace() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+lse_status lse_solve_static(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
+                            int32_t max_iters, int32_t stop_when_unchanged, uint8_t *mask_dev, float *lsf_dev,
+                            void *stream) {
+    if (max_iters < 0 || !mask_dev || (lsf_dev && (reinterpret_cast<uintptr_t>(lsf_dev) & 3)))
+        return LSE_ERR_INVALID_ARG;
+    const lse_status v = validate(p);
+    if (v != LSE_OK) return v;
+    if (layout_of(p).total > LSE_STATIC_WORKSPACE_BYTES) return LSE_ERR_WORKSPACE;
+    void *ws = static_workspace();
+    if (!ws) return LSE_ERR_DEVICE;
+    const lse_status a = check_init_args(p, image_dev, init_mask_dev, ws, LSE_STATIC_WORKSPACE_BYTES);
+    if (a != LSE_OK) return a;
+    // The context lives on this stack frame: everything the device needs
+    // from it goes out as kernel arguments before the call returns.
+    lse_ctx c;
+    const hipStream_t s = as_stream(stream);
+    if (init_ctx(&c, p, image_dev, init_mask_dev, ws, s, true) != hipSuccess) return LSE_ERR_DEVICE;
+    for (int i = 0; i < max_iters; ++i) {
+        const lse_status r = enqueue_step(&c, stop_when_unchanged ? 1 : 0, s);
+        if (r != LSE_OK) return r;
+    }
+    lse_status r = lse_mask(&c, mask_dev, stream);
+    if (r == LSE_OK && lsf_dev) r = lse_lsf(&c, lsf_dev, stream);
+    return r;
 }
 
 const char *lse_status_str(lse_status s) {
@@ -1007,6 +1090,6 @@ void lse_batch_destroy(lse_batch *b) {
     delete b;
 }
 
-int32_t lse_version(void) { return 102; }
+int32_t lse_version(void) { return 103; }
 
 }  // extern "C"

@@ -199,6 +199,11 @@ size_t tile_smem_bytes(int r, int nch, int edge);
 bool fast_radius(int r);                 // the step kernel has a compiled variant for radius r
 int step_tiles(int H, int W, int edge);  // workgroup tiles of the step kernel for an H x W image
 int mpass_groups(int H, int W);          // workgroups of the normaliser pass
+// Copy `bytes` (a multiple of 4, at most kPutWords words) of host memory to
+// dst on the stream, carried as a kernel argument (no host-to-device copy).
+constexpr int kPutWords = 512;
+static_assert(sizeof(Taps) <= 4 * kPutWords && sizeof(ImgArgs) <= 4 * kPutWords, "tables fit one kernel argument");
+hipError_t launch_put_bytes(const void *host, size_t bytes, void *dst, hipStream_t s);
 hipError_t launch_init_state(DevState *st, int raw, hipStream_t s);
 hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);
 // mode 0: bands; 1: band mean x gray_scale in FP32 (edge map input); 2: band

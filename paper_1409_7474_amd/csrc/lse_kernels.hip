@@ -28,6 +28,8 @@
 // Region sums: FP32 within a workgroup, converted per workgroup to 64-bit
 // fixed point (scale 2^s) and added atomically, so totals do not depend on
 // workgroup scheduling or on which other images share a launch.
+#include <string.h>
+
 #include "lse_device.h"
 
 namespace lse {
@@ -439,6 +441,25 @@ hipError_t launch_plan(const ImgArgs *dev_args, int k, hipStream_t s) {
 __global__ void batch_prepare_kernel(ImgArgs *args, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) args[i].n0 = args[i].st->iters;
+}
+
+// Host bytes carried to the device as a kernel argument: the launch copies
+// them when it is enqueued, so the source may change or vanish afterwards and
+// no host-to-device copy (or pinned staging) is involved.
+struct alignas(16) Words {
+    uint32_t w[kPutWords];
+};
+__global__ void put_words_kernel(Words src, uint32_t *__restrict__ dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src.w[i];
+}
+
+hipError_t launch_put_bytes(const void *host, size_t bytes, void *dst, hipStream_t s) {
+    if (bytes % 4 || bytes > sizeof(Words) || (reinterpret_cast<uintptr_t>(dst) & 3)) return hipErrorInvalidValue;
+    Words w;
+    memset(&w, 0, sizeof(w));
+    memcpy(w.w, host, bytes);
+    hipLaunchKernelGGL(put_words_kernel, dim3(1), dim3(256), 0, s, w, static_cast<uint32_t *>(dst), (int)(bytes / 4));
+    return hipGetLastError();
 }
 
 hipError_t launch_init_state(DevState *st, int raw, hipStream_t s) {

@@ -33,8 +33,11 @@ EXPORTS = (
     "lse_params_default", "lse_workspace_bytes", "lse_init", "lse_step", "lse_run", "lse_mask",
     "lse_lsf", "lse_set_mask", "lse_set_lsf", "lse_edge_map", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
     "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_run",
-    "lse_batch_destroy", "lse_status_str", "lse_version",
+    "lse_batch_destroy", "lse_solve_static", "lse_status_str", "lse_version",
 )
+
+# Size of the library-owned workspace of lse_solve_static (per GPU).
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class lse_params(ctypes.Structure):
@@ -133,6 +136,8 @@ def load() -> ctypes.CDLL:
     lib.lse_batch_run.restype = st
     lib.lse_batch_destroy.argtypes = [vp]
     lib.lse_batch_destroy.restype = None
+    lib.lse_solve_static.argtypes = [P(lse_params), vp, vp, i32, i32, vp, vp, vp]
+    lib.lse_solve_static.restype = st
     lib.lse_status_str.argtypes = [st]
     lib.lse_status_str.restype = ctypes.c_char_p
     lib.lse_version.argtypes = []
@@ -260,6 +265,14 @@ def lse_batch_run(batch, iters: int, stop_when_unchanged: bool = False, flags: i
 
 def lse_batch_destroy(batch) -> None:
     load().lse_batch_destroy(batch)
+
+
+def lse_solve_static(p: lse_params, image_ptr: int, mask_ptr: int, max_iters: int, stop_when_unchanged: bool,
+                     mask_out_ptr: int, lsf_out_ptr=None, stream: int = 0) -> None:
+    """One whole solve in the library's own per-GPU workspace (no allocation)."""
+    _check(load().lse_solve_static(ctypes.byref(p), image_ptr, mask_ptr, int(max_iters),
+                                   int(bool(stop_when_unchanged)), mask_out_ptr, lsf_out_ptr, stream),
+           "lse_solve_static")
 
 
 # ------------------------------------------------------------ torch wrapper

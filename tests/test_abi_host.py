@@ -157,3 +157,21 @@ def test_batch_argument_checks():
     assert lib.lse_batch_create(arr, 0, None, 256, 1 << 20, None, None) == lse.LSE_ERR_INVALID_ARG
     assert lib.lse_batch_run(None, 3, 0, 0, None) == lse.LSE_ERR_INVALID_ARG
     lib.lse_batch_destroy(None)
+
+
+def test_static_solve_argument_checks():
+    """lse_solve_static rejects bad arguments and images beyond its fixed
+    workspace on the host, before any HIP call."""
+    lib = lse.load()
+    small = lse.make_params(64, 64, 1)
+    big = lse.make_params(2100, 2100, 4)
+    assert lse.lse_workspace_bytes(small) <= lse.STATIC_WORKSPACE_BYTES < lse.lse_workspace_bytes(big)
+    P = ctypes.byref
+    assert lib.lse_solve_static(P(big), 16, 16, 10, 0, 16, None, None) == lse.LSE_ERR_WORKSPACE
+    assert lib.lse_solve_static(P(small), 16, 16, -1, 0, 16, None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_solve_static(P(small), 16, 16, 10, 0, None, None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_solve_static(P(small), 16, 16, 10, 0, 16, 18, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_solve_static(None, 16, 16, 10, 0, 16, None, None) == lse.LSE_ERR_INVALID_ARG
+    bad = lse.make_params(64, 64, 1)
+    bad.dt = -1.0
+    assert lib.lse_solve_static(P(bad), 16, 16, 10, 0, 16, None, None) == lse.LSE_ERR_INVALID_ARG

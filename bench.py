@@ -1,39 +1,44 @@
 """Throughput benchmark of the fast level set evolution on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
-                    [--job both|concurrent|sequential]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision]
+                    [--job all|sequential|concurrent|dense]
                     [--sections batched,precision,serving]
 
-One step = one whole job on the 4096 x 4096 x 4 multiband scene (40 roofs,
-6 roads, noise 0.03; sigma 1.5, 11 x 11 template, dt 15): lse_init + 200
-region-term iterations and lse_init + 200 edge-term iterations, with the
-image already resident in HBM.  The two solves are independent and run on two
-HIP streams at once (their latency-bound steps overlap on the device; the
-edge solve's stream runs on 7/8 of the CUs, so the region solve, the longer
-chain, always finds room); `sequential` times the same job with one solve
-after the other on one stream.  --job concurrent or --job sequential times
-one of the two only, so that a kernel trace of the run has one launch
-configuration.  `value` = pixel-iterations per second over the K timed steps
-of the two-stream job (2 x 200 x 4096^2 per step).  The line also carries
-  * roofline -- algorithmic HBM bytes of the fused region step kernel per
-    launch / its mean launch time (HIP events carried by the dispatch of one
-    launch in 8 on the launch stream) in the timed sequential pass, where the
-    kernel has the device to itself, against the MI355X HBM peak of 8 TB/s;
-    roofline_concurrent -- the same in the timed two-stream job;
+One step = one whole job on the 8192 x 8192 x 4 runway scene (one runway
+60-120 px wide and 2000-4000 px long, 200 roofs, noise 0.03; sigma 2, 13 x 13
+template, dt 15, FP32 storage): lse_init + 300 region-term iterations + the
+mask, then lse_init + 300 edge-term iterations + the mask, one after the other
+on one HIP stream, with the image already resident in HBM.  `value` =
+pixel-iterations per second over the K timed steps (2 x 300 x 8192^2 per
+step).  `--workload large` runs the 4096 x 4096 x 4 scene (sigma 1.5, 11 x 11,
+200 iterations) instead.  The line also carries
+  * concurrent -- the same job with each solve on its own HIP stream;
+  * roofline -- the fused region step kernel on a fully active step (an 8 x 8
+    checkerboard state: every tile heavy, every pixel needs its data term):
+    algorithmic HBM bytes per launch (image read once, binary state read and
+    written once) / the kernel's mean duration from HIP events carried by its
+    own dispatch packet, against the MI355X HBM peak of 8 TB/s;
+    roofline_edge -- the same for the edge step;
+  * roofline_front_sparse -- the region step inside the timed job, on the
+    bytes its launches needed (settled tiles are not visited);
+  * per_iteration -- flips, visited / heavy tile fractions and needed-pixel
+    fractions per iteration (untimed counting replay);
   * cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same job
-    (a few iterations of each term on the full image), on this host's cores;
+    (3 iterations of each term on the full image), on this host's cores;
   * batched -- 64 uneven images (sides 512-2048, 4 bands, sigma 1 / 7 x 7,
     150 iterations): one batched, graph-replayed launch sequence (FP32 and
     FP16 storage) against the 64 images run one after another (plain FP32);
-  * precision -- 8192 x 8192 x 4 runway scene (sigma 2 / 13 x 13, 300
-    iterations) with the image / edge map stored in FP32, FP16 and BF16:
-    throughput, and agreement of the 16-bit runs with the FP32 run; and a
-    1024 x 1024 window of it against the FP64 oracle;
+  * precision -- the 8192 x 8192 x 4 scene with the image / edge map stored in
+    FP32, FP16 and BF16: throughput, agreement of the 16-bit runs with the FP32
+    run, and FP64 oracle checks;
   * serving -- 2000 jobs (sides log-uniform 256-4096, 1 or 4 bands, region or
-    edge, 100-300 iterations) arriving as a Poisson stream at 80 % of the
-    measured batched capacity: continuous batching with FP16 storage under a
-    200 GB budget (and a 2 GB budget for queueing) against one-at-a-time
-    plain FP32 solves of the same trace; throughput and p50 / p99 latency.
+    edge, 100-300 iterations) arriving as a Poisson stream at several fractions
+    of the measured batched capacity: continuous batching with FP16 storage
+    under a 200 GB budget (and a 2 GB budget for queueing) against
+    one-at-a-time plain FP32 solves of the same trace; throughput and p50 /
+    p99 latency.
+--job sequential / concurrent / dense runs one part only, so that a kernel
+trace of the run has one launch configuration per kernel.
 """
 import argparse
 import json
@@ -48,10 +53,15 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "LSE Mpixel-iter/s + % HBM peak, batched vs plain FP32; p50/p99 job latency"
 
 WORKLOADS = {
-    # name: (generator kwargs, sigma, ksize, iterations, terms)
-    "large": (dict(size=4096), 1.5, 11, 200, ("region", "edge")),
-    "tiny": (dict(size=256), 1.0, 7, 100, ("region",)),
-    "precision": (dict(size=8192), 2.0, 13, 300, ("region", "edge")),
+    # name: (generator kwargs, sigma, ksize, iterations, terms, oracle iterations per term in the CPU sample)
+    "precision": (dict(size=8192), 2.0, 13, 300, ("region", "edge"), 3),
+    "large": (dict(size=4096), 1.5, 11, 200, ("region", "edge"), 12),
+    "tiny": (dict(size=256), 1.0, 7, 100, ("region",), 100),
+}
+WORKLOAD_TEXT = {
+    "precision": "runway 60-120 px wide, 2000-4000 px long, 200 roofs, noise 0.03",
+    "large": "40 roofs, 6 roads, noise 0.03",
+    "tiny": "3 rectangles, noise 0.05",
 }
 
 
@@ -60,18 +70,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="precision", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--job", default="both", choices=["both", "concurrent", "sequential"],
-                    help="timed job: solves on concurrent streams (both: and a timed sequential pass after it), "
-                         "or one after the other on one stream")
+    ap.add_argument("--job", default="all", choices=["all", "sequential", "concurrent", "dense"],
+                    help="all: the timed sequential job (value), a timed concurrent pass, the fully active step "
+                         "roofline and the counting replay; the others run one part only")
     ap.add_argument("--sections", default="batched,precision,serving",
                     help="extra sections after the headline job: batched, precision, serving (comma-separated; "
                          "empty for none)")
     ap.add_argument("--serve-jobs", type=int, default=2000)
-    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of batched capacity")
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.8,0.95",
+                    help="arrival rates as fractions of the measured batched capacity")
     ap.add_argument("--batch-images", type=int, default=64)
-    ap.add_argument("--cpu-iters", type=int, default=24, help="oracle iterations per term in the CPU sample (~10-15 s)")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="oracle iterations per term in the CPU sample (0: the workload's default, ~10-30 s)")
     ap.add_argument("--profile-summary", default="",
                     help="print the markdown summary of the rocprofv3 runs under this directory and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -106,10 +118,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per launch of `kernel_name` from a committed rocprofv3
-    summary (profiles/*.md, FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel
-    calibration), only if it was taken on the current kernel source."""
+def measured_traffic(kernel_name, job):
+    """HBM bytes per launch of `kernel_name` in the `job` configuration
+    (dense / sequential) from a committed rocprofv3 summary (profiles/*.md,
+    FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration), only if it
+    was taken on the current kernel source."""
     import glob
     sha = kernel_source_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -121,64 +134,43 @@ def measured_traffic(kernel_name):
                 continue
             if data.get("kernel_source_sha256") != sha:
                 continue
-            t = data.get("per_launch_traffic", {}).get(kernel_name)
+            t = data.get("per_launch_traffic", {}).get(job, {}).get(kernel_name)
             if t:
                 return t["read_bytes"] + t["write_bytes"], os.path.relpath(path, ROOT)
     return None, None
 
 
-def _hip():
-    import ctypes
-    return ctypes.CDLL("libamdhip64.so")
-
-
-def cu_masked_stream(ncu, first, count):
-    """A HIP stream (default priority) whose kernels run only on CUs first ..
-    first + count - 1 (hipExtStreamCreateWithCUMask); raises if the runtime
-    refuses the mask.  Release it with destroy_stream."""
-    import ctypes
-    hip = _hip()
-    words = (ncu + 31) // 32
-    mask = (ctypes.c_uint32 * words)()
-    for i in range(first, min(first + count, ncu)):
-        mask[i // 32] |= 1 << (i % 32)
-    s = ctypes.c_void_p()
-    rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(s), ctypes.c_uint32(words), mask)
-    if rc != 0:
-        raise RuntimeError(f"hipExtStreamCreateWithCUMask failed ({rc}) for CUs {first}..{first + count - 1}")
-    return s.value
-
-
-def destroy_stream(s):
-    import ctypes
-    _hip().hipStreamDestroy(ctypes.c_void_p(s))
-
-
+# rocprofv3 runs behind the committed summary (profiles/), each in its own
+# process; OUT is the output directory, $R the repository.
+_B = "python3 $R/bench.py --no-cpu-baseline --sections ''"
 PROFILE_COMMANDS = [
-    "rocprofv3 --kernel-trace --stats -d OUT/trace_concurrent -o run -- python3 $R/bench.py --steps 2 --warmup 1 "
-    "--no-cpu-baseline --sections '' --job concurrent",
-    "rocprofv3 --kernel-trace --stats -d OUT/trace_sequential -o run -- python3 $R/bench.py --steps 2 --warmup 1 "
-    "--no-cpu-baseline --sections '' --job sequential",
-    "rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/FETCH_SIZE -o run -- python3 $R/bench.py --steps 1 "
-    "--warmup 0 --no-cpu-baseline --sections '' --job sequential",
-    "rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/WRITE_SIZE -o run -- python3 $R/bench.py --steps 1 "
-    "--warmup 0 --no-cpu-baseline --sections '' --job sequential",
+    f"rocprofv3 --kernel-trace --stats -d OUT/trace_sequential -o run -- {_B} --steps 2 --warmup 1 --job sequential",
+    f"rocprofv3 --kernel-trace --stats -d OUT/trace_dense -o run -- {_B} --steps 5 --warmup 1 --job dense",
+    f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/dense_FETCH_SIZE -o run -- {_B} --steps 3 "
+    "--warmup 1 --job dense",
+    f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/dense_WRITE_SIZE -o run -- {_B} --steps 3 "
+    "--warmup 1 --job dense",
+    f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/seq_FETCH_SIZE -o run -- {_B} --steps 1 "
+    "--warmup 0 --job sequential",
+    f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/seq_WRITE_SIZE -o run -- {_B} --steps 1 "
+    "--warmup 0 --job sequential",
     "rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/cal_FETCH_SIZE -o run -- python3 $R/bench.py "
     "--calibrate-copy-mib 256",
     "rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/cal_WRITE_SIZE -o run -- python3 $R/bench.py "
     "--calibrate-copy-mib 256",
-    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY "
-    "SQ_INSTS_VMEM_RD --kernel-trace --stats -d OUT/sq -o run -- python3 $R/bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --sections '' --job sequential",
+    f"rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY "
+    f"SQ_INSTS_VMEM_RD --kernel-trace --stats -d OUT/dense_sq -o run -- {_B} --steps 3 --warmup 1 --job dense",
+    f"rocprofv3 --pmc SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_LDS_ADDR_CONFLICT SQ_LDS_UNALIGNED_STALL "
+    f"--kernel-trace --stats -d OUT/dense_lds -o run -- {_B} --steps 3 --warmup 1 --job dense",
 ]
 
 
 def profile_summary(base):
     """Markdown summary of the rocprofv3 runs of PROFILE_COMMANDS under `base`
     (one directory per run, each holding run_results.db): kernel-trace
-    statistics of both job configurations, per-dispatch byte counters scaled
-    by the copy calibration, SQ counters of the step kernels, and the
-    per-launch traffic that measured_traffic reads back."""
+    statistics of both launch configurations, per-dispatch byte counters
+    scaled by the copy calibration, SQ and LDS counters of the fully active
+    step, and the per-launch traffic that measured_traffic reads back."""
     import sqlite3
 
     def q(db, sql):
@@ -194,49 +186,54 @@ def profile_summary(base):
         return k.split("(")[0].replace("void ", "")
 
     sha = kernel_source_digest()
-    f, w = counters("FETCH_SIZE"), counters("WRITE_SIZE")
     cal_f = [v for (k, c), v in counters("cal_FETCH_SIZE").items() if "copyBuffer" in k][0]
     cal_w = [v for (k, c), v in counters("cal_WRITE_SIZE").items() if "copyBuffer" in k][0]
     copy_kib = 256 * 1024
     fac_f, fac_w = copy_kib / cal_f, copy_kib / cal_w
-    out = ["# rocprofv3: fast LSE step on 4096x4096x4 (region + edge, sigma 1.5, 11x11, 200 iterations each)\n",
-           "Workload: `bench.py` default (the 4096 x 4096 x 4 multiband scene; one step = one region job of 200 "
-           "iterations + one edge job of 200 iterations).\n",
+    out = ["# rocprofv3: fast LSE step on 8192x8192x4 (region + edge, sigma 2, 13x13, 300 iterations each)\n",
+           "Workload: `bench.py` default (the 8192 x 8192 x 4 runway scene; one step = one region solve of 300 "
+           "iterations + one edge solve of 300 iterations, one after the other), and its fully active step "
+           "(`--job dense`: an 8 x 8 checkerboard state loaded before every step, so every tile is heavy).\n",
            f"Kernel sources: `paper_1409_7474_amd/csrc/*.hip, *.h` (bench.kernel_source_digest) sha256 `{sha}`.\n",
            "## Commands (run from /tmp with TMPDIR=/tmp, repo at $R)\n", "```", *PROFILE_COMMANDS,
            "python3 $R/bench.py --profile-summary OUT", "```\n",
-           "The step timing in the PMC runs includes the untimed counting replay of bench.py (count_needed_kernel); "
-           "the trace runs are the reference for durations.  Every run traces the warm-up, the timed steps and the "
-           "counting replay, all in the one launch configuration that --job names.\n"]
-    for j in ("concurrent", "sequential"):
-        what = ("the region and edge solves on two concurrent streams, the edge one on 7/8 of the CUs (the timed "
-                "job of bench.py; its `roofline_concurrent`)" if j == "concurrent"
-                else "the two solves one after the other on one stream (bench.py's timed `sequential` pass; its "
-                     "`roofline`)")
+           "The PMC runs of `--job sequential` include its untimed counting replay (count_needed_kernel, "
+           "count_tiles_kernel); the trace runs are the reference for durations.\n"]
+    for j, what in (("sequential", "the headline job: the region and edge solves one after the other on one "
+                                   "stream (bench.py `value`, `roofline_front_sparse`)"),
+                    ("dense", "fully active steps (bench.py `roofline`, `roofline_edge`)")):
         out.append(f"## Kernel trace (--stats), --job {j}: {what}\n")
         out.append("| kernel | calls | mean (us) | % of GPU time |\n|---|---:|---:|---:|")
         for n, c, t, a, p in q(os.path.join(base, f"trace_{j}", "run_results.db"),
-                               "select name,total_calls,total_duration,average,percentage from top_kernels limit 14"):
+                               "select name,total_calls,total_duration,average,percentage from top_kernels limit 16"):
             out.append(f"| `{short(n)}` | {c} | {a:.2f} | {p:.1f} |")
         out.append("")
     out.append("## Byte counters (per dispatch, scaled)\n")
     out.append(f"Calibration: a plain 256 MiB device copy reads FETCH_SIZE = {cal_f:.0f} KiB and WRITE_SIZE = "
                f"{cal_w:.0f} KiB per dispatch, so FETCH_SIZE is scaled by {fac_f:.3f} and WRITE_SIZE by {fac_w:.3f}.\n")
-    out.append("| kernel | FETCH_SIZE (KiB, raw) | read (MB, scaled) | WRITE_SIZE (KiB, raw) | written (MB, scaled) |"
-               "\n|---|---:|---:|---:|---:|")
     traffic = {}
-    for (k, c), v in sorted(f.items()):
-        if "lse::" not in k:
-            continue
-        wv = w.get((k, "WRITE_SIZE"), 0)
-        out.append(f"| `{short(k)}` | {v:.1f} | {v * 1024 * fac_f / 1e6:.2f} | {wv:.1f} | {wv * 1024 * fac_w / 1e6:.2f} |")
-        traffic[short(k)] = {"read_bytes": int(v * 1024 * fac_f), "write_bytes": int(wv * 1024 * fac_w)}
-    out.append("\n## SQ counters (per dispatch)\n")
-    out.append("| kernel | counter | value |\n|---|---|---:|")
-    for (k, c), v in sorted(counters("sq").items()):
-        if "step_fast" in k or "mpass" in k:
-            out.append(f"| `{short(k)}` | {c} | {v:.0f} |")
-    out.append("\n## Machine-readable traffic (read by bench.py when the kernel source hash matches)\n")
+    for j, tag in (("dense", "dense"), ("sequential", "seq")):
+        f, w = counters(f"{tag}_FETCH_SIZE"), counters(f"{tag}_WRITE_SIZE")
+        out.append(f"### --job {j}\n")
+        out.append("| kernel | FETCH_SIZE (KiB, raw) | read (MB, scaled) | WRITE_SIZE (KiB, raw) | written (MB, "
+                   "scaled) |\n|---|---:|---:|---:|---:|")
+        traffic[j] = {}
+        for (k, c), v in sorted(f.items()):
+            if "lse::" not in k:
+                continue
+            wv = w.get((k, "WRITE_SIZE"), 0)
+            out.append(f"| `{short(k)}` | {v:.1f} | {v * 1024 * fac_f / 1e6:.2f} | {wv:.1f} | "
+                       f"{wv * 1024 * fac_w / 1e6:.2f} |")
+            traffic[j][short(k)] = {"read_bytes": int(v * 1024 * fac_f), "write_bytes": int(wv * 1024 * fac_w)}
+        out.append("")
+    for run, title in (("dense_sq", "SQ counters"), ("dense_lds", "LDS counters")):
+        out.append(f"## {title} of the fully active step (per dispatch)\n")
+        out.append("| kernel | counter | value |\n|---|---|---:|")
+        for (k, c), v in sorted(counters(run).items()):
+            if "step_fast" in k or "mpass" in k:
+                out.append(f"| `{short(k)}` | {c} | {v:.0f} |")
+        out.append("")
+    out.append("## Machine-readable traffic (read by bench.py when the kernel source hash matches)\n")
     out.append("```json")
     out.append(json.dumps({"kernel_source_sha256": sha, "per_launch_traffic": traffic}))
     out.append("```")
@@ -430,10 +427,17 @@ def section_serving(args):
     serve.serve(probe[:20], pool, budget_bytes=budget, storage="f16")  # warm-up
     cap = serve.serve(probe, pool, budget_bytes=budget, storage="f16")
     cap_pxit = cap.pixel_iters / cap.makespan_s
-    qps = args.serve_load * cap_pxit / mean_work
-    trace = synth.serving_trace(0, n_jobs=args.serve_jobs, qps=qps)
-    served = serve.serve(trace, pool, budget_bytes=budget, storage="f16", keep_masks=True)
-    plain = serve.serve_plain(trace, pool, storage="f32", keep_masks=True)
+    loads = [float(x) for x in args.serve_loads.split(",") if x]
+    head = min(loads, key=lambda x: abs(x - 0.8))
+    sweep = {}
+    for ld in loads:
+        qps = ld * cap_pxit / mean_work
+        trace = synth.serving_trace(0, n_jobs=args.serve_jobs, qps=qps)
+        run = serve.serve(trace, pool, budget_bytes=budget, storage="f16", keep_masks=ld == head)
+        sweep[f"{ld:.0%}"] = dict(run.summary(), qps=round(qps, 1))
+        if ld == head:
+            served, head_trace, head_qps = run, trace, qps
+    plain = serve.serve_plain(head_trace, pool, storage="f32", keep_masks=True)
     dis, px = 0, 0
     worst = 0.0
     for a, b in zip(served.records, plain.records):
@@ -442,15 +446,27 @@ def section_serving(args):
         px += a.pixels
         worst = max(worst, d / a.pixels)
         a.mask = b.mask = None
-    small = serve.serve(trace[:300], pool, budget_bytes=2 << 30, storage="f16")
-    return {"workload": f"{len(trace)} jobs, Poisson arrivals at {qps:.1f} jobs/s ({args.serve_load:.0%} of the "
-                        f"measured batched capacity), side log-uniform 256-4096, 1 or 4 bands, region/edge 50/50, "
-                        f"100-300 iterations, sigma 1.5 / 11x11; inputs cut from a resident 4096^2 pool scene",
+    small = serve.serve(head_trace[:300], pool, budget_bytes=2 << 30, storage="f16")
+    return {"workload": f"{len(head_trace)} jobs, Poisson arrivals, side log-uniform 256-4096, 1 or 4 bands, "
+                        f"region/edge 50/50, 100-300 iterations, sigma 1.5 / 11x11; inputs cut from a resident "
+                        f"4096^2 pool scene; arrival rates {', '.join(f'{x:.0%}' for x in loads)} of the measured "
+                        f"batched capacity, headline {head:.0%} ({head_qps:.1f} jobs/s)",
             "capacity": {"Mpixel_iter_per_s": round(cap_pxit / 1e6, 1),
                          "jobs_per_s": round(cap_pxit / mean_work, 2), "probe_jobs": len(probe)},
-            "batched_f16_200GB": served.summary(), "plain_f32": plain.summary(),
+            "load_sweep_batched_f16_200GB": sweep,
+            "batched_f16_200GB": sweep[f"{head:.0%}"], "plain_f32": plain.summary(),
             "batched_f16_2GB_first300": small.summary(),
             "mask_disagreement_batched_f16_vs_plain_f32": {"all_pixels": dis / px, "worst_job": worst}}
+
+
+def checkerboard(h, w, cell=8):
+    """A binary state whose front covers the whole image: cells of cell x cell
+    pixels alternate inside / outside, so every step tile is heavy and, once
+    smoothed, almost every pixel has a nonzero gradient."""
+    import numpy as np
+    yy = (np.arange(h) // cell)[:, None]
+    xx = (np.arange(w) // cell)[None, :]
+    return ((yy + xx) % 2).astype(np.uint8)
 
 
 def main():
@@ -472,45 +488,33 @@ def main():
 
     from paper_1409_7474_amd import lse
 
-    gen_kw, sigma, ksize, iters, terms = WORKLOADS[args.workload]
+    gen_kw, sigma, ksize, iters, terms, cpu_iters = WORKLOADS[args.workload]
     scene = make_scene(args.workload)
     h, w, b = scene.image.shape
+    nb = 4 if b == 3 else b
     dev = torch.device("cuda:0")
     img = torch.tensor(scene.image, dtype=torch.float32, device=dev)
     masks = {"region": torch.tensor(scene.init_region, device=dev),
              "edge": torch.tensor(scene.init_edge, device=dev)}
     params = {t: lse.make_params(h, w, b, term=t, sigma=sigma, ksize=ksize) for t in terms}
-    for p in params.values():
-        p.image_dtype = 0
-    # The solves of the two terms are independent: each has its own workspace
-    # and HIP stream (default priority), so their latency-bound steps overlap
-    # on the device.  The region solve (step + normaliser per iteration, the
-    # longer chain) may use every CU; the edge solve's stream is limited to
-    # 7/8 of them, so some CUs always have room for the region tiles.  A
-    # sequential pass on one stream (the region one) is timed as well.
-    ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    edge_cus = ncu * 7 // 8
     streams = {t: torch.cuda.Stream(dev) for t in terms}
     sids = {t: int(streams[t].cuda_stream) for t in terms}
-    if "edge" in sids and len(terms) > 1:
-        try:
-            sids["edge"] = cu_masked_stream(ncu, 0, edge_cus)
-        except RuntimeError as e:  # the line then states the schedule that ran
-            print(f"bench.py: {e}; the edge solve runs on all CUs", file=sys.stderr)
-            edge_cus = ncu
-    ws, ws_ptr, nbytes = {}, {}, {}
+    ws_ptr, nbytes, ws = {}, {}, {}
     for t in terms:
         nbytes[t] = lse.lse_workspace_bytes(params[t])
         ws[t] = torch.empty(nbytes[t] + 256, dtype=torch.uint8, device=dev)
         ws_ptr[t] = ws[t].data_ptr() + ((-ws[t].data_ptr()) % 256)
     mask_out = {t: torch.empty((h, w), dtype=torch.uint8, device=dev) for t in terms}
-    chunk = 20  # iterations enqueued per term in turn, so both streams start at once
+    chunk = 20  # concurrent pass: iterations enqueued per term in turn, so both streams start at once
 
-    # Kernel durations come from events carried by the dispatch of one step
-    # and normaliser launch in 8 (iterations 7, 15, ...): the events of a
-    # timed launch cost the device a few microseconds, so timing every launch
-    # would lower the throughput being measured.
-    def job(profile_into=None, flags=lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(3), concurrent=True):
+    # One step of the benchmark = one whole job: for each term, lse_init +
+    # `iters` iterations + the mask.  Sequential: the solves one after the
+    # other on one stream (each has the device to itself).  Concurrent: each
+    # solve on its own stream (default priority), so their latency-bound
+    # launches overlap.  Kernel durations come from events carried by the
+    # dispatch of one step and normaliser launch in 8 (iterations 7, 15, ...):
+    # the events of a timed launch cost the device a few microseconds.
+    def job(profile_into=None, flags=lse.PROFILE_TIMING | lse.PROFILE_SAMPLE(3), concurrent=False):
         one = sids[terms[0]]
         sid = {t: (sids[t] if concurrent else one) for t in terms}
         ctx = {}
@@ -530,127 +534,93 @@ def main():
         for t in terms:
             if profile_into is not None:
                 p = lse.lse_profile_read(ctx[t])
-                acc = profile_into.setdefault(t, {"step_ms": 0.0, "step_n": 0, "mpass_ms": 0.0, "mpass_n": 0,
-                                                  "needed_px": 0, "counted": 0})
+                acc = profile_into.setdefault(t, {"step_ms": 0.0, "step_n": 0, "mpass_ms": 0.0, "mpass_n": 0})
                 acc["step_ms"] += p.step_ms
                 acc["step_n"] += p.step_launches
                 acc["mpass_ms"] += p.mpass_ms
                 acc["mpass_n"] += p.mpass_launches
-                acc["needed_px"] += p.needed_pixels
-                acc["counted"] += p.counted_steps
-                acc["dense_bytes_per_px"] = lse.lse_step_bytes_per_pixel(ctx[t])
         torch.cuda.synchronize()
         for t in terms:
             lse.lse_destroy(ctx[t])
 
-    conc = args.job != "sequential"
-    for _ in range(args.warmup):
-        job(concurrent=conc)
-    torch.cuda.synchronize()
-    prof = {}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        job(prof, concurrent=conc)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    px_it = h * w * iters * len(terms) * args.steps
-    value = px_it / elapsed / 1e6
-    inside = {t: round(float(mask_out[t].float().mean().item()), 4) for t in terms}
-    concurrent_masks = {t: mask_out[t].clone() for t in terms}
-    # The same job with the two solves one after the other on one stream.
-    prof_seq, sequential = prof, None
-    if args.job == "both":
-        prof_seq = {}
+    def timed_job(concurrent):
+        prof = {}
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            job(prof_seq, concurrent=False)
+            job(prof, concurrent=concurrent)
         torch.cuda.synchronize()
-        seq_elapsed = time.perf_counter() - t0
-        sequential = {"ms_per_step": round(seq_elapsed * 1e3 / args.steps, 3),
-                      "value": round(px_it / seq_elapsed / 1e6, 1),
-                      "masks_equal_to_concurrent": all(torch.equal(concurrent_masks[t], mask_out[t]) for t in terms)}
+        return time.perf_counter() - t0, prof
 
-    # Algorithmic bytes of the step kernel: an untimed replay of the same
-    # (deterministic) job counts, per step, the pixels whose image value the
-    # step needs; each costs one pixel of image (region: B x 4 bytes) or edge
-    # map (4 bytes); the binary state adds one bit read and one bit written.
-    counted = {}
-    job(counted, lse.PROFILE_COUNT, concurrent=conc)
-    torch.cuda.synchronize()
-    if sids.get("edge") not in (None, int(streams["edge"].cuda_stream)):
-        destroy_stream(sids["edge"])
+    px_it = h * w * iters * len(terms) * args.steps
+    out = {"metric": METRIC, "value": None, "unit": "Mpixel-iter/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{h}x{w}x{b} multiband scene ({args.workload}; {WORKLOAD_TEXT[args.workload]}), "
+                                  f"{'+'.join(terms)} terms, {iters} iterations each, sigma {sigma}, "
+                                  f"{ksize}x{ksize} template, dt 15, FP32 storage, image resident in HBM; one step = "
+                                  f"lse_init + {iters} iterations + mask of each term, the solves one after the "
+                                  "other on one HIP stream",
+                      "global_batch": 1, "parallelism": "single GPU"},
+           "gpu": torch.cuda.get_device_name(0)}
+    kname_region = f"lse::step_fast_kernel<{ksize // 2}, {nb}, false, float>"
+    kname_edge = f"lse::step_fast_kernel<{ksize // 2}, 1, true, float>"
 
-    def step_bytes(t):
-        c = counted[t]
-        per_px = 4.0 * b if t == "region" else 4.0
-        return per_px * c["needed_px"] / max(c["counted"], 1) + 2.0 * h * w / 8.0
+    if args.job in ("all", "sequential", "concurrent"):
+        conc = args.job == "concurrent"
+        for _ in range(args.warmup):
+            job(concurrent=conc)
+        elapsed, prof = timed_job(conc)
+        out["value"] = round(px_it / elapsed / 1e6, 1)
+        out["ms_per_step"] = round(elapsed * 1e3 / args.steps, 3)
+        if conc:
+            out["config"]["workload"] = out["config"]["workload"].replace(
+                "the solves one after the other on one HIP stream", "each solve on its own HIP stream")
+        out["final_mask_inside_fraction"] = {t: round(float(mask_out[t].float().mean().item()), 5) for t in terms}
+        out["per_term"] = {}
+        for t, pr in prof.items():
+            d = {"step_kernel_us": round(pr["step_ms"] / max(pr["step_n"], 1) * 1e3, 2)}
+            if pr["mpass_n"]:
+                d["mpass_kernel_us"] = round(pr["mpass_ms"] / pr["mpass_n"] * 1e3, 2)
+            out["per_term"][t] = d
+        if args.job == "all" and len(terms) > 1:
+            seq_masks = {t: mask_out[t].clone() for t in terms}
+            c_elapsed, _ = timed_job(True)
+            out["concurrent"] = {
+                "what": "the same job with each solve on its own HIP stream (default priority, all CUs), "
+                        "so the two latency-bound solves overlap on the device",
+                "ms_per_step": round(c_elapsed * 1e3 / args.steps, 3), "value": round(px_it / c_elapsed / 1e6, 1),
+                "masks_equal_to_sequential": all(torch.equal(seq_masks[t], mask_out[t]) for t in terms)}
 
-    dom = "region" if "region" in prof else terms[0]
-    kname = f"lse::step_fast_kernel<{ksize // 2}, {(4 if b == 3 else b) if dom == 'region' else 1}, " \
-            f"{'false' if dom == 'region' else 'true'}, float>"
-    traffic, traffic_src = measured_traffic(kname)
+    if args.job in ("all", "dense"):
+        out["roofline"], dense_edge = dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids,
+                                                      kname_region, kname_edge)
+        if dense_edge:
+            out["roofline_edge"] = dense_edge
 
-    def roofline_of(pf):
-        pr = pf[dom]
-        step_ms = pr["step_ms"] / max(pr["step_n"], 1)
-        alg = step_bytes(dom)
-        achieved = alg / (step_ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
-                "kernel": f"step_fast_kernel ({dom} term, B={b})", "mean_launch_us": round(step_ms * 1e3, 2),
+    if args.job in ("all", "sequential"):
+        counted = count_replay(lse, torch, img, masks, params, terms, iters, ws_ptr, nbytes, sids[terms[0]])
+        out["per_iteration"] = {t: c["summary"] for t, c in counted.items()}
+        if "prof" in locals() and "region" in prof:
+            pr = prof["region"]
+            step_ms = pr["step_ms"] / max(pr["step_n"], 1)
+            c = counted["region"]
+            alg = 4.0 * nb * c["needed_px_per_step"] + 2.0 * h * w / 8.0
+            traffic, src = measured_traffic(kname_region, "sequential")
+            out["roofline_front_sparse"] = {
+                "what": "the region step inside the timed job (front-sparse: settled tiles are not visited, quiet "
+                        "tiles read no image); bytes = the image values the steps needed (counted) + the binary "
+                        "state",
+                "bound": "hbm", "achieved": round(alg / (step_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "traffic_source": src, "mean_launch_us": round(step_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": int(alg),
-                "needed_pixel_fraction": round(counted[dom]["needed_px"] / max(counted[dom]["counted"], 1) / (h * w),
-                                               4)}
+                "needed_pixel_fraction": round(c["needed_px_per_step"] / (h * w), 4),
+                "visited_tile_fraction": c["summary"]["mean_visited_tile_fraction"]}
 
-    # roofline: the region step with the device to itself (the timed
-    # sequential pass), where the dispatch-packet events and a rocprofv3
-    # kernel trace agree.  roofline_concurrent: the same kernel in the timed
-    # two-stream job; there the events of a launch also count time spent
-    # waiting for CUs that the other stream's kernels hold, and read ~15 %
-    # above the trace's kernel durations.
-    conc_note = ("two concurrent solves: dispatch-packet events include waits for CUs held by the other "
-                 "stream and read ~15 % above rocprofv3 kernel durations")
-    if conc and prof_seq is not prof:
-        roofline = dict(roofline_of(prof_seq), **{"pass": "sequential"})
-        roofline_conc = dict(roofline_of(prof), **{"pass": "concurrent", "note": conc_note})
-    elif conc:
-        roofline = dict(roofline_of(prof), **{"pass": "concurrent", "note": conc_note})
-        roofline_conc = None
-    else:
-        roofline = dict(roofline_of(prof), **{"pass": "sequential"})
-        roofline_conc = None
-    per_term = {}
-    for t, pr_t in prof.items():
-        ms_t = pr_t["step_ms"] / max(pr_t["step_n"], 1)
-        d = {"step_kernel_us": round(ms_t * 1e3, 2),
-             "step_kernel_GBps": round(step_bytes(t) / (ms_t * 1e-3) / 1e9, 1),
-             "step_dense_equiv_GBps": round(pr_t["dense_bytes_per_px"] * h * w / (ms_t * 1e-3) / 1e9, 1)}
-        if pr_t["mpass_n"]:
-            mp = pr_t["mpass_ms"] / pr_t["mpass_n"]
-            d["mpass_kernel_us"] = round(mp * 1e3, 2)
-        per_term[t] = d
-
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel-iter/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{h}x{w}x{b} multiband scene ({args.workload}), "
-                               f"{'+'.join(terms)} terms, {iters} iterations each, "
-                               f"sigma {sigma}, {ksize}x{ksize} template, dt 15, image resident in HBM; "
-                               + (f"the {len(terms)} independent solves on concurrent HIP streams, "
-                                  f"the edge one on {edge_cus} of the {ncu} CUs" if conc
-                                  else f"the {len(terms)} solves one after the other on one HIP stream"),
-                   "global_batch": 1, "parallelism": "single GPU"},
-        "sequential": sequential,
-        "roofline": roofline, "roofline_concurrent": roofline_conc, "per_term": per_term,
-        "final_mask_inside_fraction": inside,
-        "gpu": torch.cuda.get_device_name(0),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, sigma, ksize, args.cpu_iters, terms)
-    sections = [x for x in args.sections.split(",") if x]
+    if not args.no_cpu_baseline and args.job == "all":
+        out["cpu_baseline"] = cpu_baseline(scene, sigma, ksize, args.cpu_iters or cpu_iters, terms)
+    sections = [x for x in args.sections.split(",") if x] if args.job == "all" else []
     if "batched" in sections:
         out["batched"] = section_batched(args)
     if "precision" in sections:
@@ -658,6 +628,105 @@ def main():
     if "serving" in sections:
         out["serving"] = section_serving(args)
     print(json.dumps(out), flush=True)
+
+
+def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_region, kname_edge):
+    """Roofline of a fully active step: the state is an 8 x 8 checkerboard
+    (loaded as the smoothed LSF of a binary function, Table I step 4), so
+    every step tile is heavy and every pixel takes the data term.  Each timed
+    step is the first after the load; its kernel time comes from the events
+    of its own dispatch.  Algorithmic bytes: the image (region: B x 4 B) or
+    edge map (4 B) read once, and the binary LSF state (1 bit read, 1 bit
+    written) per pixel."""
+    cb = torch.tensor(checkerboard(h, w), device=img.device)
+    res = {}
+    reps = max(args.steps, 3)
+    for t in terms:
+        nbytes = lse.lse_workspace_bytes(params[t])
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=img.device)
+        ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+        s = sids[t]
+        ctx = lse.lse_init(params[t], img.data_ptr(), cb.data_ptr(), ptr, nbytes, s)
+        for _ in range(max(args.warmup, 1)):
+            lse.lse_set_mask(ctx, cb.data_ptr(), True, 0, s)
+            lse.lse_step(ctx, s)
+        lse.lse_profile(ctx, lse.PROFILE_TIMING)
+        for _ in range(reps):
+            lse.lse_set_mask(ctx, cb.data_ptr(), True, 0, s)
+            lse.lse_step(ctx, s)
+        p = lse.lse_profile_read(ctx)
+        lse.lse_profile(ctx, lse.PROFILE_COUNT)
+        lse.lse_set_mask(ctx, cb.data_ptr(), True, 0, s)
+        lse.lse_step(ctx, s)
+        q = lse.lse_profile_read(ctx)
+        torch.cuda.synchronize()
+        lse.lse_destroy(ctx)
+        del ws
+        step_ms = p.step_ms / max(p.step_launches, 1)
+        per_px = 4.0 * nb if t == "region" else 4.0
+        alg = per_px * h * w + 2.0 * h * w / 8.0
+        ach = alg / (step_ms * 1e-3) / 1e9
+        kname = kname_region if t == "region" else kname_edge
+        traffic, src = measured_traffic(kname, "dense")
+        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": src,
+             "kernel": kname.replace("lse::", "") + f" ({t} term{', B=%d' % nb if t == 'region' else ''}, "
+                                                    f"TS {params[t].ksize})",
+             "mode": f"fully active step on {h}x{w}: 8x8 checkerboard state, every tile heavy",
+             "mean_launch_us": round(step_ms * 1e3, 2), "launches_timed": int(p.step_launches),
+             "algorithmic_bytes_per_px": per_px + 0.25, "algorithmic_bytes_per_launch": int(alg),
+             "bytes_note": ("image bands read once (B x 4 B) + binary LSF state, 1 bit read and 1 bit written; an "
+                            "FP32 LSF plane (the plain design) would add 8 B/px" if t == "region" else
+                            "edge map g read once (4 B) + binary LSF state (2 bits)"),
+             "needed_pixel_fraction": round(q.needed_pixels / max(q.counted_steps, 1) / (h * w), 4),
+             "visited_tile_fraction": round(q.visited_tiles / max(q.counted_steps * q.tiles, 1), 4),
+             "heavy_tile_fraction": round(q.heavy_tiles / max(q.counted_steps * q.tiles, 1), 4)}
+        if p.mpass_launches:
+            r["mpass_kernel_us"] = round(p.mpass_ms / p.mpass_launches * 1e3, 2)
+        res[t] = r
+    region = res.get("region") or res[terms[0]]
+    edge = res.get("edge") if "region" in res else None
+    return region, edge
+
+
+def count_replay(lse, torch, img, masks, params, terms, iters, ws_ptr, nbytes, sid):
+    """Untimed replay of the (deterministic) job, one iteration at a time with
+    LSE_PROFILE_COUNT: per iteration the flips (Table I step 5), the step
+    tiles visited and heavy, and the pixels whose image value the step
+    needed."""
+    h, w = int(params[terms[0]].height), int(params[terms[0]].width)
+    out = {}
+    for t in terms:
+        ctx = lse.lse_init(params[t], img.data_ptr(), masks[t].data_ptr(), ws_ptr[t], nbytes[t], sid)
+        lse.lse_profile(ctx, lse.PROFILE_COUNT)
+        flips, vis, heavy, need = [], [], [], []
+        prev = (0, 0, 0)
+        tiles = 1
+        for _ in range(iters):
+            lse.lse_step(ctx, sid)
+            st = lse.lse_stats(ctx, sid)
+            p = lse.lse_profile_read(ctx)
+            flips.append(int(st.flips))
+            tiles = max(int(p.tiles), 1)
+            cur = (int(p.needed_pixels), int(p.visited_tiles), int(p.heavy_tiles))
+            need.append(cur[0] - prev[0])
+            vis.append(cur[1] - prev[1])
+            heavy.append(cur[2] - prev[2])
+            prev = cur
+        torch.cuda.synchronize()
+        lse.lse_destroy(ctx)
+        changing = [i for i, f in enumerate(flips) if f > 0]
+        every = max(1, iters // 30)
+        summ = {"last_iteration_with_flips": changing[-1] if changing else -1,
+                "iterations": iters, "tiles": tiles, "sampled_every": every,
+                "flips": flips[::every],
+                "visited_tile_fraction": [round(v / tiles, 4) for v in vis[::every]],
+                "heavy_tile_fraction": [round(v / tiles, 4) for v in heavy[::every]],
+                "needed_pixel_fraction": [round(v / (h * w), 4) for v in need[::every]],
+                "mean_visited_tile_fraction": round(sum(vis) / (iters * tiles), 4),
+                "mean_needed_pixel_fraction": round(sum(need) / (iters * h * w), 4)}
+        out[t] = {"summary": summ, "needed_px_per_step": sum(need) / iters}
+    return out
 
 
 if __name__ == "__main__":

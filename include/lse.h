@@ -128,6 +128,12 @@ typedef struct {
     int64_t needed_pixels; /* LSE_PROFILE_COUNT: pixels whose image (region) or
                               edge-map (edge) value the counted steps read    */
     int64_t counted_steps;
+    int64_t visited_tiles; /* LSE_PROFILE_COUNT, binary-state path: step tiles
+                              the counted steps visited (the others were
+                              settled, Table I step 3 leaving them unchanged);
+                              -1 where the path has no tile schedule          */
+    int64_t heavy_tiles;   /* of those, tiles whose bit window was not uniform */
+    int64_t tiles;         /* step tiles of one iteration (-1 as above)       */
 } lse_profile_t;
 
 /* lse_profile flags.  LSE_PROFILE_SAMPLE(k), k = 0..15, or-ed with

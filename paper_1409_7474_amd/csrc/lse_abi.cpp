@@ -380,6 +380,8 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     if ((c->prof & LSE_PROFILE_COUNT) && !c->dense) {
         if (launch_count_needed(a, a.raw, region ? 0 : 1, c->host_args.tilesum != nullptr, s) != hipSuccess)
             return LSE_ERR_DEVICE;
+        if (c->host_args.sched_mask && fast_radius(c->r) && launch_count_tiles(c->dargs, c->n, s) != hipSuccess)
+            return LSE_ERR_DEVICE;
     }
     c->n += 1;
     c->raw_next = 0;
@@ -691,10 +693,14 @@ lse_status lse_profile_read(lse_ctx *c, lse_profile_t *host_out) {
         c->pool.push_back(e);
     }
     c->pending.clear();
-    unsigned long long acc[2] = {0, 0};
+    unsigned long long acc[4] = {0, 0, 0, 0};
     if (hipMemcpy(acc, &c->st->acc_needed, sizeof(acc), hipMemcpyDeviceToHost) != hipSuccess) return LSE_ERR_DEVICE;
     host_out->needed_pixels = (int64_t)acc[0];
     host_out->counted_steps = (int64_t)acc[1];
+    const bool tiled = c->host_args.sched_mask && fast_radius(c->r) && !c->dense;
+    host_out->visited_tiles = tiled ? (int64_t)acc[2] : -1;
+    host_out->heavy_tiles = tiled ? (int64_t)acc[3] : -1;
+    host_out->tiles = tiled ? (int64_t)c->host_args.tiles : -1;
     host_out->step_ms = c->prof_ms[0];
     host_out->mpass_ms = c->prof_ms[1];
     host_out->step_launches = c->prof_n[0];
@@ -1090,6 +1096,6 @@ void lse_batch_destroy(lse_batch *b) {
     delete b;
 }
 
-int32_t lse_version(void) { return 103; }
+int32_t lse_version(void) { return 104; }
 
 }  // extern "C"

@@ -84,6 +84,8 @@ struct DevState {
     int pad1[3];
     unsigned long long acc_needed;  // profiling: pixels whose image value the steps needed
     unsigned long long acc_steps;   // profiling: steps counted into acc_needed
+    unsigned long long acc_visited; // profiling: step tiles the counted steps visited (fast path)
+    unsigned long long acc_heavy;   // profiling: of those, tiles recorded as heavy (not quiet)
 };
 
 // Fixed-point region sums and count of one step tile: the all-inside case
@@ -251,5 +253,8 @@ hipError_t launch_lsf_out(const StepArgs &a, const uint32_t *const bits[2], int 
                           hipStream_t s);
 hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, int fast_quiet, hipStream_t s);
 hipError_t launch_reset_profile(DevState *st, hipStream_t s);
+// Profiling: after launch k of a single image on the fast path, add the tiles
+// that step visited and the tiles it recorded as heavy to the totals.
+hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, hipStream_t s);
 
 }  // namespace lse

@@ -305,6 +305,8 @@ __global__ void reset_profile_kernel(DevState *st) {
     if (threadIdx.x == 0) {
         st->acc_needed = 0;
         st->acc_steps = 0;
+        st->acc_visited = 0;
+        st->acc_heavy = 0;
     }
 }
 
@@ -429,6 +431,31 @@ hipError_t launch_batch_plan(const ImgArgs *args, const uint32_t *wbase, int nim
                              uint32_t *list, hipStream_t s) {
     if (nimg < 1 || nimg > kBatchPlanImages) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, args, wbase, nimg, unit_bits, k, list);
+    return hipGetLastError();
+}
+
+// Profiling: step n = n0 + k visited the tiles that iteration n - 1 recorded
+// as heavy (record n % 3) and their neighbours, and recorded its own heavy
+// tiles in record (n + 1) % 3; both records are intact until step n + 1.
+__global__ __launch_bounds__(kPlanThreads) void count_tiles_kernel(const ImgArgs *__restrict__ args, int k) {
+    const ImgArgs &E = args[0];
+    const int n = E.n0 + k;
+    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
+    const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
+    const uint32_t *next = E.sched_mask + (size_t)((n + 1) % 3) * nw;
+    unsigned long long vis = 0, heavy = 0;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+        const int valid = min(32, ntiles - 32 * w);
+        const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
+        vis += __popc(active_word(hr, nw, ntx, w) & vm);
+        heavy += __popc(next[w] & vm);
+    }
+    if (vis) atomicAdd(&E.st->acc_visited, vis);
+    if (heavy) atomicAdd(&E.st->acc_heavy, heavy);
+}
+
+hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, hipStream_t s) {
+    hipLaunchKernelGGL(count_tiles_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_args, k);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ class lse_profile_t(ctypes.Structure):
         ("step_ms", ctypes.c_double), ("mpass_ms", ctypes.c_double),
         ("step_launches", ctypes.c_int64), ("mpass_launches", ctypes.c_int64),
         ("needed_pixels", ctypes.c_int64), ("counted_steps", ctypes.c_int64),
+        ("visited_tiles", ctypes.c_int64), ("heavy_tiles", ctypes.c_int64), ("tiles", ctypes.c_int64),
     ]
 
 
@@ -427,7 +428,8 @@ class LSE:
         p = lse_profile_read(self.ctx)
         return {"step_ms": p.step_ms, "mpass_ms": p.mpass_ms, "step_launches": int(p.step_launches),
                 "mpass_launches": int(p.mpass_launches), "needed_pixels": int(p.needed_pixels),
-                "counted_steps": int(p.counted_steps)}
+                "counted_steps": int(p.counted_steps), "visited_tiles": int(p.visited_tiles),
+                "heavy_tiles": int(p.heavy_tiles), "tiles": int(p.tiles)}
 
     def step_bytes_per_pixel(self) -> float:
         return lse_step_bytes_per_pixel(self.ctx)

@@ -31,12 +31,12 @@ def test_more_than_one_gpu_exits_with_a_message(args, env):
 def test_default_arguments(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
-    assert (a.gpus, a.workload, a.job) == (1, "large", "both")
+    assert (a.gpus, a.workload, a.job) == (1, "precision", "all")
     assert a.steps >= 1 and a.warmup >= 0
     assert set(a.sections.split(",")) == {"batched", "precision", "serving"}
 
 
-@pytest.mark.parametrize("job", ["both", "concurrent", "sequential"])
+@pytest.mark.parametrize("job", ["all", "concurrent", "sequential", "dense"])
 def test_job_choices(monkeypatch, job):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--job", job])
     assert bench.parse().job == job
@@ -51,7 +51,25 @@ def test_unknown_job_rejected(monkeypatch):
 def test_profile_summary_matches_kernel_sources():
     # The summary records the hash of csrc/*.hip, *.h it was measured on;
     # the benchmark reports measured traffic only while the two agree.
-    name = "lse::step_fast_kernel<5, 4, false, float>"
-    traffic, source = bench.measured_traffic(name)
+    name = "lse::step_fast_kernel<6, 4, false, float>"
+    traffic, source = bench.measured_traffic(name, "dense")
     assert traffic is not None, "profiles/ summary is stale for the current kernel sources"
     assert traffic > 0 and source.startswith("profiles/")
+
+
+def test_checkerboard_state_is_fully_active():
+    cb = bench.checkerboard(40, 50)
+    assert cb.shape == (40, 50) and cb.dtype.name == "uint8"
+    assert cb[0, 0] == 0 and cb[0, 8] == 1 and cb[8, 0] == 1 and cb[8, 8] == 0
+    # every 8-row, 16-column window holds both values
+    for y in range(0, 33, 4):
+        for x in range(0, 35, 5):
+            assert 0 < cb[y:y + 8, x:x + 16].sum() < 128
+
+
+def test_profile_commands_are_single_counter_block_runs():
+    # rocprofv3 does not split counters over passes: at most 8 SQ counters per run.
+    for cmd in bench.PROFILE_COMMANDS:
+        if "--pmc" in cmd:
+            counters = cmd.split("--pmc")[1].split("--")[0].split()
+            assert len([c for c in counters if c.startswith("SQ_")]) <= 8, cmd

@@ -269,6 +269,69 @@ def test_profile_counts_needed_pixels(dev):
             assert quiet_px > 0  # the case is exercised
 
 
+def _heavy_tiles(bits_prev, r, edge):
+    """Tile grid of the fast step kernel (96 x 48 region, 96 x 64 edge tiles)
+    with True where the tile is heavy (not quiet) given the binary state it
+    reads: quiet needs the tile and its whole halo inside the image and every
+    staged bit it reads uniform (rows y0 - RU - 1 - r .. + FY + 2 RU + 2 + 2r,
+    columns x0 - 1 - RU - r .. x0 + 96 + RU + r; RU = r for the region term,
+    0 for the edge term)."""
+    h, w = bits_prev.shape
+    fy, ru = (64, 0) if edge else (48, r)
+    nty, ntx = -(-h // fy), -(-w // 96)
+    heavy = np.ones((nty, ntx), bool)
+    for ty in range(nty):
+        for tx in range(ntx):
+            y0, x0 = ty * fy, tx * 96
+            by0, nr = y0 - ru - 1 - r, fy + 2 * ru + 2 + 2 * r
+            if x0 - 2 * r - 2 < 0 or x0 + 96 + 2 * r + 2 > w or by0 < 0 or by0 + nr > h:
+                continue
+            win = bits_prev[by0:by0 + nr, x0 - 1 - ru - r:x0 + 97 + ru + r]
+            heavy[ty, tx] = not (win.all() or not win.any())
+    return heavy
+
+
+def _dilate_tiles(t):
+    out = t.copy()
+    nty, ntx = t.shape
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            src = t[max(0, -dy):nty - max(0, dy), max(0, -dx):ntx - max(0, dx)]
+            out[max(0, dy):nty - max(0, -dy), max(0, dx):ntx - max(0, -dx)] |= src
+    return out
+
+
+@pytest.mark.parametrize("term", ["region", "edge"])
+def test_profile_counts_visited_and_heavy_tiles(dev, term):
+    """Profiling counts of the front-sparse schedule: the tiles a step visits
+    are the heavy tiles of the previous iteration and their neighbours (all
+    tiles right after a restart), and its heavy tiles are those whose bit
+    window is not uniform; both recomputed here from the exported masks."""
+    from paper_1409_7474_amd import lse
+    sc = synth.scene_multiband(4, size=1400, bands=4, n_roofs=12, n_roads=1, height=1100, width=1400)
+    img, _ = _as_gpu(sc.image, dev)
+    r = 6
+    job = _make(dev, img, sc.init_region if term == "region" else sc.init_edge, term=term, sigma=2.0, ksize=2 * r + 1)
+    job.profile(lse.PROFILE_COUNT)
+    job.step()
+    p = job.profile_read()
+    assert p["tiles"] == p["visited_tiles"] > 0 and p["counted_steps"] == 1
+    masks = [job.mask().cpu().numpy().astype(bool)]
+    job.step()
+    masks.append(job.mask().cpu().numpy().astype(bool))
+    job.profile(lse.PROFILE_COUNT)
+    want_vis = want_heavy = 0
+    for _ in range(4):
+        want_vis += int(_dilate_tiles(_heavy_tiles(masks[-2], r, term == "edge")).sum())
+        want_heavy += int(_heavy_tiles(masks[-1], r, term == "edge").sum())
+        job.step()
+        masks.append(job.mask().cpu().numpy().astype(bool))
+    p = job.profile_read()
+    assert (p["visited_tiles"], p["heavy_tiles"]) == (want_vis, want_heavy), (p, want_vis, want_heavy)
+    assert want_heavy < want_vis < 4 * p["tiles"]  # the schedule skips settled tiles here
+    job.close()
+
+
 def test_profile_timing_samples(dev):
     """LSE_PROFILE_SAMPLE(k): one launch in 2^k of each kernel carries timing
     events (launches 2^k - 1, 2 * 2^k - 1, ...); every launch with k = 0."""

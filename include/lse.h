@@ -285,6 +285,18 @@ size_t lse_batch_bytes(lse_ctx *const *cs, int32_t n);
 lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
                             size_t table_bytes, void *stream, lse_batch **out);
 
+/* Re-plan an existing batch for a new set of n distinct contexts (members
+ * joining or leaving, as in continuous batching), keeping its family streams
+ * and events: nothing is synchronised.  LSE_ERR_STATE for a batch that has
+ * run with LSE_BATCH_GRAPH (its captured sequence names the old table; create
+ * a new batch instead).  The new
+ * table (table_dev, lse_batch_bytes(cs, n) bytes) is written on `stream`;
+ * the previous table must stay alive and untouched until the last run
+ * enqueued on it has completed (the caller tracks that, e.g. with an event).
+ * targets as for lse_batch_create.  On an error the batch is unchanged. */
+lse_status lse_batch_update(lse_batch *b, lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
+                            size_t table_bytes, void *stream);
+
 /* Up to `iters` iterations of every context of the batch (each stops at its
  * target, and with stop_when_unchanged at its Step-5 fixed point), enqueued
  * on `stream` without synchronising.  With more than one kernel family, each

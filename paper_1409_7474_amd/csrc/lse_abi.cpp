@@ -82,7 +82,26 @@ struct lse_batch {
     std::vector<hipStream_t> gstream;
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
+    // Table uploads go through two pinned host buffers used in turn, so a
+    // copy is truly stream-ordered (a pageable source would make the copy
+    // wait for the stream): before a buffer is refilled, the copy that last
+    // read it (two uploads ago) must have completed.
+    struct Staging {
+        void *host = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    Staging stage[2];
+    int next_stage = 0;
     ~lse_batch() {
+        for (Staging &g : stage) {
+            if (g.done) {
+                if (g.pending) (void)hipEventSynchronize(g.done);
+                (void)hipEventDestroy(g.done);
+            }
+            if (g.host) (void)hipHostFree(g.host);
+        }
         for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
         for (hipEvent_t ev : join) (void)hipEventDestroy(ev);
         if (fork) (void)hipEventDestroy(fork);
@@ -908,37 +927,29 @@ size_t lse_batch_bytes(lse_ctx *const *cs, int32_t n) {
     return plan_batch(cs, n, &b);
 }
 
-lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
-                            size_t table_bytes, void *stream, lse_batch **out) {
-    if (!out) return LSE_ERR_INVALID_ARG;
-    *out = nullptr;
+namespace {
+
+// Check the arguments of a batch plan for cs / targets and plan it into *b;
+// LSE_OK or the reason it cannot be planned.
+lse_status plan_checked(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev, size_t table_bytes,
+                        lse_batch *b) {
     if (!cs || n <= 0) return LSE_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i)
         if (!cs[i]) return LSE_ERR_INVALID_ARG;
     if (targets)
         for (int i = 0; i < n; ++i)
             if (targets[i] < 0) return LSE_ERR_INVALID_ARG;
-    lse_batch *b = new (std::nothrow) lse_batch();
-    if (!b) return LSE_ERR_INVALID_ARG;
     const size_t need = plan_batch(cs, n, b);
     if (need == 0) {
         // Repeated or null contexts are invalid; a radius without a compiled
         // step variant is valid but not batched by this build.
         std::set<const lse_ctx *> seen;
-        lse_status v = LSE_ERR_UNSUPPORTED;
         for (int i = 0; i < n; ++i)
-            if (!seen.insert(cs[i]).second) v = LSE_ERR_INVALID_ARG;
-        delete b;
-        return v;
+            if (!seen.insert(cs[i]).second) return LSE_ERR_INVALID_ARG;
+        return LSE_ERR_UNSUPPORTED;
     }
-    if (!table_dev || (reinterpret_cast<uintptr_t>(table_dev) % kAlign)) {
-        delete b;
-        return LSE_ERR_WORKSPACE;
-    }
-    if (table_bytes < need) {
-        delete b;
-        return LSE_ERR_WORKSPACE;
-    }
+    if (!table_dev || (reinterpret_cast<uintptr_t>(table_dev) % kAlign)) return LSE_ERR_WORKSPACE;
+    if (table_bytes < need) return LSE_ERR_WORKSPACE;
     b->dargs = static_cast<ImgArgs *>(table_dev);
     b->dmap = reinterpret_cast<uint32_t *>(static_cast<char *>(table_dev) + align_up(b->cs.size() * sizeof(ImgArgs)));
     b->hargs.resize(b->cs.size());
@@ -955,40 +966,110 @@ lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *target
         b->hargs[i].n0 = 0;
         b->target[i] = t;
     }
+    return LSE_OK;
+}
+
+// Streams and events for the batch's kernel families (more than one family:
+// each on a stream of its own, default priority); kept across updates.
+hipError_t ensure_streams(lse_batch *b) {
+    if (b->groups.size() <= 1) return hipSuccess;
+    if (!b->fork && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return hipErrorUnknown;
+    while (b->gstream.size() < b->groups.size()) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return hipErrorUnknown;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            return hipErrorUnknown;
+        }
+        b->gstream.push_back(st);
+        b->join.push_back(ev);
+    }
+    return hipSuccess;
+}
+
+// Copy the planned table (argument records, then maps) to the device on s
+// through the next pinned staging buffer.  Only the parts the device reads
+// before writing are copied: a visit list is rebuilt by every launch.
+hipError_t upload_table(lse_batch *b, hipStream_t s) {
+    const size_t a_bytes = b->hargs.size() * sizeof(ImgArgs);
+    const size_t m_bytes = b->hmap.size() * sizeof(uint32_t);
+    const size_t total = a_bytes + m_bytes;
+    lse_batch::Staging &g = b->stage[b->next_stage];
+    b->next_stage ^= 1;
+    if (g.pending) {
+        if (hipEventSynchronize(g.done) != hipSuccess) return hipErrorUnknown;
+        g.pending = false;
+    }
+    if (!g.done && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return hipErrorUnknown;
+    if (g.cap < total) {
+        if (g.host) (void)hipHostFree(g.host);
+        g.host = nullptr;
+        g.cap = 0;
+        const size_t cap = std::max<size_t>(total + total / 2, 4096);
+        if (hipHostMalloc(&g.host, cap, hipHostMallocDefault) != hipSuccess) {
+            g.host = nullptr;
+            return hipErrorUnknown;
+        }
+        g.cap = cap;
+    }
+    char *h = static_cast<char *>(g.host);
+    memcpy(h, b->hargs.data(), a_bytes);
+    memcpy(h + a_bytes, b->hmap.data(), m_bytes);
+    hipError_t e = hipMemcpyAsync(b->dargs, h, a_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->dmap, h + a_bytes, m_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(g.done, s);
+    g.pending = e == hipSuccess;
+    return e;
+}
+
+}  // namespace
+
+lse_status lse_batch_create(lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
+                            size_t table_bytes, void *stream, lse_batch **out) {
+    if (!out) return LSE_ERR_INVALID_ARG;
+    *out = nullptr;
+    lse_batch *b = new (std::nothrow) lse_batch();
+    if (!b) return LSE_ERR_INVALID_ARG;
+    const lse_status v = plan_checked(cs, n, targets, table_dev, table_bytes, b);
+    if (v != LSE_OK) {
+        delete b;
+        return v;
+    }
     b->exec = nullptr;
     b->exec_iters = -1;
     b->exec_stop = -1;
-    if (b->groups.size() > 1) {
-        if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
-            delete b;
-            return LSE_ERR_DEVICE;
-        }
-        for (size_t g = 0; g < b->groups.size(); ++g) {
-            hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-                delete b;
-                return LSE_ERR_DEVICE;
-            }
-            b->gstream.push_back(st);
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                delete b;
-                return LSE_ERR_DEVICE;
-            }
-            b->join.push_back(ev);
-        }
-    }
     const hipStream_t s = as_stream(stream);
     b->last_stream = s;
-    hipError_t e = hipMemcpyAsync(b->dargs, b->hargs.data(), b->hargs.size() * sizeof(ImgArgs),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->dmap, b->hmap.data(), b->hmap.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) {
+    if (ensure_streams(b) != hipSuccess || upload_table(b, s) != hipSuccess) {
         delete b;
         return LSE_ERR_DEVICE;
     }
     *out = b;
+    return LSE_OK;
+}
+
+lse_status lse_batch_update(lse_batch *b, lse_ctx *const *cs, int32_t n, const int32_t *targets, void *table_dev,
+                            size_t table_bytes, void *stream) {
+    if (!b) return LSE_ERR_INVALID_ARG;
+    // A batch replayed from a graph is not re-planned: its captured launch
+    // sequence names the old table, and capturing again after a re-plan has
+    // failed on the host (a segmentation fault inside the capture, cause not
+    // found), so that path is not taken.
+    if (b->exec) return LSE_ERR_STATE;
+    lse_batch next;
+    const lse_status v = plan_checked(cs, n, targets, table_dev, table_bytes, &next);
+    if (v != LSE_OK) return v;
+    const hipStream_t s = as_stream(stream);
+    b->cs.swap(next.cs);
+    b->target.swap(next.target);
+    b->groups.swap(next.groups);
+    b->hargs.swap(next.hargs);
+    b->hmap.swap(next.hmap);
+    b->dargs = next.dargs;
+    b->dmap = next.dmap;
+    b->last_stream = s;
+    if (ensure_streams(b) != hipSuccess || upload_table(b, s) != hipSuccess) return LSE_ERR_DEVICE;
     return LSE_OK;
 }
 
@@ -999,10 +1080,11 @@ hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
     // Several groups: fork their streams from `s` after the prepare kernel
     // and join them back at the end (inside a graph capture, these event
     // records and waits make the group streams part of the captured graph).
-    const bool multi = !b->gstream.empty();
+    const size_t ng = b->groups.size();
+    const bool multi = ng > 1;
     if (multi) {
         if (e == hipSuccess) e = hipEventRecord(b->fork, s);
-        for (size_t gi = 0; gi < b->gstream.size() && e == hipSuccess; ++gi)
+        for (size_t gi = 0; gi < ng && e == hipSuccess; ++gi)
             e = hipStreamWaitEvent(b->gstream[gi], b->fork, 0);
     }
     for (int k = 0; k < iters && e == hipSuccess; ++k) {
@@ -1026,7 +1108,7 @@ hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
         }
     }
     if (multi) {
-        for (size_t gi = 0; gi < b->gstream.size(); ++gi) {
+        for (size_t gi = 0; gi < ng; ++gi) {
             // Join even after an error, so that no group stream is left
             // forked (or a capture left open on it).
             const hipError_t r = hipEventRecord(b->join[gi], b->gstream[gi]);
@@ -1096,6 +1178,6 @@ void lse_batch_destroy(lse_batch *b) {
     delete b;
 }
 
-int32_t lse_version(void) { return 104; }
+int32_t lse_version(void) { return 105; }
 
 }  // extern "C"

@@ -880,23 +880,27 @@ __device__ __forceinline__ int tile_of(int ntiles) {
     return (t < hi && (j >> 3) < per) ? t : -1;
 }
 
-// Word w of a record (buffer resource over its words), or zero outside it:
-// single-word buffer loads return zero outside their range.  The offset
-// passes through an empty asm statement so that the compiler cannot merge
-// loads of neighbouring words into one multi-word load, which would return
-// zeros for all of its words when one of them lies outside.
-__device__ __forceinline__ uint32_t record_word(__amdgpu_buffer_rsrc_t rec, int w) {
-    uint32_t off = (uint32_t)w * 4u;
-    asm volatile("" : "+v"(off));
-    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rec, off, 0, 0);
+// A record of heavy tiles: nw words, bit t % 32 of word t / 32 for tile t.
+struct Record {
+    const uint32_t *w;
+    int nw;
+};
+
+// Word w of a record, or zero outside it.  The load address is clamped into
+// the record, so every load stays in range whatever the compiler does with
+// neighbouring loads (it may merge them), and the value is masked after.
+__device__ __forceinline__ uint32_t record_word(Record rec, int w) {
+    const int wc = min(max(w, 0), rec.nw - 1);
+    const uint32_t v = rec.w[wc];
+    return w == wc ? v : 0u;
 }
 
-// Active tiles of word w of the heavy-tile record (nw words): a tile is
+// Active tiles of word w of the heavy-tile record: a tile is
 // active when it or one of its eight neighbours (in a grid of ntx tiles per
 // row) was heavy.  The record bits at tile offsets dy * ntx + dx around the
 // word are read as funnel shifts of word pairs; all eighteen loads are
 // issued straight away (no branches), then combined.
-__device__ __forceinline__ uint32_t active_word(__amdgpu_buffer_rsrc_t heavy, int nw, int ntx, int w) {
+__device__ __forceinline__ uint32_t active_word(Record heavy, int ntx, int w) {
     const int base = 32 * w;
     uint32_t lo[9], hi[9];
 #pragma unroll
@@ -935,7 +939,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
     const int nw = (ntiles + 31) >> 5;
     const int w0 = lane * kPer;
     uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
-    const __amdgpu_buffer_rsrc_t hr = image_rsrc(heavy, (uint32_t)nw * 4u);
+    const Record hr{heavy, nw};
     int nh = 0, na = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
@@ -943,7 +947,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
         const int valid = max(0, min(32, ntiles - 32 * w));  // 0 past the record
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         hw[i] = record_word(hr, w) & vm;
-        aw[i] = active_word(hr, nw, ntx, w) & vm & ~hw[i];
+        aw[i] = active_word(hr, ntx, w) & vm & ~hw[i];
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
     }
@@ -993,7 +997,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
 template <int NT>
 __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
-    const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
+    const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (nw + NT - 1) / NT;
     const int w0 = tid * per;
@@ -1001,7 +1005,7 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         h = record_word(hr, w) & vm;
-        a = active_word(hr, nw, ntx, w) & vm & ~h;
+        a = active_word(hr, ntx, w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {

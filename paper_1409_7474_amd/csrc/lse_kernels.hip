@@ -374,9 +374,9 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const ImgArgs 
         const int nw = (E.tiles + 31) >> 5, w = g - (int)s_wb[img];
         const int valid = min(32, E.tiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
+        const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
         h = record_word(hr, w) & vm;
-        a = active_word(hr, nw, (E.W + kFX - 1) / kFX, w) & vm & ~h;
+        a = active_word(hr, (E.W + kFX - 1) / kFX, w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {
@@ -441,13 +441,13 @@ __global__ __launch_bounds__(kPlanThreads) void count_tiles_kernel(const ImgArgs
     const ImgArgs &E = args[0];
     const int n = E.n0 + k;
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
-    const __amdgpu_buffer_rsrc_t hr = image_rsrc(E.sched_mask + (size_t)(n % 3) * nw, (uint32_t)nw * 4u);
+    const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
     const uint32_t *next = E.sched_mask + (size_t)((n + 1) % 3) * nw;
     unsigned long long vis = 0, heavy = 0;
     for (int w = threadIdx.x; w < nw; w += blockDim.x) {
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        vis += __popc(active_word(hr, nw, ntx, w) & vm);
+        vis += __popc(active_word(hr, ntx, w) & vm);
         heavy += __popc(next[w] & vm);
     }
     if (vis) atomicAdd(&E.st->acc_visited, vis);

@@ -620,6 +620,7 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
     }
     totals_commit(!EDGE, tregs, &tot);
     __syncthreads();
+    // Tile 0 leads: every iteration visits it (it is always recorded heavy).
     const bool lead_block = t == 0;
     const bool lead = lead_block && threadIdx.x == 0;
     {
@@ -700,8 +701,12 @@ __global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *_
         // nothing.  The all-inside sums were computed at init by this
         // kernel's own reduction (tile_sums_kernel), so the totals are those
         // of the full computation bit for bit.
+        // Tile 0 is never quiet (it is also a border tile): it carries the
+        // bookkeeping of the iteration (totals carry-over, slot and record
+        // clearing, iteration count), so it must be recorded heavy every
+        // iteration, which makes the next iteration visit it.
         int quiet = -1;
-        if (!border && by0 >= 0 && by0 + G::PH + 2 * R <= H) {
+        if (!border && t != 0 && by0 >= 0 && by0 + G::PH + 2 * R <= H) {
             int all1 = 1, all0 = 1;
             for (int i = tid; i < (G::PH + 2 * R) * 2; i += kThreads) {
                 all1 &= s_codes[i] == 1;

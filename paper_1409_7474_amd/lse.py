@@ -32,7 +32,8 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTS = (
     "lse_params_default", "lse_workspace_bytes", "lse_init", "lse_step", "lse_run", "lse_mask",
     "lse_lsf", "lse_set_mask", "lse_set_lsf", "lse_edge_map", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
-    "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_run",
+    "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_update",
+    "lse_batch_run",
     "lse_batch_destroy", "lse_solve_static", "lse_status_str", "lse_version",
 )
 
@@ -133,6 +134,8 @@ def load() -> ctypes.CDLL:
     lib.lse_batch_bytes.restype = ctypes.c_size_t
     lib.lse_batch_create.argtypes = [P(vp), i32, P(i32), vp, ctypes.c_size_t, vp, P(vp)]
     lib.lse_batch_create.restype = st
+    lib.lse_batch_update.argtypes = [vp, P(vp), i32, P(i32), vp, ctypes.c_size_t, vp]
+    lib.lse_batch_update.restype = st
     lib.lse_batch_run.argtypes = [vp, i32, i32, i32, vp]
     lib.lse_batch_run.restype = st
     lib.lse_batch_destroy.argtypes = [vp]
@@ -257,6 +260,14 @@ def lse_batch_create(ctxs, targets, table_ptr: int, table_bytes: int, stream: in
     _check(load().lse_batch_create(_ctx_array(ctxs), len(ctxs), tg, table_ptr, table_bytes, stream,
                                    ctypes.byref(b)), "lse_batch_create")
     return b
+
+
+def lse_batch_update(batch, ctxs, targets, table_ptr: int, table_bytes: int, stream: int = 0) -> None:
+    tg = None
+    if targets is not None:
+        tg = (ctypes.c_int32 * len(ctxs))(*[int(t) for t in targets])
+    _check(load().lse_batch_update(batch, _ctx_array(ctxs), len(ctxs), tg, table_ptr, table_bytes, stream),
+           "lse_batch_update")
 
 
 def lse_batch_run(batch, iters: int, stop_when_unchanged: bool = False, flags: int = 0, stream: int = 0) -> None:
@@ -458,12 +469,33 @@ class Batch:
         self.device = self.jobs[0].device
         self.stream = stream if stream is not None else self.jobs[0].stream
         ctxs = [j.ctx for j in self.jobs]
-        nbytes = lse_batch_bytes(ctxs)
+        self.table, ptr, nbytes = self._table(ctxs)
         if nbytes == 0:
             self.batch = lse_batch_create(ctxs, targets, 0, 0, self._s())  # raises with the reason
-        self.table = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.table.data_ptr()
-        self.batch = lse_batch_create(ctxs, targets, base + (-base) % 256, nbytes, self._s())
+        self.batch = lse_batch_create(ctxs, targets, ptr, nbytes, self._s())
+
+    def _table(self, ctxs):
+        nbytes = lse_batch_bytes(ctxs)
+        table = _torch().empty(max(nbytes, 1) + 256, dtype=_torch().uint8, device=self.device)
+        base = table.data_ptr()
+        return table, base + (-base) % 256, nbytes
+
+    @property
+    def table_bytes(self) -> int:
+        return int(self.table.numel())
+
+    def update(self, jobs, targets=None):
+        """Re-plan for a new member list (lse_batch_update) on a new table;
+        returns the previous table tensor, which the caller keeps alive until
+        the runs enqueued on it have completed."""
+        jobs = list(jobs)
+        ctxs = [j.ctx for j in jobs]
+        table, ptr, nbytes = self._table(ctxs)
+        if nbytes == 0:
+            lse_batch_update(self.batch, ctxs, targets, 0, 0, self._s())  # raises with the reason
+        lse_batch_update(self.batch, ctxs, targets, ptr, nbytes, self._s())
+        old, self.table, self.jobs = self.table, table, jobs
+        return old
 
     def _s(self) -> int:
         return int(self.stream.cuda_stream)

@@ -7,10 +7,13 @@ from the start of the run).  A job is admitted, first come first served, when
 it has arrived and its workspace (lse_workspace_bytes) fits in the remaining
 budget and a slot is free; admitted jobs keep their binary state and
 statistics resident until they finish.  The running jobs form one batch
-(lse_batch_create); the batch advances in chunks of iterations, each chunk
-ending at the next job completion or after `chunk` iterations, and jobs that
-arrived meanwhile join at chunk boundaries, so new work overlaps running work
-on the device.  Each job's result equals its solo run bit for bit (the batch
+(lse_batch_create, then lse_batch_update whenever jobs join or leave: the
+batch keeps its streams and nothing synchronises); the batch advances in
+chunks of iterations, each chunk ending at the next job completion or after
+`chunk` iterations, and jobs that arrived meanwhile join at chunk
+boundaries, so new work overlaps running work on the device.  At most two
+chunks are in flight; memory is released when the chunk that last used it
+has completed.  Each job's result equals its solo run bit for bit (the batch
 keeps per-image state and exact fixed-point statistics).
 
 serve_plain runs the same trace one job at a time with plain FP32 solves
@@ -47,7 +50,8 @@ class ServeStats:
     pixel_iters: int
     max_running: int = 0
     max_queue: int = 0
-    batches_built: int = 0
+    batches_created: int = 0
+    batch_updates: int = 0
     chunks: int = 0
     extra: dict = field(default_factory=dict)
 
@@ -63,11 +67,25 @@ class ServeStats:
                 "latency_max_ms": round(float(lat.max()) * 1e3, 2),
                 "queue_wait_p50_ms": round(float(np.percentile(wait, 50)) * 1e3, 2),
                 "max_running": self.max_running, "max_queue": self.max_queue,
-                "batches_built": self.batches_built, "chunks": self.chunks, **self.extra}
+                "batches_created": self.batches_created, "batch_updates": self.batch_updates,
+                "chunks": self.chunks, **self.extra}
 
 
 def _params(job, storage, sigma, ksize):
     return lse.make_params(job.side, job.side, job.bands, term=job.term, sigma=sigma, ksize=ksize, storage=storage)
+
+
+def _table_bound(workspace_bytes: int) -> int:
+    """Upper bound of the bytes one job adds to a batch table: its argument
+    record (160 B), 4 B per step tile and per normaliser group, and map
+    alignment.  A step tile covers at least 4608 pixels, whose workspace
+    holds at least 2.25 B per pixel, so 4 B per tile is below 1/2048 of the
+    workspace; 1/256 plus 1 KiB leaves a wide margin."""
+    return workspace_bytes // 256 + 1024
+
+
+def _tensor_bytes(*ts) -> int:
+    return sum(int(t.numel()) * t.element_size() for t in ts if t is not None)
 
 
 def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: float = 1.5, ksize: int = 11,
@@ -75,7 +93,13 @@ def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: 
     """Continuous-batching server over `trace` (objects with job_id,
     arrival_s, side, bands, term, iters).  make_input(job) returns the job's
     image (H x W x B float tensor on the device) and initial mask (H x W
-    uint8).  Returns ServeStats."""
+    uint8).  Returns ServeStats.
+
+    Device memory held by the server never exceeds budget_bytes: the
+    workspaces of admitted jobs, their input tensors until lse_init has run,
+    and the batch tables (the current one and those still read by chunks in
+    flight) are all counted, and each is released only when the chunk that
+    last used it has completed (its event has been waited for)."""
     import torch
     dev = torch.device("cuda:0")
     stream = stream if stream is not None else torch.cuda.Stream(dev)
@@ -83,10 +107,13 @@ def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: 
     pending = collections.deque(sorted(trace, key=lambda j: j.arrival_s))
     queue = collections.deque()
     running = []            # [job, LSE, record, done_iters, workspace bytes]
-    inflight = collections.deque()   # (event, [finished running entries])
+    inflight = collections.deque()   # [event, finished entries, held tensors, bytes released at retire]
     records = []
-    used = 0
+    used = 0                # workspaces, held inputs and live tables
+    peak = 0
     batch, members = None, None
+    table_bytes = 0         # the current table
+    next_hold, next_bytes = [], 0    # held until the next chunk completes (inputs of new jobs)
     st = ServeStats(records=records, makespan_s=0.0, pixel_iters=0)
     ws_need = {}
     with torch.cuda.stream(stream):
@@ -96,30 +123,62 @@ def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: 
             while pending and pending[0].arrival_s <= now:
                 queue.append(pending.popleft())
             st.max_queue = max(st.max_queue, len(queue))
-            # Admission: first come first served, by workspace budget and slots.
+            # Admission: first come first served, by budget and slots.  Room
+            # is left for the new table (the old one stays until its last
+            # chunk completes).
+            grow = 0
             while queue and len(running) < max_slots:
                 job = queue[0]
                 need = ws_need.get(job.job_id)
                 if need is None:
                     need = ws_need[job.job_id] = lse.lse_workspace_bytes(_params(job, storage, sigma, ksize))
-                    if need == 0 or need > budget_bytes:
-                        raise ValueError(f"job {job.job_id} cannot be served within the budget")
-                if used + need > budget_bytes:
+                    if need == 0:
+                        raise ValueError(f"job {job.job_id}: invalid parameters")
+                in_bytes = job.side * job.side * (4 * job.bands + 1)
+                g = _table_bound(need)
+                if need + in_bytes + 2 * g > budget_bytes:
+                    raise ValueError(f"job {job.job_id} cannot be served within the budget")
+                if used + need + in_bytes + table_bytes + grow + g > budget_bytes:
                     break
                 queue.popleft()
                 img, init = make_input(job)
                 ctx = lse.LSE(img, init, term=job.term, sigma=sigma, ksize=ksize, storage=storage, stream=stream)
+                ctx._keep = None  # the next chunk's retirement releases the inputs
+                next_hold += [img, init]
+                b_in = _tensor_bytes(img, init)
+                next_bytes += b_in
                 rec = JobRecord(job.job_id, job.arrival_s, job.side * job.side, job.iters, admitted_s=clock() - t0)
                 records.append(rec)
                 running.append([job, ctx, rec, 0, need])
-                used += need
+                used += need + b_in
+                grow += g
             st.max_running = max(st.max_running, len(running))
             if running:
                 ids = [e[0].job_id for e in running]
                 if ids != members:
-                    batch = lse.Batch([e[1] for e in running], targets=[e[0].iters for e in running], stream=stream)
+                    jobs, targets = [e[1] for e in running], [e[0].iters for e in running]
+                    if batch is None:
+                        batch = lse.Batch(jobs, targets=targets, stream=stream)
+                        st.batches_created += 1
+                        old = None
+                    else:
+                        old = batch.update(jobs, targets=targets)
+                        st.batch_updates += 1
+                    new_bytes = batch.table_bytes
+                    if new_bytes > table_bytes + grow + 256:
+                        raise AssertionError("batch table larger than its reserve")
+                    used += new_bytes
+                    if old is not None:
+                        # Read by the chunks already enqueued: released with the last of them.
+                        if inflight:
+                            inflight[-1][2].append(old)
+                            inflight[-1][3] += table_bytes
+                        else:
+                            used -= table_bytes
+                        del old
+                    table_bytes = new_bytes
                     members = ids
-                    st.batches_built += 1
+                peak = max(peak, used)
                 c = min(chunk, min(e[0].iters - e[3] for e in running))
                 batch.run(c)
                 st.chunks += 1
@@ -132,20 +191,27 @@ def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: 
                     if keep_masks:
                         e[2].mask = e[1].mask()
                     running.remove(e)
-                    used -= e[4]          # stream-ordered: later work may reuse the memory
                     st.pixel_iters += e[2].pixels * e[2].iters
+                if finished:
+                    # The batch object no longer references finished jobs;
+                    # this chunk's entry keeps them until it completes.
+                    batch.jobs = [e[1] for e in running]
                 ev = torch.cuda.Event()
                 ev.record(stream)
-                inflight.append((ev, finished))
+                inflight.append([ev, finished, next_hold, next_bytes + sum(e[4] for e in finished)])
+                next_hold, next_bytes = [], 0
             # Retire chunks: keep at most two in flight while there is work to
             # enqueue; otherwise wait for the oldest.
             while inflight and (len(inflight) > 2 or not running or inflight[0][0].query()):
-                ev, fin = inflight.popleft()
+                ev, fin, held, freed = inflight.popleft()
                 ev.synchronize()
                 t = clock() - t0
                 for e in fin:
                     e[2].completed_s = t
                     e[1].close()
+                    e[1] = None
+                del fin, held
+                used -= freed
             if not running and not inflight and not queue and pending:
                 wait = pending[0].arrival_s - (clock() - t0)
                 if wait > 0:
@@ -153,6 +219,8 @@ def serve(trace, make_input, *, budget_bytes: int, storage: str = "f16", sigma: 
         st.makespan_s = clock() - t0
     if batch is not None:
         batch.close()
+    st.extra["peak_reserved_bytes"] = peak
+    st.extra["budget_bytes"] = budget_bytes
     records.sort(key=lambda r: r.job_id)
     return st
 

@@ -34,10 +34,20 @@ def test_served_results_equal_solo_runs(dev, budget_mb):
     from paper_1409_7474_amd import lse, serve
     pool = serve.PoolInputs(synth.serving_pool(0, size=512), dev)
     trace = _trace()
+    torch.cuda.synchronize(dev)
+    base = torch.cuda.memory_allocated(dev)
+    torch.cuda.reset_peak_memory_stats(dev)
     st = serve.serve(trace, pool, budget_bytes=budget_mb << 20, storage="f16", chunk=8, keep_masks=True)
+    torch.cuda.synchronize(dev)
+    # Device memory the server allocated: within the budget, plus the masks
+    # it returns (kept) and allocator rounding.
+    masks = sum(j.side * j.side for j in trace)
+    grown = torch.cuda.max_memory_allocated(dev) - base
+    assert st.extra["peak_reserved_bytes"] <= budget_mb << 20
+    assert grown <= (budget_mb << 20) + masks + (1 << 20), (grown, budget_mb << 20, masks)
     assert len(st.records) == len(trace)
     if budget_mb == 24:
-        assert st.max_queue > 0 and st.batches_built > 3
+        assert st.max_queue > 0 and st.batch_updates > 3 and st.batches_created == 1
     else:
         assert st.max_running > 3
     for rec, job in zip(st.records, sorted(trace, key=lambda j: j.job_id)):

@@ -284,6 +284,50 @@ def test_batch_interleaves_with_single_steps(dev):
     batch.close()
 
 
+def test_batch_update_equals_alone(dev):
+    """lse_batch_update: members leave and join between runs (as in
+    continuous batching), on new tables while the old ones are still alive;
+    every image's state equals its run alone bit for bit."""
+    from paper_1409_7474_amd import lse
+    spec = _jobs_spec()
+    jobs = _build(dev, spec)
+    solo = _build(dev, spec)
+    stream = torch.cuda.Stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    batch = lse.Batch(jobs[:4], targets=[30, 25, 30, 12], stream=stream)
+    batch.run(10)
+    held = [batch.update(jobs[1:6], targets=[25, 30, 12, 40, 40])]  # job 0 leaves, 4 and 5 join
+    batch.run(8)
+    held.append(batch.update([jobs[5], jobs[6], jobs[2]], targets=[40, 9, 30]))  # only families 1, 3 left
+    batch.run(9)
+    torch.cuda.synchronize(dev)
+    done = {0: 10, 1: 18, 2: 27, 3: 12, 4: 8, 5: 17, 6: 9}
+    for i, n in done.items():
+        solo[i].run(n)
+        _assert_same(_state(jobs[i]), _state(solo[i]), f"image {i} after {n} iterations")
+    batch.close()
+    del held
+
+
+def test_batch_update_refused_after_graph_runs(dev):
+    """A batch that has replayed from a graph is not re-planned (its captured
+    sequence names the old table): lse_batch_update returns LSE_ERR_STATE and
+    leaves the batch as it was.  Host-side check; nothing is re-captured."""
+    from paper_1409_7474_amd import lse
+    jobs = _build(dev, _jobs_spec()[:3])
+    stream = torch.cuda.Stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    batch = lse.Batch(jobs, stream=stream)
+    batch.run(4, graph=True)
+    with pytest.raises(lse.LSEError) as e:
+        batch.update(jobs[:2])
+    assert e.value.status == lse.LSE_ERR_STATE
+    batch.run(4, graph=True)  # the same captured sequence replays
+    stream.synchronize()
+    assert all(j.stats()["iters_done"] == 8 for j in jobs)
+    batch.close()
+
+
 def test_batch_stop_when_unchanged(dev):
     """Step 5 inside a batch: the noise-free rectangle reaches its exact mask
     and stops; a noisy partner keeps iterating; both equal their solo runs."""

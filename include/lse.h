@@ -313,6 +313,53 @@ lse_status lse_batch_run(lse_batch *b, int32_t iters, int32_t stop_when_unchange
  * caller's. */
 void lse_batch_destroy(lse_batch *b);
 
+/* ---------------------------------------------------------------- autotuner
+ *
+ * The binary-state step kernel (Table I order, binarisation every iteration,
+ * TS 7..15) comes in variants: the tile's owned rows (edge term: 64, 48 or 80;
+ * region terms: 48) and the waves per SIMD it is compiled for (region terms:
+ * 4, 3 or 5; edge: 4).  All variants compute the same results bit for bit.
+ * A process-wide table holds the variant per kernel family (term, template
+ * radius, stored bands, storage type) and size class (round(log2(side)) - 8
+ * clamped to 0..5, side = sqrt(H * W)); lse_init, lse_solve_static and the
+ * batch planner use it (variant 0 where the table has no entry).  Batches
+ * group contexts by family and variant. */
+#define LSE_TUNE_MAX_CANDIDATES 4
+typedef struct {
+    int32_t variant;        /* step-kernel variant, 0 .. 2                    */
+    int32_t tile_rows;      /* owned rows of a step tile                       */
+    int32_t tile_cols;      /* owned columns of a step tile (96)               */
+    int32_t waves_per_simd; /* occupancy the variant is compiled for           */
+    int32_t size_class;     /* size class of the image                         */
+    int32_t candidates;     /* variants timed by lse_autotune (0: not timed)   */
+    float ms[LSE_TUNE_MAX_CANDIDATES]; /* each candidate's run time, in variant order */
+} lse_tuning_t;
+
+/* Time every variant on this job: lse_init (on the caller's workspace, as
+ * for lse_init) and `iters` iterations per candidate, twice, the second run
+ * timed with events on `stream` (synchronises it).  Checks that the
+ * candidates end in the same binary state (LSE_ERR_STATE otherwise, never
+ * expected), enters the fastest in the table for this family and size class,
+ * and reports it in *out.  The workspace holds the last candidate's state
+ * afterwards (initialise again before use).  LSE_ERR_UNSUPPORTED for the
+ * modes without variants (continuous LSF, TS outside 7..15). */
+lse_status lse_autotune(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,
+                        size_t workspace_bytes, int32_t iters, void *stream, lse_tuning_t *out);
+
+/* The table's entry for p's family and size class (variant 0 and
+ * candidates 0 when there is none). */
+lse_status lse_tuning_lookup(const lse_params *p, lse_tuning_t *out);
+
+/* The variant a context runs (fixed at its lse_init). */
+lse_status lse_ctx_tuning(const lse_ctx *c, lse_tuning_t *out);
+
+/* Enter `variant` for p's family and size class by hand (tests, or a table
+ * kept from an earlier process). */
+lse_status lse_tuning_set(const lse_params *p, int32_t variant);
+
+/* Empty the table. */
+void lse_tuning_clear(void);
+
 /* ------------------------------------------------- allocation-free solve
  *
  * For callers that cannot allocate device memory (code under HIP graph

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <set>
@@ -23,6 +24,7 @@ struct lse_ctx {
     int dense;          // continuous LSF kept in a plane (any mode but Table I with binarisation every iteration)
     int phi_binary;     // dense: the next iteration's phi is the binary function in the bit plane
     int r, ts, nch;     // LSF smoothing
+    int variant;        // step-kernel variant (tile rows, waves per SIMD), from the autotuner's table
     int r1, ts1;        // edge term: image pre-smoothing
     int WW;             // bit words per row
     long long hw;
@@ -59,6 +61,7 @@ struct lse_ctx {
 struct lse_batch {
     struct Group {
         int r, NB, edge, storage;     // kernel family
+        int variant;                  // step-kernel variant of its contexts
         int first, count;             // ImgArgs index range
         int step_bits, mpass_bits;    // unit bits of the map entries
         size_t step_map, mpass_map;   // offsets (entries) into the map
@@ -185,13 +188,14 @@ Layout layout_of(const lse_params *p) {
     L.tilesum = L.tilelast = 0;
     if (p->term != LSE_TERM_EDGE && !dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
         L.tilesum = o;
-        o = align_up(o + (size_t)step_tiles(p->height, p->width, 0) * sizeof(TileSum));
+        o = align_up(o + (size_t)step_tiles_max(p->height, p->width, 0) * sizeof(TileSum));
         L.tilelast = o;
-        o = align_up(o + (size_t)step_tiles(p->height, p->width, 0) * sizeof(TileSum));
+        o = align_up(o + (size_t)step_tiles_max(p->height, p->width, 0) * sizeof(TileSum));
     }
     L.sched = L.plan = 0;
     if (!dense_mode(p) && fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) {
-        const size_t tiles = (size_t)step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE);
+        // sized for every variant, so the workspace does not depend on the tuning
+        const size_t tiles = (size_t)step_tiles_max(p->height, p->width, p->term == LSE_TERM_EDGE);
         L.sched = o;
         o = align_up(o + 3 * ((tiles + 31) / 32) * 4);
         L.plan = o;
@@ -389,7 +393,7 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
         if (c->host_args.plan && !(region && c->NB > 1)) e = launch_plan(c->dargs, c->n, s);
         if (e == hipSuccess)
             e = launch_step(c->dargs, nullptr, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r,
-                            c->NB, region ? 0 : 1, storage, s);
+                            c->NB, region ? 0 : 1, storage, c->variant, s);
     } else {
         e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
     }
@@ -406,6 +410,59 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     c->raw_next = 0;
     c->last_stream = s;
     return LSE_OK;
+}
+
+// ------------------------------------------------------------ tuning table
+//
+// The autotuner's choices: step-kernel variant per kernel family (term, radius,
+// stored bands, storage type) and size class (image side rounded to a power of
+// two, 256 .. 8192 and up).  lse_init takes the variant from here; families
+// and sizes never tuned run variant 0.
+struct TuneKey {
+    int edge, r, NB, storage, cls;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(edge, r, NB, storage, cls) < std::tie(o.edge, o.r, o.NB, o.storage, o.cls);
+    }
+};
+struct TuneEntry {
+    int variant;
+    int candidates;
+    float ms[LSE_TUNE_MAX_CANDIDATES];
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+int size_class(long long hw) {
+    // round(log2(sqrt(hw))) - 8, clamped to 0 .. 5 (sides 256 .. 8192)
+    const double side = sqrt((double)hw);
+    int c = (int)lround(log2(side)) - 8;
+    return std::max(0, std::min(5, c));
+}
+
+TuneKey tune_key(const lse_params *p) {
+    const int edge = p->term == LSE_TERM_EDGE;
+    const int nb = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
+    return TuneKey{edge, resolved_ksize(p->ksize, p->sigma) / 2, nb, p->storage,
+                   size_class((long long)p->height * p->width)};
+}
+
+int tuned_variant(const lse_params *p) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(p));
+    return it == g_tune.end() ? 0 : it->second.variant;
+}
+
+void fill_tuning(const lse_params *p, int variant, const TuneEntry *e, lse_tuning_t *out) {
+    memset(out, 0, sizeof(*out));
+    const int edge = p->term == LSE_TERM_EDGE;
+    out->variant = variant;
+    step_variant_info(edge, variant, &out->tile_rows, &out->waves_per_simd);
+    out->tile_cols = 96;
+    out->size_class = size_class((long long)p->height * p->width);
+    if (e) {
+        out->candidates = e->candidates;
+        for (int i = 0; i < e->candidates && i < LSE_TUNE_MAX_CANDIDATES; ++i) out->ms[i] = e->ms[i];
+    }
 }
 
 // Host-side checks of lse_init's arguments (nothing enqueued).
@@ -427,9 +484,10 @@ lse_status check_init_args(const lse_params *p, const void *image_dev, const uin
 // tables and the image arguments reach the device as kernel arguments rather
 // than host-to-device copies.
 hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev,
-                    void *workspace_dev, hipStream_t st, bool tables_by_kernel) {
+                    void *workspace_dev, hipStream_t st, bool tables_by_kernel, int variant = -1) {
     const Layout L = layout_of(p);
     c->p = *p;
+    c->variant = variant >= 0 ? variant : tuned_variant(p);
     c->region = p->term != LSE_TERM_EDGE;
     c->NB = p->term != LSE_TERM_REGION ? 1 : (p->bands == 3 ? 4 : p->bands);
     c->esz = p->storage == LSE_F32 ? 4 : 2;
@@ -477,7 +535,7 @@ hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, cons
         A.H = p->height;
         A.W = p->width;
         A.WW = c->WW;
-        A.tiles = step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE);
+        A.tiles = step_tiles(p->height, p->width, p->term == LSE_TERM_EDGE, c->variant);
         A.dt = p->dt;
         A.fix = c->fix;
         A.inv_fix = c->inv_fix;
@@ -744,6 +802,97 @@ void lse_destroy(lse_ctx *c) {
     delete c;
 }
 
+lse_status lse_tuning_lookup(const lse_params *p, lse_tuning_t *out) {
+    if (!out) return LSE_ERR_INVALID_ARG;
+    const lse_status v = validate(p);
+    if (v != LSE_OK) return v;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(p));
+    if (it == g_tune.end()) fill_tuning(p, 0, nullptr, out);
+    else fill_tuning(p, it->second.variant, &it->second, out);
+    return LSE_OK;
+}
+
+lse_status lse_ctx_tuning(const lse_ctx *c, lse_tuning_t *out) {
+    if (!c || !out) return LSE_ERR_INVALID_ARG;
+    fill_tuning(&c->p, c->variant, nullptr, out);
+    return LSE_OK;
+}
+
+lse_status lse_tuning_set(const lse_params *p, int32_t variant) {
+    const lse_status v = validate(p);
+    if (v != LSE_OK) return v;
+    if (variant < 0 || variant >= kNumStepVariants) return LSE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneEntry e;
+    memset(&e, 0, sizeof(e));
+    e.variant = variant;
+    g_tune[tune_key(p)] = e;
+    return LSE_OK;
+}
+
+void lse_tuning_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+}
+
+lse_status lse_autotune(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,
+                        size_t workspace_bytes, int32_t iters, void *stream, lse_tuning_t *out) {
+    if (!out || iters < 1) return LSE_ERR_INVALID_ARG;
+    const lse_status v = check_init_args(p, image_dev, init_mask_dev, workspace_dev, workspace_bytes);
+    if (v != LSE_OK) return v;
+    if (dense_mode(p) || !fast_radius(resolved_ksize(p->ksize, p->sigma) / 2)) return LSE_ERR_UNSUPPORTED;
+    const hipStream_t s = as_stream(stream);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return LSE_ERR_DEVICE;
+    }
+    TuneEntry e;
+    memset(&e, 0, sizeof(e));
+    e.candidates = std::min(kNumStepVariants, (int)LSE_TUNE_MAX_CANDIDATES);
+    lse_status r = LSE_OK;
+    unsigned long long first = 0;
+    for (int var = 0; var < e.candidates && r == LSE_OK; ++var) {
+        // Each candidate runs twice from the same initial state; the second
+        // run is timed (the first loads the code and warms the caches).
+        for (int rep = 0; rep < 2 && r == LSE_OK; ++rep) {
+            lse_ctx c;
+            hipError_t he = init_ctx(&c, p, image_dev, init_mask_dev, workspace_dev, s, false, var);
+            if (he == hipSuccess) he = hipEventRecord(ev[0], s);
+            for (int i = 0; i < iters && he == hipSuccess; ++i)
+                if (enqueue_step(&c, 0, s) != LSE_OK) he = hipErrorUnknown;
+            if (he == hipSuccess) he = hipEventRecord(ev[1], s);
+            const uint32_t *const bits[2] = {c.bits[0], c.bits[1]};
+            if (he == hipSuccess) he = launch_digest(bits, c.st, p->height, c.WW, s);
+            unsigned long long d = 0;
+            if (he == hipSuccess) he = hipMemcpyAsync(&d, &c.st->digest, sizeof(d), hipMemcpyDeviceToHost, s);
+            if (he == hipSuccess) he = hipStreamSynchronize(s);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (he != hipSuccess) {
+                r = LSE_ERR_DEVICE;
+                break;
+            }
+            if (var == 0 && rep == 0) first = d;
+            else if (d != first) r = LSE_ERR_STATE;  // variants must agree bit for bit
+            if (rep == 1) e.ms[var] = ms;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (r != LSE_OK) return r;
+    e.variant = 0;
+    for (int var = 1; var < e.candidates; ++var)
+        if (e.ms[var] < e.ms[e.variant]) e.variant = var;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(p)] = e;
+    }
+    fill_tuning(p, e.variant, &e, out);
+    return LSE_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------- allocation-free solve
@@ -843,7 +992,7 @@ size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
     auto key = [&](int i) {
         const lse_ctx *c = cs[i];
         const int edge = c->p.term == LSE_TERM_EDGE;
-        return std::make_tuple(edge, c->r, edge ? 1 : c->NB, (int)c->p.storage);
+        return std::make_tuple(edge, c->r, edge ? 1 : c->NB, (int)c->p.storage, c->variant);
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     b->cs.clear();
@@ -857,6 +1006,7 @@ size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
         g.r = std::get<1>(key(order[j]));
         g.NB = std::get<2>(key(order[j]));
         g.storage = std::get<3>(key(order[j]));
+        g.variant = std::get<4>(key(order[j]));
         g.first = (int)b->cs.size();
         g.count = (int)(e - j);
         long long total = 0, maxt = 1, maxm = 1;
@@ -1103,7 +1253,7 @@ hipError_t enqueue_batch(lse_batch *b, int iters, int stop, hipStream_t s) {
                                  g.storage, gs);
             if (e == hipSuccess)
                 e = launch_step(b->dargs + g.first, map, nmap, g.step_bits, g.step_grid, k, stop, g.r, g.NB, g.edge,
-                                g.storage, gs);
+                                g.storage, g.variant, gs);
             if (e != hipSuccess) break;
         }
     }
@@ -1178,6 +1328,6 @@ void lse_batch_destroy(lse_batch *b) {
     delete b;
 }
 
-int32_t lse_version(void) { return 105; }
+int32_t lse_version(void) { return 106; }
 
 }  // extern "C"

@@ -587,11 +587,25 @@ constexpr int kFWords = 6;     // staged bit words per row: global words x0/32 -
 constexpr int kSB = 8;         // rows per block of the rolling vertical window
 constexpr int kCG = 4;         // rows per group of data-term loads in the binarisation phase
 
-template <int R, bool EDGE>
+// Variants of the step kernel, picked per kernel family and image size by
+// the autotuner (lse_autotune): the tile's owned rows and the waves per SIMD
+// the kernel is compiled for (its register budget).  Every variant gives the
+// same values bit for bit: the edge step's results are per pixel, and the
+// region variants keep the 48-row tiling, which fixes the order of the FP32
+// statistics sums within a tile.
+constexpr int kStepVariants = 3;
+template <bool EDGE, int V>
+struct StepVariant {
+    // edge: 64, 48 or 80 rows at 4 waves per SIMD; region: 48 rows at 4, 3 or 5.
+    static constexpr int FY = EDGE ? (V == 0 ? kFYEdge : V == 1 ? 48 : 80) : kFYRegion;
+    static constexpr int OCC = EDGE ? 4 : (V == 0 ? 4 : V == 1 ? 3 : 5);
+};
+
+template <int R, bool EDGE, int FYV = (EDGE ? kFYEdge : kFYRegion)>
 struct FastGeom {
     static constexpr int TS = 2 * R + 1;
     static constexpr int RU = EDGE ? 0 : R;      // halo of the binarised field
-    static constexpr int FY = EDGE ? kFYEdge : kFYRegion;  // owned rows
+    static constexpr int FY = FYV;               // owned rows
     static constexpr int UH = FY + 2 * RU;       // rows where b^n is computed
     static constexpr int PH = UH + 2;            // rows of phi^n
     static constexpr int PW = kFX + 2 * RU + 2;  // columns of phi^n (<= 128)

@@ -86,6 +86,7 @@ struct DevState {
     unsigned long long acc_steps;   // profiling: steps counted into acc_needed
     unsigned long long acc_visited; // profiling: step tiles the counted steps visited (fast path)
     unsigned long long acc_heavy;   // profiling: of those, tiles recorded as heavy (not quiet)
+    unsigned long long digest;      // launch_digest: digest of the binary state
 };
 
 // Fixed-point region sums and count of one step tile: the all-inside case
@@ -177,7 +178,7 @@ struct Store {
     static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
     static hipError_t step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
-                           int k, int stop, int r, int NB, int edge, hipStream_t s);
+                           int k, int stop, int r, int NB, int edge, int variant, hipStream_t s);
     static hipError_t step_generic(const StepArgs &a, int NB, int edge, hipStream_t s);
     static hipError_t mpass(const ImgArgs *args, const uint32_t *map, int unit_bits, unsigned grid, int k, int stop,
                             int NB, hipStream_t s);
@@ -199,7 +200,11 @@ struct Store {
 // error; `storage` is an lse_dtype.
 size_t tile_smem_bytes(int r, int nch, int edge);
 bool fast_radius(int r);                 // the step kernel has a compiled variant for radius r
-int step_tiles(int H, int W, int edge);  // workgroup tiles of the step kernel for an H x W image
+// Step-kernel variants (tile rows, waves per SIMD; see StepVariant).
+constexpr int kNumStepVariants = 3;
+void step_variant_info(int edge, int variant, int *tile_rows, int *waves_per_simd);
+int step_tiles(int H, int W, int edge, int variant);  // workgroup tiles of the step kernel for an H x W image
+int step_tiles_max(int H, int W, int edge);           // the most over the variants (workspace sizing)
 int mpass_groups(int H, int W);          // workgroups of the normaliser pass
 // Copy `bytes` (a multiple of 4, at most kPutWords words) of host memory to
 // dst on the stream, carried as a kernel argument (no host-to-device copy).
@@ -227,7 +232,10 @@ hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float
 // (batch visit list) has *nmap entries; workgroups past them have no work.
 unsigned step_launch_grid(int tiles);
 hipError_t launch_step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid, int k,
-                       int stop, int r, int NB, int edge, int storage, hipStream_t s);
+                       int stop, int r, int NB, int edge, int storage, int variant, hipStream_t s);
+// Order-independent 64-bit digest of the current binary state (bits[iters &
+// 1]) into st->digest (cleared first): a check that two runs agree.
+hipError_t launch_digest(const uint32_t *const bits[2], DevState *st, int H, int WW, hipStream_t s);
 // Batch visit list of one group for launch k: list[0] entries, then
 // (image << unit_bits) | tile, heavy tiles first.  wbase: nimg + 1 prefix
 // offsets of the images' heavy-record words.

@@ -30,6 +30,8 @@
 // workgroup scheduling or on which other images share a launch.
 #include <string.h>
 
+#include <algorithm>
+
 #include "lse_device.h"
 
 namespace lse {
@@ -535,9 +537,32 @@ size_t tile_smem_bytes(int r, int nch, int edge) { return tile_smem_words(r, nch
 
 bool fast_radius(int r) { return r >= 3 && r <= 7; }
 
-int step_tiles(int H, int W, int edge) {
-    const int fy = edge ? kFYEdge : kFYRegion;
+void step_variant_info(int edge, int variant, int *tile_rows, int *waves_per_simd) {
+    static_assert(kNumStepVariants == kStepVariants, "host and device agree on the variants");
+    int fy = 0, occ = 0;
+    switch (variant) {
+        case 0: fy = edge ? StepVariant<true, 0>::FY : StepVariant<false, 0>::FY;
+                occ = edge ? StepVariant<true, 0>::OCC : StepVariant<false, 0>::OCC; break;
+        case 1: fy = edge ? StepVariant<true, 1>::FY : StepVariant<false, 1>::FY;
+                occ = edge ? StepVariant<true, 1>::OCC : StepVariant<false, 1>::OCC; break;
+        case 2: fy = edge ? StepVariant<true, 2>::FY : StepVariant<false, 2>::FY;
+                occ = edge ? StepVariant<true, 2>::OCC : StepVariant<false, 2>::OCC; break;
+    }
+    if (tile_rows) *tile_rows = fy;
+    if (waves_per_simd) *waves_per_simd = occ;
+}
+
+int step_tiles(int H, int W, int edge, int variant) {
+    int fy = 0;
+    step_variant_info(edge, variant, &fy, nullptr);
+    if (fy <= 0) return 0;
     return ((W + kFX - 1) / kFX) * ((H + fy - 1) / fy);
+}
+
+int step_tiles_max(int H, int W, int edge) {
+    int t = 0;
+    for (int v = 0; v < kNumStepVariants; ++v) t = std::max(t, step_tiles(H, W, edge, v));
+    return t;
 }
 
 int mpass_groups(int H, int W) {
@@ -584,14 +609,41 @@ hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float
 }
 
 hipError_t launch_step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid, int k,
-                       int stop, int r, int NB, int edge, int storage, hipStream_t s) {
+                       int stop, int r, int NB, int edge, int storage, int variant, hipStream_t s) {
     if (grid == 0) return hipSuccess;
     switch (storage) {
-        case LSE_F32: return Store<float>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
-        case LSE_F16: return Store<__half>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, s);
+        case LSE_F32: return Store<float>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, variant, s);
+        case LSE_F16: return Store<__half>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, variant, s);
+        case LSE_BF16:
+            return Store<__hip_bfloat16>::step(args, map, nmap, unit_bits, grid, k, stop, r, NB, edge, variant, s);
     }
     return hipErrorInvalidValue;
+}
+
+__global__ void digest_clear_kernel(DevState *st) {
+    if (threadIdx.x == 0) st->digest = 0ull;
+}
+
+// Sum over the words of the current bit plane of a per-word mix of value and
+// index (modulo 2^64, so the order of the atomics does not matter).
+__global__ void digest_kernel(const uint32_t *__restrict__ b0, const uint32_t *__restrict__ b1, DevState *st,
+                              long long nwords) {
+    const uint32_t *bits = (st->iters & 1) ? b1 : b0;
+    unsigned long long acc = 0ull;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (long long)gridDim.x * blockDim.x) {
+        unsigned long long v = ((unsigned long long)bits[i] + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+        v ^= (unsigned long long)i * 0x94D049BB133111EBull;
+        acc += v ^ (v >> 31);
+    }
+    if (acc) atomicAdd(&st->digest, acc);
+}
+
+hipError_t launch_digest(const uint32_t *const bits[2], DevState *st, int H, int WW, hipStream_t s) {
+    const long long n = (long long)H * WW;
+    hipLaunchKernelGGL(digest_clear_kernel, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(digest_kernel, dim3(stream_blocks(n, 8)), dim3(kThreads), 0, s, bits[0], bits[1], st, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_step_generic(const StepArgs &a, int NB, int edge, int storage, hipStream_t s) {

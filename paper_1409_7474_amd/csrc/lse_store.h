@@ -513,14 +513,13 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs A) {
 // region term, 64 for the edge term).  Launch k runs iteration
 // n = n0 + k of every image it covers (one image when map is null; else the
 // workgroup map names image and tile).
-template <int R, int NB, bool EDGE, typename ST>
-// At least 4 waves per SIMD: the B = 4 region kernels of the larger radii
-// otherwise take 129-134 VGPRs and drop to 3 (R = 6: 128, no spill).
-__global__ __launch_bounds__(kThreads, 4) void step_fast_kernel(const ImgArgs *__restrict__ args,
-                                                                 const uint32_t *__restrict__ map,
-                                                                 const int *__restrict__ nmap, int unit_bits, int k,
-                                                                 int stop) {
-    using G = FastGeom<R, EDGE>;
+template <int R, int NB, bool EDGE, typename ST, int V>
+// V: the variant's tile rows and waves per SIMD (StepVariant).  At 4 waves per
+// SIMD the B = 4 region kernels of the larger radii are held to 128 VGPRs.
+__global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fast_kernel(
+    const ImgArgs *__restrict__ args, const uint32_t *__restrict__ map, const int *__restrict__ nmap, int unit_bits,
+    int k, int stop) {
+    using G = FastGeom<R, EDGE, StepVariant<EDGE, V>::FY>;
     constexpr int TS = G::TS;
     extern __shared__ float smem[];
     __shared__ Totals tot;
@@ -1370,24 +1369,36 @@ __global__ void plane_out_kernel(const ST *__restrict__ p0, const ST *__restrict
 
 // ---------------------------------------------------------------- launchers
 
+template <int R, int NB, bool EDGE, typename ST, int V>
+static hipError_t launch_step_fast_v(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits,
+                                     unsigned grid, int k, int stop, hipStream_t s) {
+    const size_t sm = (size_t)FastGeom<R, EDGE, StepVariant<EDGE, V>::FY>::smem_words * 4;
+    const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE, ST, V>, sm);
+    if (e != hipSuccess) return e;
+    return launch_timed(step_fast_kernel<R, NB, EDGE, ST, V>, dim3(grid), dim3(kThreads), (uint32_t)sm, s, args, map,
+                        nmap, unit_bits, k, stop);
+}
+
 template <int R, int NB, bool EDGE, typename ST>
 static hipError_t launch_step_fast_t(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits,
-                                     unsigned grid, int k, int stop, hipStream_t s) {
-    const size_t sm = (size_t)FastGeom<R, EDGE>::smem_words * 4;
-    const hipError_t e = ensure_lds(step_fast_kernel<R, NB, EDGE, ST>, sm);
-    if (e != hipSuccess) return e;
-    return launch_timed(step_fast_kernel<R, NB, EDGE, ST>, dim3(grid), dim3(kThreads), (uint32_t)sm, s, args, map,
-                        nmap, unit_bits, k, stop);
+                                     unsigned grid, int k, int stop, int variant, hipStream_t s) {
+    static_assert(kStepVariants == 3, "one case per variant");
+    switch (variant) {
+        case 0: return launch_step_fast_v<R, NB, EDGE, ST, 0>(args, map, nmap, unit_bits, grid, k, stop, s);
+        case 1: return launch_step_fast_v<R, NB, EDGE, ST, 1>(args, map, nmap, unit_bits, grid, k, stop, s);
+        case 2: return launch_step_fast_v<R, NB, EDGE, ST, 2>(args, map, nmap, unit_bits, grid, k, stop, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int R, typename ST>
 static hipError_t launch_step_fast_r(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits,
-                                     unsigned grid, int k, int stop, int NB, int edge, hipStream_t s) {
-    if (edge) return launch_step_fast_t<R, 1, true, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
+                                     unsigned grid, int k, int stop, int NB, int edge, int variant, hipStream_t s) {
+    if (edge) return launch_step_fast_t<R, 1, true, ST>(args, map, nmap, unit_bits, grid, k, stop, variant, s);
     switch (NB) {
-        case 1: return launch_step_fast_t<R, 1, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
-        case 2: return launch_step_fast_t<R, 2, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
-        case 4: return launch_step_fast_t<R, 4, false, ST>(args, map, nmap, unit_bits, grid, k, stop, s);
+        case 1: return launch_step_fast_t<R, 1, false, ST>(args, map, nmap, unit_bits, grid, k, stop, variant, s);
+        case 2: return launch_step_fast_t<R, 2, false, ST>(args, map, nmap, unit_bits, grid, k, stop, variant, s);
+        case 4: return launch_step_fast_t<R, 4, false, ST>(args, map, nmap, unit_bits, grid, k, stop, variant, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1494,13 +1505,13 @@ hipError_t Store<ST>::stats(const StepArgs &a, int NB, int raw, int slot, hipStr
 
 template <typename ST>
 hipError_t Store<ST>::step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
-                           int k, int stop, int r, int NB, int edge, hipStream_t s) {
+                           int k, int stop, int r, int NB, int edge, int variant, hipStream_t s) {
     switch (r) {
-        case 3: return launch_step_fast_r<3, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
-        case 4: return launch_step_fast_r<4, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
-        case 5: return launch_step_fast_r<5, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
-        case 6: return launch_step_fast_r<6, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
-        case 7: return launch_step_fast_r<7, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, s);
+        case 3: return launch_step_fast_r<3, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, variant, s);
+        case 4: return launch_step_fast_r<4, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, variant, s);
+        case 5: return launch_step_fast_r<5, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, variant, s);
+        case 6: return launch_step_fast_r<6, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, variant, s);
+        case 7: return launch_step_fast_r<7, ST>(args, map, nmap, unit_bits, grid, k, stop, NB, edge, variant, s);
     }
     return hipErrorInvalidValue;
 }

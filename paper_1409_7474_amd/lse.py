@@ -33,7 +33,7 @@ EXPORTS = (
     "lse_params_default", "lse_workspace_bytes", "lse_init", "lse_step", "lse_run", "lse_mask",
     "lse_lsf", "lse_set_mask", "lse_set_lsf", "lse_edge_map", "lse_stats", "lse_check", "lse_profile", "lse_profile_read",
     "lse_step_bytes_per_pixel", "lse_destroy", "lse_batch_bytes", "lse_batch_create", "lse_batch_update",
-    "lse_batch_run",
+    "lse_batch_run", "lse_autotune", "lse_tuning_lookup", "lse_ctx_tuning", "lse_tuning_set", "lse_tuning_clear",
     "lse_batch_destroy", "lse_solve_static", "lse_status_str", "lse_version",
 )
 
@@ -67,6 +67,19 @@ class lse_profile_t(ctypes.Structure):
         ("needed_pixels", ctypes.c_int64), ("counted_steps", ctypes.c_int64),
         ("visited_tiles", ctypes.c_int64), ("heavy_tiles", ctypes.c_int64), ("tiles", ctypes.c_int64),
     ]
+
+
+class lse_tuning_t(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+        ("waves_per_simd", ctypes.c_int32), ("size_class", ctypes.c_int32), ("candidates", ctypes.c_int32),
+        ("ms", ctypes.c_float * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"variant": self.variant, "tile_rows": self.tile_rows, "tile_cols": self.tile_cols,
+                "waves_per_simd": self.waves_per_simd, "size_class": self.size_class,
+                "candidates": self.candidates, "ms": [round(float(x), 4) for x in self.ms[:self.candidates]]}
 
 
 PROFILE_TIMING = 1
@@ -142,6 +155,16 @@ def load() -> ctypes.CDLL:
     lib.lse_batch_destroy.restype = None
     lib.lse_solve_static.argtypes = [P(lse_params), vp, vp, i32, i32, vp, vp, vp]
     lib.lse_solve_static.restype = st
+    lib.lse_autotune.argtypes = [P(lse_params), vp, vp, vp, ctypes.c_size_t, i32, vp, P(lse_tuning_t)]
+    lib.lse_autotune.restype = st
+    lib.lse_tuning_lookup.argtypes = [P(lse_params), P(lse_tuning_t)]
+    lib.lse_tuning_lookup.restype = st
+    lib.lse_ctx_tuning.argtypes = [vp, P(lse_tuning_t)]
+    lib.lse_ctx_tuning.restype = st
+    lib.lse_tuning_set.argtypes = [P(lse_params), i32]
+    lib.lse_tuning_set.restype = st
+    lib.lse_tuning_clear.argtypes = []
+    lib.lse_tuning_clear.restype = None
     lib.lse_status_str.argtypes = [st]
     lib.lse_status_str.restype = ctypes.c_char_p
     lib.lse_version.argtypes = []
@@ -285,6 +308,34 @@ def lse_solve_static(p: lse_params, image_ptr: int, mask_ptr: int, max_iters: in
     _check(load().lse_solve_static(ctypes.byref(p), image_ptr, mask_ptr, int(max_iters),
                                    int(bool(stop_when_unchanged)), mask_out_ptr, lsf_out_ptr, stream),
            "lse_solve_static")
+
+
+def lse_autotune(p: lse_params, image_ptr: int, mask_ptr: int, workspace_ptr: int, workspace_bytes: int,
+                 iters: int, stream: int = 0) -> lse_tuning_t:
+    out = lse_tuning_t()
+    _check(load().lse_autotune(ctypes.byref(p), image_ptr, mask_ptr, workspace_ptr, workspace_bytes, int(iters),
+                               stream, ctypes.byref(out)), "lse_autotune")
+    return out
+
+
+def lse_tuning_lookup(p: lse_params) -> lse_tuning_t:
+    out = lse_tuning_t()
+    _check(load().lse_tuning_lookup(ctypes.byref(p), ctypes.byref(out)), "lse_tuning_lookup")
+    return out
+
+
+def lse_ctx_tuning(ctx) -> lse_tuning_t:
+    out = lse_tuning_t()
+    _check(load().lse_ctx_tuning(ctx, ctypes.byref(out)), "lse_ctx_tuning")
+    return out
+
+
+def lse_tuning_set(p: lse_params, variant: int) -> None:
+    _check(load().lse_tuning_set(ctypes.byref(p), int(variant)), "lse_tuning_set")
+
+
+def lse_tuning_clear() -> None:
+    load().lse_tuning_clear()
 
 
 # ------------------------------------------------------------ torch wrapper
@@ -445,6 +496,10 @@ class LSE:
     def step_bytes_per_pixel(self) -> float:
         return lse_step_bytes_per_pixel(self.ctx)
 
+    def tuning(self) -> dict:
+        """The step-kernel variant this job runs (lse_ctx_tuning)."""
+        return lse_ctx_tuning(self.ctx).as_dict()
+
     def close(self) -> None:
         if getattr(self, "ctx", None):
             lse_destroy(self.ctx)
@@ -455,6 +510,25 @@ class LSE:
             self.close()
         except Exception:
             pass
+
+
+def autotune(image, init_mask, iters: int = 30, stream=None, **kw) -> dict:
+    """lse_autotune on this job (image / init_mask as for LSE, keyword
+    parameters as for make_params) with a temporary workspace; the choice is
+    entered in the library's table for the job's family and size class."""
+    torch = _torch()
+    if image.dim() == 2:
+        image = image.unsqueeze(-1)
+    image = image.contiguous()
+    init_mask = init_mask.to(torch.uint8).contiguous()
+    h, w, b = image.shape
+    p = make_params(h, w, b, **kw)
+    p.image_dtype = _dtype_code(image)
+    nbytes = lse_workspace_bytes(p)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=image.device)
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    s = stream if stream is not None else torch.cuda.current_stream(image.device)
+    return lse_autotune(p, image.data_ptr(), init_mask.data_ptr(), ptr, nbytes, iters, int(s.cuda_stream)).as_dict()
 
 
 class Batch:

@@ -175,3 +175,36 @@ def test_static_solve_argument_checks():
     bad = lse.make_params(64, 64, 1)
     bad.dt = -1.0
     assert lib.lse_solve_static(P(bad), 16, 16, 10, 0, 16, None, None) == lse.LSE_ERR_INVALID_ARG
+
+
+def test_tuning_table_host_side():
+    """The autotuner's table: set, look up by family and size class, clear;
+    invalid variants and parameters are refused.  No GPU call is involved."""
+    lse.lse_tuning_clear()
+    p = lse.make_params(1000, 1100, 4, term="edge", ksize=11)
+    t = lse.lse_tuning_lookup(p)
+    assert (t.variant, t.candidates, t.tile_rows, t.tile_cols) == (0, 0, 64, 96)
+    assert t.size_class == 2  # side ~1049 rounds to 1024
+    lse.lse_tuning_set(p, 2)
+    assert lse.lse_tuning_lookup(p).tile_rows == 80
+    # same family and size class, other size: same entry; other class: none
+    assert lse.lse_tuning_lookup(lse.make_params(900, 1200, 4, term="edge", ksize=11)).variant == 2
+    assert lse.lse_tuning_lookup(lse.make_params(2048, 2048, 4, term="edge", ksize=11)).variant == 0
+    # other family (band count does not matter for the edge term, the radius does)
+    assert lse.lse_tuning_lookup(lse.make_params(1000, 1100, 1, term="edge", ksize=11)).variant == 2
+    assert lse.lse_tuning_lookup(lse.make_params(1000, 1100, 4, term="edge", ksize=13)).variant == 0
+    r = lse.make_params(1000, 1100, 4, ksize=11)
+    lse.lse_tuning_set(r, 1)
+    t = lse.lse_tuning_lookup(r)
+    assert (t.variant, t.tile_rows, t.waves_per_simd) == (1, 48, 3)
+    lib = lse.load()
+    assert lib.lse_tuning_set(ctypes.byref(p), 3) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_tuning_set(ctypes.byref(p), -1) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_tuning_set(None, 0) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_tuning_lookup(None, None) == lse.LSE_ERR_INVALID_ARG
+    assert lib.lse_ctx_tuning(None, None) == lse.LSE_ERR_INVALID_ARG
+    out = lse.lse_tuning_t()
+    assert lib.lse_autotune(ctypes.byref(p), 16, 16, 256, 1 << 30, 0, None, ctypes.byref(out)) == \
+        lse.LSE_ERR_INVALID_ARG  # no iterations
+    lse.lse_tuning_clear()
+    assert lse.lse_tuning_lookup(p).variant == 0

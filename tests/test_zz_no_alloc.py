@@ -64,6 +64,8 @@ def test_static_solve_equals_workspace_solve_twice(dev, term, bands, storage, or
         assert lse.lse_workspace_bytes(p) <= lse.STATIC_WORKSPACE_BYTES
         mask = masks["edge" if term == "edge" else "region"]
         runs.append((p, img, mask))
+    # inputs were written on the current stream: the solve stream waits for them
+    stream.wait_stream(torch.cuda.current_stream(dev))
     print(f"static solve: {term} B={bands} {storage} {order} every {every} TS {ts}: {big} then {small}",
           flush=True)
     refs = [_workspace_run(p, img, mask, iters, False, dev, sid) for p, img, mask in runs]
@@ -83,13 +85,19 @@ def test_static_solve_stops_when_unchanged_like_run(dev):
     stream = torch.cuda.Stream(dev)
     sid = int(stream.cuda_stream)
     big_img, big_masks = _inputs(dev, 700, 500, 4, 3)
+    stream.wait_stream(torch.cuda.current_stream(dev))
     pb = lse.make_params(700, 500, 4, sigma=1.0, ksize=7)
-    _static_run(pb, big_img, big_masks["region"], 25, False, dev, sid)
+    # its outputs stay referenced until the stream has written them (a freed
+    # tensor's memory could otherwise be handed to the next inputs meanwhile)
+    big_out = _static_run(pb, big_img, big_masks["region"], 25, False, dev, sid)
+    torch.cuda.synchronize(dev)
+    del big_out
     img = torch.full((200, 240, 1), 0.3, dtype=torch.float32, device=dev)
     img[60:130, 80:150] = 0.7
     mask = torch.zeros((200, 240), dtype=torch.uint8, device=dev)
     mask[50:150, 60:180] = 1
     p = lse.make_params(200, 240, 1, sigma=1.0, ksize=7)
+    stream.wait_stream(torch.cuda.current_stream(dev))  # inputs written on the current stream
     m_ref, f_ref = _workspace_run(p, img, mask, 200, True, dev, sid)
     m, f = _static_run(p, img, mask, 200, True, dev, sid)
     torch.cuda.synchronize(dev)

@@ -14,14 +14,14 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _trace():
+def _trace(gap=0.01):
     # 14 small jobs, both terms, 1 and 4 bands, staggered arrivals (some at
-    # once), uneven iteration counts.
+    # once, mean gap `gap` seconds otherwise), uneven iteration counts.
     rng = np.random.default_rng(5)
     jobs = []
     t = 0.0
     for i in range(14):
-        t += float(rng.exponential(0.01)) if i % 3 else 0.0
+        t += float(rng.exponential(gap)) if i % 3 else 0.0
         jobs.append(synth.Job(i, t, int(rng.integers(64, 400)), 1 if i % 2 else 4,
                               "region" if i % 4 < 2 else "edge", int(rng.integers(20, 60))))
     return jobs
@@ -29,11 +29,12 @@ def _trace():
 
 @pytest.mark.parametrize("budget_mb", [4096, 24])
 def test_served_results_equal_solo_runs(dev, budget_mb):
-    """With a large budget every job runs concurrently; with 24 MB jobs queue
-    for memory and join running batches as others finish."""
+    """With a large budget and arrivals close together the jobs run
+    concurrently; with 24 MB jobs queue for memory and join running batches
+    as others finish."""
     from paper_1409_7474_amd import lse, serve
     pool = serve.PoolInputs(synth.serving_pool(0, size=512), dev)
-    trace = _trace()
+    trace = _trace(0.01 if budget_mb == 24 else 0.0002)
     torch.cuda.synchronize(dev)
     base = torch.cuda.memory_allocated(dev)
     torch.cuda.reset_peak_memory_stats(dev)
@@ -69,3 +70,50 @@ def test_plain_server_matches(dev):
     b = serve.serve(trace, pool, budget_bytes=1 << 30, storage="f32", keep_masks=True)
     for ra, rb in zip(a.records, b.records):
         assert torch.equal(ra.mask, rb.mask)
+
+
+def _sample_trace(n=50, seed=11):
+    """The serving workload's job mix (1 or 4 bands, region or edge 50/50,
+    100-300 iterations, Poisson arrivals) with sides log-uniform in 256-512
+    so that the FP64 oracle can follow every job."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(0.002, size=n))
+    return [synth.Job(i, float(t[i]), int(round(np.exp(rng.uniform(np.log(256), np.log(512))))),
+                      1 if rng.random() < 0.5 else 4, "region" if rng.random() < 0.5 else "edge",
+                      int(rng.integers(100, 301))) for i in range(n)]
+
+
+def test_served_fp16_jobs_match_the_oracle_on_their_rounded_inputs(dev):
+    """A 50-job sample of the serving mix, served with FP16 storage, against
+    the FP64 oracle run on the same stored values (the image rounded to FP16
+    for the region term; the edge map rounded to FP16 for the edge term).
+    Over the sample at most 1e-4 of the pixels may differ in the final mask;
+    per job the disagreement, and how much the rounding itself moves the
+    oracle's own result (FP16-rounded against exact inputs), are printed."""
+    import oracle
+    from parity_helpers import round_storage
+    from paper_1409_7474_amd import serve
+    pool = serve.PoolInputs(synth.serving_pool(0, size=1024), dev)
+    trace = _sample_trace()
+    st = serve.serve(trace, pool, budget_bytes=2 << 30, storage="f16", chunk=16, keep_masks=True)
+    diff = px = 0
+    worst = (-1.0, -1)
+    moved = []
+    for rec, job in zip(st.records, sorted(trace, key=lambda j: j.job_id)):
+        img, init = pool(job)
+        x = img.cpu().double().numpy()
+        m0 = init.cpu().numpy()
+        if job.term == "region":
+            ref = oracle.run(round_storage(x, "f16"), m0, iters=job.iters, sigma=1.5, ts=11)
+        else:
+            g = oracle.edge_map(x, 1.0, 9, 255.0)
+            ref = oracle.run(None, m0, term="edge", iters=job.iters, sigma=1.5, ts=11, g=round_storage(g, "f16"))
+        d = int((rec.mask.cpu().numpy().astype(bool) != (ref.b > 0)).sum())
+        diff += d
+        px += job.side * job.side
+        worst = max(worst, (d / job.side ** 2, job.job_id))
+        if d:
+            moved.append((job.job_id, job.term, job.side, job.iters, d))
+    print(f"50 served FP16 jobs vs FP64 oracle on the rounded inputs: {diff} of {px} pixels differ "
+          f"({diff / px:.3g}); worst job {worst[1]} at {worst[0]:.3g}; jobs with differences: {moved}", flush=True)
+    assert diff / px <= 1e-4

@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="precision", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="run every kernel family in variant 0 instead of autotuning it on the job first")
     ap.add_argument("--job", default="all", choices=["all", "sequential", "concurrent", "dense"],
                     help="all: the timed sequential job (value), a timed concurrent pass, the fully active step "
                          "roofline and the counting replay; the others run one part only")
@@ -286,7 +288,8 @@ def _agreement(mask_a, mask_b, lsf_a, lsf_b):
 
 
 def section_batched(args):
-    """64 uneven images advanced together vs one after another."""
+    """64 uneven images advanced together vs one after another; with the
+    step-kernel variants fixed (variant 0) and autotuned per size class."""
     import numpy as np
     import torch
 
@@ -295,17 +298,17 @@ def section_batched(args):
     iters = 150
     shapes = synth.batch_shapes(0, n=args.batch_images)
     stream = torch.cuda.Stream(dev)
-    jobs = {}
+    masks, imgs = [], []
     with torch.cuda.stream(stream):
-        masks = []
-        imgs = []
         for i, (h, w) in enumerate(shapes):
             sc = synth.scene_batch_image(0, i, h, w)
             imgs.append(torch.tensor(sc.image, dtype=torch.float32, device=dev))
             masks.append(torch.tensor(sc.init_region, device=dev))
-        for st in ("f32", "f16"):
-            jobs[st] = [lse.LSE(im, m, sigma=1.0, ksize=7, storage=st, stream=stream) for im, m in zip(imgs, masks)]
     npx = sum(h * w for h, w in shapes)
+
+    def make(st):
+        with torch.cuda.stream(stream):
+            return [lse.LSE(im, m, sigma=1.0, ksize=7, storage=st, stream=stream) for im, m in zip(imgs, masks)]
 
     def reset(js):
         for j, m in zip(js, masks):
@@ -330,22 +333,49 @@ def section_batched(args):
     out = {"workload": f"{len(shapes)} images, sides U{{512..2048}} (non-square), 4 bands, region term, "
                        f"sigma 1.0 / 7x7, dt 15, {iters} iterations, {npx / 1e6:.1f} Mpx in total",
            "pixels": npx}
+    lse.lse_tuning_clear()
+    jobs = {st: make(st) for st in ("f32", "f16")}
     t_plain = timed(lambda: plain_all(jobs["f32"]), jobs["f32"])
     ref_masks = [j.mask().cpu().numpy() for j in jobs["f32"]]
     out["plain_f32"] = {"ms": round(t_plain * 1e3, 2), "value": round(npx * iters / t_plain / 1e6, 1)}
-    for st in ("f32", "f16"):
-        batch = lse.Batch(jobs[st], targets=[iters] * len(shapes), stream=stream)
+
+    def batched(st, js, key):
+        batch = lse.Batch(js, targets=[iters] * len(shapes), stream=stream)
         for graph in (False, True):
-            reset(jobs[st])
+            reset(js)
             batch.run(iters, graph=graph)  # warm-up (and graph capture)
-            t = timed(lambda: batch.run(iters, graph=graph), jobs[st])
-            key = f"batched_{st}" + ("_graph" if graph else "")
-            out[key] = {"ms": round(t * 1e3, 2), "value": round(npx * iters / t / 1e6, 1),
-                        "speedup_vs_plain_f32": round(t_plain / t, 3)}
-        masks_b = [j.mask().cpu().numpy() for j in jobs[st]]
-        dis = float(sum(np.sum(a != b) for a, b in zip(masks_b, ref_masks)) / npx)
-        out[f"batched_{st}"]["mask_disagreement_vs_plain_f32"] = dis
+            t = timed(lambda: batch.run(iters, graph=graph), js)
+            k = key + ("_graph" if graph else "")
+            out[k] = {"ms": round(t * 1e3, 2), "value": round(npx * iters / t / 1e6, 1),
+                      "speedup_vs_plain_f32": round(t_plain / t, 3)}
+        masks_b = [j.mask().cpu().numpy() for j in js]
+        out[key]["mask_disagreement_vs_plain_f32"] = float(
+            sum(np.sum(a != b) for a, b in zip(masks_b, ref_masks)) / npx)
         batch.close()
+
+    for st in ("f32", "f16"):
+        batched(st, jobs[st], f"batched_{st}")
+    # Autotuner: one representative image per size class (the median-area
+    # image of the class), 30 iterations per candidate variant, untimed; then
+    # new contexts pick the tuned variants up and the batch runs again.
+    classes = {}
+    for i, (h, w) in enumerate(shapes):
+        classes.setdefault(lse.lse_tuning_lookup(lse.make_params(h, w, 4, sigma=1.0, ksize=7)).size_class,
+                           []).append(i)
+    tuned = {}
+    for st in ("f32", "f16"):
+        for c, idx in sorted(classes.items()):
+            rep = sorted(idx, key=lambda i: shapes[i][0] * shapes[i][1])[len(idx) // 2]
+            tuned[f"{st}_class{c}"] = dict(lse.autotune(imgs[rep], masks[rep], iters=30, stream=stream, sigma=1.0,
+                                                        ksize=7, storage=st), image=list(shapes[rep]), images=len(idx))
+        for j in jobs[st]:
+            j.close()
+        jobs[st] = make(st)
+        batched(st, jobs[st], f"batched_{st}_tuned")
+        out[f"batched_{st}_tuned"]["speedup_vs_fixed_variant"] = round(
+            out[f"batched_{st}"]["ms"] / out[f"batched_{st}_tuned"]["ms"], 3)
+    out["tuning"] = tuned
+    lse.lse_tuning_clear()
     out["unit"] = "Mpixel-iter/s"
     return out
 
@@ -407,6 +437,20 @@ def section_serving(args):
     work = [j.side * j.side * j.iters for j in base]
     mean_work = sum(work) / len(work)
     budget = 200 << 30
+    # Autotune the step kernels of the served families (FP16 storage): one
+    # job per (term, bands, size class) of the trace, untimed.
+    from paper_1409_7474_amd import lse
+    lse.lse_tuning_clear()
+    tuned, seen = {}, set()
+    for j in base:
+        p = lse.make_params(j.side, j.side, j.bands, term=j.term, sigma=1.5, ksize=11, storage="f16")
+        key = (j.term, j.bands if j.term == "region" else 1, lse.lse_tuning_lookup(p).size_class)
+        if key in seen:
+            continue
+        seen.add(key)
+        img, init = pool(j)
+        tuned["%s_B%d_class%d" % key] = lse.autotune(img, init, iters=20, term=j.term, sigma=1.5, ksize=11,
+                                                      storage="f16")
     # Capacity: the first 300 jobs all present at t = 0 (saturated batching).
     probe = [dataclasses.replace(j, arrival_s=0.0) for j in base[:300]]
     serve.serve(probe[:20], pool, budget_bytes=budget, storage="f16")  # warm-up
@@ -438,6 +482,7 @@ def section_serving(args):
                         f"batched capacity, headline {head:.0%} ({head_qps:.1f} jobs/s)",
             "capacity": {"Mpixel_iter_per_s": round(cap_pxit / 1e6, 1),
                          "jobs_per_s": round(cap_pxit / mean_work, 2), "probe_jobs": len(probe)},
+            "tuning": tuned,
             "load_sweep_batched_f16_200GB": sweep,
             "batched_f16_200GB": sweep[f"{head:.0%}"], "plain_f32": plain.summary(),
             "batched_f16_2GB_first300": small.summary(),
@@ -548,8 +593,18 @@ def main():
                                   "other on one HIP stream",
                       "global_batch": 1, "parallelism": "single GPU"},
            "gpu": torch.cuda.get_device_name(0)}
-    kname_region = f"lse::step_fast_kernel<{ksize // 2}, {nb}, false, float>"
-    kname_edge = f"lse::step_fast_kernel<{ksize // 2}, 1, true, float>"
+    # Step-kernel variants: tuned once on this job (lse_autotune, untimed);
+    # every lse_init below picks the chosen variant from the library's table.
+    tuning = {}
+    if not args.no_tune:
+        for t in terms:
+            tuning[t] = lse.autotune(img, masks[t], iters=20, stream=streams[t], term=t, sigma=sigma, ksize=ksize)
+    else:
+        lse.lse_tuning_clear()
+    var = {t: lse.lse_tuning_lookup(params[t]).variant for t in terms}
+    out["tuning"] = tuning or {t: "not tuned: variant 0" for t in terms}
+    kname_region = f"lse::step_fast_kernel<{ksize // 2}, {nb}, false, float, {var.get('region', 0)}>"
+    kname_edge = f"lse::step_fast_kernel<{ksize // 2}, 1, true, float, {var.get('edge', 0)}>"
 
     if args.job in ("all", "sequential", "concurrent"):
         conc = args.job == "concurrent"

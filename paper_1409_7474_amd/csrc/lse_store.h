@@ -818,6 +818,26 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
             int flips = 0;
             constexpr int NBC = (G::UH + kSB - 1) / kSB;
+            // Per lane and chunk, fixed for the whole phase: the U column, its
+            // image column, whether it lies in U and in the image, its phi
+            // column, and the weights of the x difference (central inside,
+            // one-sided on the image's first and last column):
+            // gx = ar * phi(x+1) + al * phi(x-1) + ac * phi(x), each case
+            // rounding exactly as 0.5 (phi(x+1) - phi(x-1)), phi(1) - phi(0)
+            // or phi(W-1) - phi(W-2) does.
+            // (The phi column of U column xb = 32 - RU + 64 c + lane is
+            // 64 c + lane + 1; ac = -(ar + al).)
+            const int cx0 = x0 - G::RU + lane;
+            bool cok[2];
+            float ar[2], al[2];
+    #pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int x = cx0 + 64 * c;
+                cok[c] = 64 * c + lane < 96 + 2 * G::RU && x >= 0 && x < W;
+                const bool first = x == 0, last = x == W - 1;
+                ar[c] = first ? 1.f : (last ? 0.f : 0.5f);
+                al[c] = first ? 0.f : (last ? -1.f : -0.5f);
+            }
     #pragma unroll 1
             for (int bi = wave; bi < NBC; bi += kThreads / 64) {
                 const int u0 = bi * kSB;
@@ -875,42 +895,41 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                     int pixv[kCG][2];
     #pragma unroll
                     for (int i = 0; i < kCG; ++i) {
+                        // Row quantities are the same in every lane (scalar).
                         const int uy = u0 + r0 + i;
                         const int y = y0 - G::RU + uy;
                         const bool rowok = r0 + i < nr && y >= 0 && y < H;
+                        // Rows past U read phi row UH instead (in the array; the
+                        // results are masked).  The y difference like the x one.
+                        const float *prow = s_phi + (min(uy, G::UH - 1) + 1) * G::PS;
+                        const float dr = y == 0 ? 1.f : (y == H - 1 ? 0.f : 0.5f);
+                        const float ur = y == 0 ? 0.f : (y == H - 1 ? -1.f : -0.5f);
+                        const float cr0 = y == 0 ? -1.f : (y == H - 1 ? 1.f : 0.f);
+                        const int rowpix = y * W;
     #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            const int xb = 32 - G::RU + c * 64 + lane;
-                            const int x = x0 - 32 + xb;
-                            need[i][c] = false;
-                            pred[i][c] = false;
-                            phv[i][c] = 0.f;
-                            gmv[i][c] = 0.f;
-                            const bool ok = rowok && xb < 128 + G::RU && x >= 0 && x < W;
+                            const bool ok = rowok && cok[c];
                             if (EDGE && ucs[c] >= 0) {  // constant phi over this chunk's gradients
                                 phv[i][c] = 0.f;
                                 pred[i][c] = ok && ucs[c] == 1;
                                 need[i][c] = false;
                                 gmv[i][c] = 0.f;
                             } else {
-                                // All five values are read and the border case
-                                // (one-sided differences on the image's first and
-                                // last row and column) is a select: branches here
-                                // would wait for each read in turn.  Lanes outside
-                                // U read pixel (0, 32 - RU), inside phi.
-                                const int uyc = ok ? uy : 0, xbc = ok ? xb : 32 - G::RU;
-                                const int xc = x0 - 32 + xbc, yc = y0 - G::RU + uyc;
-                                const float *cc = s_phi + (uyc + 1) * G::PS + (xbc - 32 + G::RU + 1);
+                                // All five values are read (branch-free: lanes
+                                // outside U read phi inside the array) and the
+                                // image-border cases are weights, so the reads of
+                                // a group are in flight together.
+                                const float *cc = prow + 64 * c + lane + 1;
                                 const float c0 = cc[0], cl = cc[-1], cr = cc[1], cu = cc[-G::PS], cd = cc[G::PS];
-                                const float gxc = 0.5f * (cr - cl), gyc = 0.5f * (cd - cu);
-                                const float gx = xc == 0 ? cr - c0 : (xc == W - 1 ? c0 - cl : gxc);
-                                const float gy = yc == 0 ? cd - c0 : (yc == H - 1 ? c0 - cu : gyc);
-                                phv[i][c] = ok ? c0 : 0.f;
+                                const float gx = fmaf(ar[c], cr, fmaf(al[c], cl, -(ar[c] + al[c]) * c0));
+                                const float gy = fmaf(dr, cd, fmaf(ur, cu, cr0 * c0));
+                                const float g2 = gx * gx + gy * gy;
+                                phv[i][c] = c0;
                                 pred[i][c] = ok && c0 >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                                need[i][c] = ok && !(gx == 0.f && gy == 0.f);
-                                gmv[i][c] = sqrtf(gx * gx + gy * gy);
+                                need[i][c] = ok && g2 != 0.f;
+                                gmv[i][c] = sqrtf(g2);
                             }
-                            const int pix = y * W + x;
+                            const int pix = rowpix + cx0 + 64 * c;
                             pixv[i][c] = pix;
                             if constexpr (!EDGE)
                                 v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pix * PB : kNoLoad);

@@ -339,8 +339,8 @@ typedef struct {
  * for lse_init) and `iters` iterations per candidate, twice, the second run
  * timed with events on `stream` (synchronises it).  Checks that the
  * candidates end in the same binary state (LSE_ERR_STATE otherwise, never
- * expected), enters the fastest in the table for this family and size class,
- * and reports it in *out.  The workspace holds the last candidate's state
+ * expected), enters the fastest in the table for this family and size class
+ * (variant 0 unless another is more than 3 % faster), and reports it in *out.  The workspace holds the last candidate's state
  * afterwards (initialise again before use).  LSE_ERR_UNSUPPORTED for the
  * modes without variants (continuous LSF, TS outside 7..15). */
 lse_status lse_autotune(const lse_params *p, const void *image_dev, const uint8_t *init_mask_dev, void *workspace_dev,

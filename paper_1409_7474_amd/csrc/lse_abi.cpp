@@ -882,9 +882,11 @@ lse_status lse_autotune(const lse_params *p, const void *image_dev, const uint8_
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (r != LSE_OK) return r;
+    // Variant 0 stays unless another is faster by more than 3 % (run-to-run
+    // noise must not flip the choice).
     e.variant = 0;
     for (int var = 1; var < e.candidates; ++var)
-        if (e.ms[var] < e.ms[e.variant]) e.variant = var;
+        if (e.ms[var] < 0.97f * e.ms[0] && e.ms[var] < e.ms[e.variant]) e.variant = var;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune[tune_key(p)] = e;

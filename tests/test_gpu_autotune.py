@@ -98,7 +98,9 @@ def test_autotune_times_every_candidate_and_enters_the_fastest(dev):
         t = lse.autotune(img, torch.tensor(init, device=dev), iters=12, **kw)
         print(f"autotune {term} 1024^2: {t}", flush=True)
         assert t["candidates"] == 3 and all(m > 0 for m in t["ms"])
-        assert t["variant"] == int(np.argmin(t["ms"]))
+        ms = t["ms"]
+        faster = [v for v in (1, 2) if ms[v] < 0.97 * ms[0]]
+        assert t["variant"] == (min(faster, key=lambda v: ms[v]) if faster else 0)
         p = lse.make_params(1024, 1024, 4, **kw)
         assert lse.lse_tuning_lookup(p).as_dict() == t
         job = lse.LSE(img, torch.tensor(init, device=dev), **kw)

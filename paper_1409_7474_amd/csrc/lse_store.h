@@ -880,21 +880,24 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                     }
                     continue;
                 }
-                // Rows in groups of kCG: gradients first (LDS), then every data-term
+                constexpr int CG = NV >= 4 ? 2 : kCG;
+                // Rows in groups of CG (kCG; 2 for four bands, whose loaded values
+                // would otherwise exceed the register budget): gradients first
+                // (LDS), then every data-term
                 // load of the group, then the updates, so that one memory round
                 // trip serves the whole group.
     #pragma unroll 1
-                for (int r0 = 0; r0 < nr; r0 += kCG) {
-                    float phv[kCG][2], gmv[kCG][2];
-                    bool need[kCG][2], pred[kCG][2];
+                for (int r0 = 0; r0 < nr; r0 += CG) {
+                    float phv[CG][2], gmv[CG][2];
+                    bool need[CG][2], pred[CG][2];
                     // Data term of each pixel: the region term (B values per pixel) loads
                     // it as soon as the pixel's gradient is known (fewer live registers,
                     // earlier loads); the edge term loads the group afterwards (measured
                     // faster there).
-                    Px<NV> v[kCG][2];
-                    int pixv[kCG][2];
+                    Px<NV> v[CG][2];
+                    int pixv[CG][2];
     #pragma unroll
-                    for (int i = 0; i < kCG; ++i) {
+                    for (int i = 0; i < CG; ++i) {
                         // Row quantities are the same in every lane (scalar).
                         const int uy = u0 + r0 + i;
                         const int y = y0 - G::RU + uy;
@@ -937,15 +940,15 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                     }
                     if constexpr (EDGE) {
     #pragma unroll
-                        for (int i = 0; i < kCG; ++i)
+                        for (int i = 0; i < CG; ++i)
     #pragma unroll
                             for (int c = 0; c < 2; ++c)
                                 v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
                     }
-                    float coef[kCG][2];
+                    float coef[CG][2];
                     {
     #pragma unroll
-                        for (int i = 0; i < kCG; ++i)
+                        for (int i = 0; i < CG; ++i)
     #pragma unroll
                             for (int c = 0; c < 2; ++c) {
                                 if constexpr (EDGE)
@@ -955,7 +958,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                             }
                     }
     #pragma unroll
-                    for (int i = 0; i < kCG; ++i) {
+                    for (int i = 0; i < CG; ++i) {
                         if (r0 + i >= nr) break;
                         const int uy = u0 + r0 + i;
                         const int y = y0 - G::RU + uy;

@@ -15,16 +15,18 @@ step).  `--workload large` runs the 4096 x 4096 x 4 scene (sigma 1.5, 11 x 11,
   * concurrent -- the same job with each solve on its own HIP stream;
   * roofline -- the fused region step kernel on a fully active step (an 8 x 8
     checkerboard state: every tile heavy, every pixel needs its data term):
-    algorithmic HBM bytes per launch (image read once, binary state read and
-    written once) / the kernel's mean duration from HIP events carried by its
-    own dispatch packet, against the MI355X HBM peak of 8 TB/s;
+    algorithmic HBM bytes per launch (image read once, the stored LSF read and
+    written once as FP32: 24 B per pixel with 4 bands) / the kernel's mean
+    duration from HIP events carried by its own dispatch packet, against the
+    MI355X HBM peak of 8 TB/s (the binary LSF of this design needs 16.25 of
+    those bytes, stated beside it);
     roofline_edge -- the same for the edge step;
   * roofline_front_sparse -- the region step inside the timed job, on the
     bytes its launches needed (settled tiles are not visited);
   * per_iteration -- flips, visited / heavy tile fractions and needed-pixel
     fractions per iteration (untimed counting replay);
   * cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same job
-    (3 iterations of each term on the full image), on this host's cores;
+    (5 iterations of each term on the full image), on this host's cores;
   * batched -- 64 uneven images (sides 512-2048, 4 bands, sigma 1 / 7 x 7,
     150 iterations): one batched, graph-replayed launch sequence (FP32 and
     FP16 storage) against the 64 images run one after another (plain FP32);
@@ -54,7 +56,7 @@ METRIC = "LSE Mpixel-iter/s + % HBM peak, batched vs plain FP32; p50/p99 job lat
 
 WORKLOADS = {
     # name: (generator kwargs, sigma, ksize, iterations, terms, oracle iterations per term in the CPU sample)
-    "precision": (dict(size=8192), 2.0, 13, 300, ("region", "edge"), 3),
+    "precision": (dict(size=8192), 2.0, 13, 300, ("region", "edge"), 5),
     "large": (dict(size=4096), 1.5, 11, 200, ("region", "edge"), 12),
     "tiny": (dict(size=256), 1.0, 7, 100, ("region",), 100),
 }
@@ -683,9 +685,9 @@ def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_
     (loaded as the smoothed LSF of a binary function, Table I step 4), so
     every step tile is heavy and every pixel takes the data term.  Each timed
     step is the first after the load; its kernel time comes from the events
-    of its own dispatch.  Algorithmic bytes: the image (region: B x 4 B) or
-    edge map (4 B) read once, and the binary LSF state (1 bit read, 1 bit
-    written) per pixel."""
+    of its own dispatch.  Algorithmic bytes per pixel: the image (region:
+    B x 4 B) or edge map (4 B) read once, and the stored LSF read and written
+    once in FP32 (8 B)."""
     cb = torch.tensor(checkerboard(h, w), device=img.device)
     res = {}
     reps = max(args.steps, 3)
@@ -711,8 +713,13 @@ def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_
         lse.lse_destroy(ctx)
         del ws
         step_ms = p.step_ms / max(p.step_launches, 1)
+        # Algorithmic bytes per pixel and iteration as the measurement plan
+        # fixes them for this path: the image (region: B x 4 B) or edge map
+        # (4 B) read once, and the stored LSF read and written once (FP32,
+        # 2 x 4 B).  This design stores the LSF as its binary function, so it
+        # needs only 2 bits of that 8 B (bytes_needed_per_px).
         per_px = 4.0 * nb if t == "region" else 4.0
-        alg = per_px * h * w + 2.0 * h * w / 8.0
+        alg = (per_px + 8.0) * h * w
         ach = alg / (step_ms * 1e-3) / 1e9
         kname = kname_region if t == "region" else kname_edge
         traffic, src = measured_traffic(kname, "dense")
@@ -722,10 +729,13 @@ def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_
                                                     f"TS {params[t].ksize})",
              "mode": f"fully active step on {h}x{w}: 8x8 checkerboard state, every tile heavy",
              "mean_launch_us": round(step_ms * 1e3, 2), "launches_timed": int(p.step_launches),
-             "algorithmic_bytes_per_px": per_px + 0.25, "algorithmic_bytes_per_launch": int(alg),
-             "bytes_note": ("image bands read once (B x 4 B) + binary LSF state, 1 bit read and 1 bit written; an "
-                            "FP32 LSF plane (the plain design) would add 8 B/px" if t == "region" else
-                            "edge map g read once (4 B) + binary LSF state (2 bits)"),
+             "algorithmic_bytes_per_px": per_px + 8.0, "algorithmic_bytes_per_launch": int(alg),
+             "bytes_needed_per_px": per_px + 0.25,
+             "bytes_note": ("algorithmic: image bands read once (B x 4 B) + the stored LSF read and written once "
+                            "(FP32, 8 B); this design keeps the LSF as its binary function (1 bit read, 1 bit "
+                            "written), so a launch needs 16.25 B/px" if t == "region" else
+                            "algorithmic: edge map g read once (4 B) + the stored LSF read and written once (FP32, "
+                            "8 B); needed with the binary LSF: 4.25 B/px"),
              "needed_pixel_fraction": round(q.needed_pixels / max(q.counted_steps, 1) / (h * w), 4),
              "visited_tile_fraction": round(q.visited_tiles / max(q.counted_steps * q.tiles, 1), 4),
              "heavy_tile_fraction": round(q.heavy_tiles / max(q.counted_steps * q.tiles, 1), 4)}

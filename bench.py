@@ -149,7 +149,7 @@ def measured_traffic(kernel_name, job):
 _B = "python3 $R/bench.py --no-cpu-baseline --no-tune --sections ''"
 PROFILE_COMMANDS = [
     f"rocprofv3 --kernel-trace --stats -d OUT/trace_sequential -o run -- {_B} --steps 2 --warmup 1 --job sequential",
-    f"rocprofv3 --kernel-trace --stats -d OUT/trace_dense -o run -- {_B} --steps 5 --warmup 1 --job dense",
+    f"rocprofv3 --kernel-trace --stats -d OUT/trace_dense -o run -- {_B} --steps 20 --warmup 5 --job dense",
     f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --stats -d OUT/dense_FETCH_SIZE -o run -- {_B} --steps 3 "
     "--warmup 1 --job dense",
     f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --stats -d OUT/dense_WRITE_SIZE -o run -- {_B} --steps 3 "

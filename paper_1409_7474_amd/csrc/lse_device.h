@@ -79,6 +79,11 @@ __device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x
 // Totals of one statistics slot and of the image lines, reduced over the
 // kBins accumulation lines: wave 0 takes the slot (line i in lane i), wave 1
 // the image lines.  Called by every thread of the workgroup.
+// Index of this thread's wave in the workgroup, as a wave-uniform (scalar)
+// value: every lane of a wave64 has the same threadIdx.x >> 6, and saying so
+// lets per-wave row and segment arithmetic run on the scalar unit.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
 struct Totals {
     long long sum[4];
     unsigned long long nplus, flips, mkey;
@@ -771,7 +776,7 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
     using G = FastGeom<R, false>;
     static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");
     const int tid = (int)threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = wave_id();
     const int chunk = wave & 1, seg = wave >> 1;
     const int ox = chunk * 64 + lane;
     const int x = x0 + ox;

@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     DevState *st = A.st;
     const int sl = A.n % 3;
     const int H = A.H, W = A.W;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int ntx = (W + kFX - 1) / kFX;
     int x0 = 0, y0 = 0, by0 = 0, px0 = 0, py0 = 0;
     bool border = true;

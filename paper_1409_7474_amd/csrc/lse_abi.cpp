@@ -40,7 +40,6 @@ struct lse_ctx {
     float *boxes;       // region, B > 1: per-block band min / max for the normaliser
     uint32_t *bits[2];
     void *plane[2];     // dense: LSF planes (storage type), iteration n reads plane[n & 1]
-    float *tmp[2];
     Taps host_taps;
     hipStream_t last_stream;
     // profiling
@@ -159,8 +158,7 @@ lse_status validate(const lse_params *p) {
 }
 
 struct Layout {
-    size_t state, taps, args, img, boxes, tilesum, tilelast, sched, plan, bits0, bits1, plane0, plane1, tmp0, tmp1,
-        total;
+    size_t state, taps, args, img, boxes, tilesum, tilelast, sched, plan, bits0, bits1, plane0, plane1, total;
 };
 
 bool dense_mode(const lse_params *p) { return !(p->order == LSE_ORDER_TABLE1 && p->reinit_every == 1); }
@@ -211,14 +209,6 @@ Layout layout_of(const lse_params *p) {
         o = align_up(o + hw * es);
         L.plane1 = o;
         o = align_up(o + hw * es);
-    }
-    if (p->term == LSE_TERM_EDGE) {
-        L.tmp0 = o;
-        o = align_up(o + hw * 4);
-        L.tmp1 = o;
-        o = align_up(o + hw * 4);
-    } else {
-        L.tmp0 = L.tmp1 = 0;
     }
     L.total = o;
     return L;
@@ -516,8 +506,6 @@ hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, cons
     c->bits[1] = reinterpret_cast<uint32_t *>(base + L.bits1);
     c->plane[0] = L.plane0 ? base + L.plane0 : nullptr;
     c->plane[1] = L.plane1 ? base + L.plane1 : nullptr;
-    c->tmp[0] = L.tmp0 ? reinterpret_cast<float *>(base + L.tmp0) : nullptr;
-    c->tmp[1] = L.tmp1 ? reinterpret_cast<float *>(base + L.tmp1) : nullptr;
     c->prof = 0;
     c->prof_ms[0] = c->prof_ms[1] = 0.0;
     c->prof_n[0] = c->prof_n[1] = 0;
@@ -566,18 +554,15 @@ hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, cons
     if (e == hipSuccess) {
         if (c->region) {
             e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st, c->fix,
-                                  p->term == LSE_TERM_REGION ? 0 : 2, 0.f, st);
+                                  p->term == LSE_TERM_REGION ? 0 : 2, st);
             if (e == hipSuccess && c->NB > 1)
                 e = launch_mbox(c->img, p->height, p->width, c->NB, p->storage, c->boxes, st);
             if (e == hipSuccess && L.tilesum)
                 e = launch_tile_sums(c->dargs, c->host_args.tiles, c->r, c->NB, p->storage,
                                      reinterpret_cast<TileSum *>(base + L.tilesum), st);
         } else {
-            e = launch_init_image(image_dev, p->image_dtype, LSE_F32, p->bands, 1, c->tmp[1], c->hw, c->st, c->fix, 1,
-                                  p->edge_scale, st);
-            if (e == hipSuccess)
-                e = launch_edge_map(c->tmp[1], p->height, p->width, c->taps, c->r1, c->tmp[0], c->tmp[1], c->img,
-                                    p->storage, st);
+            e = launch_edge_map(image_dev, p->image_dtype, p->bands, p->edge_scale, c->taps, c->r1, c->img,
+                                p->height, p->width, p->storage, c->st, st);
         }
     }
     if (e == hipSuccess) e = launch_pack_mask(init_mask_dev, c->bits[0], p->height, p->width, c->WW, st);

@@ -173,8 +173,9 @@ constexpr int kPlanMinTiles = 4096;
 template <typename T>
 struct Store {
     static hipError_t init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
-                                 DevState *st, float fix, int mode, float gray_scale, hipStream_t s);
-    static hipError_t edge_g(const float *Is, void *g, int H, int W, hipStream_t s);
+                                 DevState *st, float fix, int mode, hipStream_t s);
+    static hipError_t edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
+                               int H, int W, DevState *st, hipStream_t s);
     static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
     static hipError_t step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
@@ -213,17 +214,19 @@ static_assert(sizeof(Taps) <= 4 * kPutWords && sizeof(ImgArgs) <= 4 * kPutWords,
 hipError_t launch_put_bytes(const void *host, size_t bytes, void *dst, hipStream_t s);
 hipError_t launch_init_state(DevState *st, int raw, hipStream_t s);
 hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s);
-// mode 0: bands; 1: band mean x gray_scale in FP32 (edge map input); 2: band
-// mean (intensity-only region term).
+// mode 0: bands; 2: band mean (intensity-only region term).
 hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
-                             DevState *st, float fix, int mode, float gray_scale, hipStream_t s);
+                             DevState *st, float fix, int mode, hipStream_t s);
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s);
 // Bits of sign(lsf) (lsf >= 0 -> 1), H x W float32.
 hipError_t launch_pack_sign(const float *lsf, uint32_t *bits, int H, int W, int WW, hipStream_t s);
 hipError_t launch_plane_load(const float *src, void *dst, long long n, DevState *st, int storage, hipStream_t s);
 hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slot, hipStream_t s);
-hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is,
-                           void *g, int storage, hipStream_t s);
+// Edge map g of eq. (14) from the caller's image (B bands of src_dtype), in
+// one launch: gray = scale x band mean, smoothed by the k1 taps, central-
+// difference gradient, g = 1 / (1 + |grad|^2) stored as `storage`.
+hipError_t launch_edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
+                           int H, int W, int storage, DevState *st, hipStream_t s);
 size_t mbox_floats(int H, int W, int NB);
 hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float *boxes, hipStream_t s);
 // Step / normaliser launches over ImgArgs: map == nullptr runs image args[0]

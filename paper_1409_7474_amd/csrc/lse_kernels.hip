@@ -68,60 +68,29 @@ __global__ void init_state_kernel(DevState *st, int keep_image_stats, int raw) {
 }
 
 // uint8 mask (nonzero = inside) -> bit words, bit i of word w = column 32 w + i.
+// Bit rows from a per-pixel predicate: one wave per 64 pixels of a row (two
+// bit words; coalesced reads), bit i of word w = column 32 w + i.
+template <typename P>
+__device__ __forceinline__ void pack_row_pair(P inside, uint32_t *__restrict__ bits, int H, int W, int WW) {
+    const int lane = threadIdx.x & 63;
+    const long long task = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // (row, word pair)
+    const int pairs = (WW + 1) >> 1;
+    if (task >= (long long)H * pairs) return;  // whole waves leave together
+    const int y = (int)(task / pairs), p = (int)(task - (long long)y * pairs);
+    const int x = 64 * p + lane;
+    const unsigned long long m = __ballot(x < W && inside((size_t)y * W + x));
+    if (lane < 2 && 2 * p + lane < WW) bits[(size_t)y * WW + 2 * p + lane] = (uint32_t)(m >> (32 * lane));
+}
+
+// uint8 mask (nonzero = inside) -> bit words.
 __global__ void pack_mask_kernel(const uint8_t *__restrict__ mask, uint32_t *__restrict__ bits, int H, int W,
                                  int WW) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * WW) return;
-    const int y = (int)(i / WW), w = (int)(i - (long long)y * WW);
-    uint32_t v = 0;
-    for (int b = 0; b < 32; ++b) {
-        const int x = w * 32 + b;
-        if (x < W && mask[(size_t)y * W + x]) v |= 1u << b;
-    }
-    bits[i] = v;
+    pack_row_pair([&](size_t i) { return mask[i] != 0; }, bits, H, W, WW);
 }
 
 // sign(lsf) -> bit words (lsf >= 0 -> 1, the tie rule of eq. (15)).
 __global__ void pack_sign_kernel(const float *__restrict__ lsf, uint32_t *__restrict__ bits, int H, int W, int WW) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * WW) return;
-    const int y = (int)(i / WW), w = (int)(i - (long long)y * WW);
-    uint32_t v = 0;
-    for (int b = 0; b < 32; ++b) {
-        const int x = w * 32 + b;
-        if (x < W && lsf[(size_t)y * W + x] >= 0.f) v |= 1u << b;
-    }
-    bits[i] = v;
-}
-
-// ------------------------------------------------------------ edge map init
-
-// out(y, x) = sum_j k[j] in(y, x + j - r)   (zero outside)
-__global__ void hconv_f32_kernel(const float *__restrict__ in, float *__restrict__ out, int H, int W,
-                                 const Taps *__restrict__ taps, int r) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * W) return;
-    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
-    float acc = 0.f;
-    for (int j = 0; j <= 2 * r; ++j) {
-        const int xx = x + j - r;
-        if (xx >= 0 && xx < W) acc = fmaf(taps->k1[j], in[(size_t)y * W + xx], acc);
-    }
-    out[i] = acc;
-}
-
-// out(y, x) = sum_j k[j] in(y + j - r, x)   (zero outside)
-__global__ void vconv_f32_kernel(const float *__restrict__ in, float *__restrict__ out, int H, int W,
-                                 const Taps *__restrict__ taps, int r) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * W) return;
-    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
-    float acc = 0.f;
-    for (int j = 0; j <= 2 * r; ++j) {
-        const int yy = y + j - r;
-        if (yy >= 0 && yy < H) acc = fmaf(taps->k1[j], in[(size_t)yy * W + x], acc);
-    }
-    out[i] = acc;
+    pack_row_pair([&](size_t i) { return lsf[i] >= 0.f; }, bits, H, W, WW);
 }
 
 // Per-block band min / max for the normaliser pruning (64 x 32 blocks).
@@ -502,25 +471,28 @@ hipError_t launch_reset_state(DevState *st, int raw, hipStream_t s) {
 }
 
 hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B, int NB, void *dst, long long npx,
-                             DevState *st, float fix, int mode, float gray_scale, hipStream_t s) {
-    if (mode == 1) return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, 1, gray_scale, s);
+                             DevState *st, float fix, int mode, hipStream_t s) {
     switch (storage) {
-        case LSE_F32: return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
-        case LSE_F16: return Store<__half>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, 0.f, s);
+        case LSE_F32: return Store<float>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, s);
+        case LSE_F16: return Store<__half>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::init_image(src, src_dtype, B, NB, dst, npx, st, fix, mode, s);
     }
     return hipErrorInvalidValue;
 }
 
+// Threads of the packing kernels: 64 per (row, word pair).
+static inline unsigned pack_blocks(int H, int WW) {
+    const long long threads = (long long)H * ((WW + 1) / 2) * 64;
+    return (unsigned)((threads + 255) / 256);
+}
+
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
-    const long long n = (long long)H * WW;
-    hipLaunchKernelGGL(pack_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mask, bits, H, W, WW);
+    hipLaunchKernelGGL(pack_mask_kernel, dim3(pack_blocks(H, WW)), dim3(256), 0, s, mask, bits, H, W, WW);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_sign(const float *lsf, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
-    const long long n = (long long)H * WW;
-    hipLaunchKernelGGL(pack_sign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lsf, bits, H, W, WW);
+    hipLaunchKernelGGL(pack_sign_kernel, dim3(pack_blocks(H, WW)), dim3(256), 0, s, lsf, bits, H, W, WW);
     return hipGetLastError();
 }
 
@@ -583,18 +555,12 @@ hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slo
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_edge_map(const float *gray, int H, int W, const Taps *taps, int r1, float *tmp, float *Is, void *g,
-                           int storage, hipStream_t s) {
-    const long long n = (long long)H * W;
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    hipLaunchKernelGGL(hconv_f32_kernel, grid, block, 0, s, gray, tmp, H, W, taps, r1);
-    hipLaunchKernelGGL(vconv_f32_kernel, grid, block, 0, s, tmp, Is, H, W, taps, r1);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
+                           int H, int W, int storage, DevState *st, hipStream_t s) {
     switch (storage) {
-        case LSE_F32: return Store<float>::edge_g(Is, g, H, W, s);
-        case LSE_F16: return Store<__half>::edge_g(Is, g, H, W, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::edge_g(Is, g, H, W, s);
+        case LSE_F32: return Store<float>::edge_map(src, src_dtype, B, scale, taps, r1, g, H, W, st, s);
+        case LSE_F16: return Store<__half>::edge_map(src, src_dtype, B, scale, taps, r1, g, H, W, st, s);
+        case LSE_BF16: return Store<__hip_bfloat16>::edge_map(src, src_dtype, B, scale, taps, r1, g, H, W, st, s);
     }
     return hipErrorInvalidValue;
 }

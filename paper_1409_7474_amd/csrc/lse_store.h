@@ -11,17 +11,15 @@ namespace lse {
 
 // Convert the caller's image (B bands of type T) to the resident copy of type
 // ST and check its values.  mode 0: the bands (NB >= B slots, extra ones
-// zero); mode 1: the band mean times gray_scale (input of the edge map);
-// mode 2: the band mean (intensity-only region term).  The per-band totals,
+// zero); mode 2: the band mean (intensity-only region term).  The per-band totals,
 // minima and maxima of the stored (rounded) values are reduced into the image
 // statistics lines, so that they describe exactly the image the iterations
 // read.
 template <typename T, typename ST>
 __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restrict__ src, int B, int NB,
                                                               ST *__restrict__ dst, long long npx,
-                                                              DevState *st, float fix, int mode,
-                                                              float gray_scale) {
-    const int nsv = mode == 0 ? B : (mode == 2 ? 1 : 0);  // statistics values per pixel
+                                                              DevState *st, float fix, int mode) {
+    const int nsv = mode == 0 ? B : 1;  // statistics values per pixel
     float sum[4] = {0.f, 0.f, 0.f, 0.f};
     float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -41,7 +39,6 @@ __global__ __launch_bounds__(kThreads) void init_image_kernel(const T *__restric
             for (int b = 0; b < 4; ++b)
                 if (b < B) g += v[b];
             g = g / (float)B;
-            if (mode == 1) g = gray_scale * g;
             const ST q = from_f32<ST>(g);
             dst[i] = q;
             v[0] = to_f32<ST>(q);
@@ -112,28 +109,87 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StepArgs A, int raw, in
     reduce_commit<NB>(s, acc, cnt, 0, &A.st->slot[slot][block_linear_id() % kBins], A.fix, true);
 }
 
-// g = 1 / (1 + |grad Is|^2), eq. (14), stored as ST; central differences
-// inside, one-sided at the border.
-template <typename ST>
-__global__ void edge_g_kernel(const float *__restrict__ Is, ST *__restrict__ g, int H, int W) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * W) return;
-    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
-    const float *row = Is + (size_t)y * W;
-    float gx, gy;
-    if (x == 0)
-        gx = row[1] - row[0];
-    else if (x == W - 1)
-        gx = row[W - 1] - row[W - 2];
-    else
-        gx = 0.5f * (row[x + 1] - row[x - 1]);
-    if (y == 0)
-        gy = Is[(size_t)W + x] - Is[x];
-    else if (y == H - 1)
-        gy = Is[(size_t)(H - 1) * W + x] - Is[(size_t)(H - 2) * W + x];
-    else
-        gy = 0.5f * (Is[(size_t)(y + 1) * W + x] - Is[(size_t)(y - 1) * W + x]);
-    g[i] = from_f32<ST>(1.f / (1.f + (gx * gx + gy * gy)));
+// Edge map of eq. (14) in one pass over an EMX x EMY output tile: the gray
+// value (band mean times the scale, as the listing's 8-bit intensity) on the
+// tile plus a (r1 + 1) halo, the image pre-smoothing G_sigma1 * gray as a
+// horizontal then a vertical FMA chain in tap order (taps outside the image
+// contribute nothing: zero padding), the central-difference gradient of the
+// smoothed image (one-sided on the image border), and g = 1 / (1 + |grad|^2)
+// rounded once to the storage type.  Every value is computed with the same
+// FP32 operations, in the same order, as separate whole-image passes would.
+constexpr int kEMX = 128, kEMY = 32;
+
+inline size_t edge_map_smem_bytes(int r1) {
+    const size_t gw = kEMX + 2 + 2 * r1, gh = kEMY + 2 + 2 * r1;
+    return (gh * gw + gh * (kEMX + 2) + (size_t)(kEMY + 2) * (kEMX + 2)) * 4;
+}
+
+template <typename T, typename ST>
+__global__ __launch_bounds__(kThreads) void edge_map_kernel(const T *__restrict__ src, int B, float scale,
+                                                            const Taps *__restrict__ taps, int r1,
+                                                            ST *__restrict__ g, int H, int W, DevState *st) {
+    extern __shared__ float smem[];
+    const int GW = kEMX + 2 + 2 * r1, GH = kEMY + 2 + 2 * r1, SW = kEMX + 2;
+    float *sg = smem;                 // gray, GH x GW, image origin (y0 - 1 - r1, x0 - 1 - r1)
+    float *sh = sg + GH * GW;         // horizontal sums, GH x SW, origin (y0 - 1 - r1, x0 - 1)
+    float *ss = sh + GH * SW;         // smoothed image, (kEMY + 2) x SW, origin (y0 - 1, x0 - 1)
+    const int x0 = blockIdx.x * kEMX, y0 = blockIdx.y * kEMY;
+    const int ts1 = 2 * r1 + 1;
+    int bad = 0;
+    for (int i = threadIdx.x; i < GH * GW; i += kThreads) {
+        const int r = i / GW, c = i - r * GW;
+        const int y = y0 - 1 - r1 + r, x = x0 - 1 - r1 + c;
+        float v = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            const T *px = src + ((size_t)y * W + x) * B;
+            float sum = 0.f;
+            for (int b = 0; b < B; ++b) {
+                const float f = to_f32<T>(px[b]);
+                if (!(fabsf(f) < 65536.f)) bad = 1;  // also catches NaN / Inf
+                sum += f;
+            }
+            v = scale * (sum / (float)B);
+        }
+        sg[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < GH * SW; i += kThreads) {
+        const int r = i / SW, c = i - r * SW;
+        const float *row = sg + r * GW + c;
+        float acc = 0.f;
+        for (int j = 0; j < ts1; ++j) acc = fmaf(taps->k1[j], row[j], acc);
+        sh[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (kEMY + 2) * SW; i += kThreads) {
+        const int r = i / SW, c = i - r * SW;
+        const float *col = sh + r * SW + c;
+        float acc = 0.f;
+        for (int j = 0; j < ts1; ++j) acc = fmaf(taps->k1[j], col[j * SW], acc);
+        ss[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kEMY * kEMX; i += kThreads) {
+        const int ty = i / kEMX, tx = i - ty * kEMX;
+        const int y = y0 + ty, x = x0 + tx;
+        if (y >= H || x >= W) continue;
+        const float *c0 = ss + (ty + 1) * SW + (tx + 1);
+        float gx, gy;
+        if (x == 0)
+            gx = c0[1] - c0[0];
+        else if (x == W - 1)
+            gx = c0[0] - c0[-1];
+        else
+            gx = 0.5f * (c0[1] - c0[-1]);
+        if (y == 0)
+            gy = c0[SW] - c0[0];
+        else if (y == H - 1)
+            gy = c0[0] - c0[-SW];
+        else
+            gy = 0.5f * (c0[SW] - c0[-SW]);
+        g[(size_t)y * W + x] = from_f32<ST>(1.f / (1.f + (gx * gx + gy * gy)));
+    }
+    if (bad) st->bad = 1;
 }
 
 // ------------------------------------------------------------ normaliser
@@ -1467,22 +1523,21 @@ static hipError_t launch_step_generic_t(const StepArgs &a, hipStream_t s) {
 
 template <typename ST>
 hipError_t Store<ST>::init_image(const void *src, int src_dtype, int B, int NB, void *dst, long long npx,
-                                 DevState *st, float fix, int mode, float gray_scale, hipStream_t s) {
+                                 DevState *st, float fix, int mode, hipStream_t s) {
     const dim3 grid(stream_blocks(npx, 4)), block(kThreads);
     ST *d = static_cast<ST *>(dst);
     switch (src_dtype) {
         case LSE_F32:
             hipLaunchKernelGGL((init_image_kernel<float, ST>), grid, block, 0, s, static_cast<const float *>(src), B,
-                               NB, d, npx, st, fix, mode, gray_scale);
+                               NB, d, npx, st, fix, mode);
             break;
         case LSE_F16:
             hipLaunchKernelGGL((init_image_kernel<__half, ST>), grid, block, 0, s, static_cast<const __half *>(src),
-                               B, NB, d, npx, st, fix, mode, gray_scale);
+                               B, NB, d, npx, st, fix, mode);
             break;
         case LSE_BF16:
             hipLaunchKernelGGL((init_image_kernel<__hip_bfloat16, ST>), grid, block, 0, s,
-                               static_cast<const __hip_bfloat16 *>(src), B, NB, d, npx, st, fix, mode,
-                               gray_scale);
+                               static_cast<const __hip_bfloat16 *>(src), B, NB, d, npx, st, fix, mode);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1491,11 +1546,33 @@ hipError_t Store<ST>::init_image(const void *src, int src_dtype, int B, int NB, 
 }
 
 template <typename ST>
-hipError_t Store<ST>::edge_g(const float *Is, void *g, int H, int W, hipStream_t s) {
-    const long long n = (long long)H * W;
-    hipLaunchKernelGGL((edge_g_kernel<ST>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Is,
-                       static_cast<ST *>(g), H, W);
-    return hipGetLastError();
+hipError_t Store<ST>::edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
+                               int H, int W, DevState *st, hipStream_t s) {
+    const dim3 grid((W + kEMX - 1) / kEMX, (H + kEMY - 1) / kEMY);
+    const size_t sm = edge_map_smem_bytes(r1);
+    ST *out = static_cast<ST *>(g);
+    hipError_t e = hipErrorInvalidValue;
+    switch (src_dtype) {
+        case LSE_F32:
+            e = ensure_lds(edge_map_kernel<float, ST>, sm);
+            if (e == hipSuccess)
+                hipLaunchKernelGGL((edge_map_kernel<float, ST>), grid, dim3(kThreads), sm, s,
+                                   static_cast<const float *>(src), B, scale, taps, r1, out, H, W, st);
+            break;
+        case LSE_F16:
+            e = ensure_lds(edge_map_kernel<__half, ST>, sm);
+            if (e == hipSuccess)
+                hipLaunchKernelGGL((edge_map_kernel<__half, ST>), grid, dim3(kThreads), sm, s,
+                                   static_cast<const __half *>(src), B, scale, taps, r1, out, H, W, st);
+            break;
+        case LSE_BF16:
+            e = ensure_lds(edge_map_kernel<__hip_bfloat16, ST>, sm);
+            if (e == hipSuccess)
+                hipLaunchKernelGGL((edge_map_kernel<__hip_bfloat16, ST>), grid, dim3(kThreads), sm, s,
+                                   static_cast<const __hip_bfloat16 *>(src), B, scale, taps, r1, out, H, W, st);
+            break;
+    }
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename ST>

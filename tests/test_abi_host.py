@@ -50,7 +50,8 @@ def test_workspace_bytes_scales_with_image():
     # image (16 B/px) + two bit planes (1/4 B/px) + fixed overhead
     assert 4096 * 4096 * 16 < big < 4096 * 4096 * 16.5 + 65536
     edge = lse.lse_workspace_bytes(lse.make_params(1000, 1000, 3, term="edge"))
-    assert 1000 * 1000 * 12 < edge < 1000 * 1000 * 12.5 + 65536
+    # edge map g (4 B/px) + two bit planes: the fused edge map needs no scratch planes
+    assert 1000 * 1000 * 4 < edge < 1000 * 1000 * 4.5 + 65536
 
 
 @pytest.mark.parametrize("field,value", [

@@ -551,7 +551,7 @@ __device__ __forceinline__ void reduce_commit(const TileSmem &s, float (&acc)[NB
 }
 
 
-constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 32;
+constexpr int kMBX = 64, kMBY = 32, kMBlocksPerWG = 64;  // one block per lane of wave 0
 
 // One thread of a step's lead workgroup: the image values of the pixel that
 // maximised |D| for this iteration (key `mkey`, from its statistics slot
@@ -1026,51 +1026,78 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
         h = record_word(hr, w) & vm;
         a = active_word(hr, ntx, w) & vm & ~h;
     };
-    int nh = 0, na = 0;
-    for (int i = 0; i < per; ++i) {
-        const int w = w0 + i;
-        if (w < nw) {
-            uint32_t h, a;
-            word_masks(w, h, a);
-            nh += __popc(h);
-            na += __popc(a);
-        }
-    }
-    // Exclusive scan over the workgroup: within the wave, then over waves.
-    int ih = nh, ia = na;
+    // List positions of this thread's first heavy and first other tile: an
+    // exclusive scan over the workgroup (within the wave, then over waves).
+    auto offsets = [&](int nh, int na, int &oh, int &oa) {
+        int ih = nh, ia = na;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int vh = __shfl_up(ih, d, 64), va = __shfl_up(ia, d, 64);
-        if (lane >= d) {
-            ih += vh;
-            ia += va;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int vh = __shfl_up(ih, d, 64), va = __shfl_up(ia, d, 64);
+            if (lane >= d) {
+                ih += vh;
+                ia += va;
+            }
+        }
+        if (lane == 63) {
+            s_tot[wave] = ih;
+            s_tot[NT / 64 + wave] = ia;
+        }
+        __syncthreads();
+        int bh = 0, ba = 0, NH = 0, NA = 0;
+        for (int v = 0; v < NT / 64; ++v) {
+            if (v < wave) {
+                bh += s_tot[v];
+                ba += s_tot[NT / 64 + v];
+            }
+            NH += s_tot[v];
+            NA += s_tot[NT / 64 + v];
+        }
+        oh = 1 + bh + ih - nh;
+        oa = 1 + NH + ba + ia - na;
+        if (tid == 0) E.plan[0] = NH + NA;
+    };
+    auto emit = [&](int w, uint32_t h, uint32_t a, int &oh, int &oa) {
+        for (; h; h &= h - 1u) E.plan[oh++] = 32 * w + (__ffs((int)h) - 1);
+        for (; a; a &= a - 1u) E.plan[oa++] = 32 * w + (__ffs((int)a) - 1);
+    };
+    constexpr int kKeep = 4;
+    int nh = 0, na = 0, oh, oa;
+    if (per <= kKeep) {
+        // One pass of record loads; the word masks stay in registers.
+        uint32_t hm[kKeep], am[kKeep];
+#pragma unroll
+        for (int i = 0; i < kKeep; ++i) {
+            hm[i] = am[i] = 0u;
+            if (i < per && w0 + i < nw) {
+                word_masks(w0 + i, hm[i], am[i]);
+                nh += __popc(hm[i]);
+                na += __popc(am[i]);
+            }
+        }
+        offsets(nh, na, oh, oa);
+#pragma unroll
+        for (int i = 0; i < kKeep; ++i) emit(w0 + i, hm[i], am[i], oh, oa);
+    } else {
+        // Many words per thread: count, then form the masks again to write.
+        for (int i = 0; i < per; ++i) {
+            const int w = w0 + i;
+            if (w < nw) {
+                uint32_t h, a;
+                word_masks(w, h, a);
+                nh += __popc(h);
+                na += __popc(a);
+            }
+        }
+        offsets(nh, na, oh, oa);
+        for (int i = 0; i < per; ++i) {
+            const int w = w0 + i;
+            if (w < nw) {
+                uint32_t h, a;
+                word_masks(w, h, a);
+                emit(w, h, a, oh, oa);
+            }
         }
     }
-    if (lane == 63) {
-        s_tot[wave] = ih;
-        s_tot[NT / 64 + wave] = ia;
-    }
-    __syncthreads();
-    int bh = 0, ba = 0, NH = 0, NA = 0;
-    for (int v = 0; v < NT / 64; ++v) {
-        if (v < wave) {
-            bh += s_tot[v];
-            ba += s_tot[NT / 64 + v];
-        }
-        NH += s_tot[v];
-        NA += s_tot[NT / 64 + v];
-    }
-    int oh = 1 + bh + ih - nh, oa = 1 + NH + ba + ia - na;
-    for (int i = 0; i < per; ++i) {
-        const int w = w0 + i;
-        if (w < nw) {
-            uint32_t h, a;
-            word_masks(w, h, a);
-            for (; h; h &= h - 1u) E.plan[oh++] = 32 * w + (__ffs((int)h) - 1);
-            for (; a; a &= a - 1u) E.plan[oa++] = 32 * w + (__ffs((int)a) - 1);
-        }
-    }
-    if (tid == 0) E.plan[0] = NH + NA;
 }
 
 // ---------------------------------------------------------------- launchers

@@ -176,6 +176,9 @@ struct Store {
                                  DevState *st, float fix, int mode, hipStream_t s);
     static hipError_t edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
                                int H, int W, DevState *st, hipStream_t s);
+    template <typename S>
+    static hipError_t edge_map_t(const S *src, int B, float scale, const Taps *taps, int r1, T *g, int H, int W,
+                                 DevState *st, hipStream_t s);
     static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
     static hipError_t step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,

@@ -67,30 +67,68 @@ __global__ void init_state_kernel(DevState *st, int keep_image_stats, int raw) {
     }
 }
 
-// uint8 mask (nonzero = inside) -> bit words, bit i of word w = column 32 w + i.
-// Bit rows from a per-pixel predicate: one wave per 64 pixels of a row (two
-// bit words; coalesced reads), bit i of word w = column 32 w + i.
-template <typename P>
-__device__ __forceinline__ void pack_row_pair(P inside, uint32_t *__restrict__ bits, int H, int W, int WW) {
-    const int lane = threadIdx.x & 63;
-    const long long task = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // (row, word pair)
-    const int pairs = (WW + 1) >> 1;
-    if (task >= (long long)H * pairs) return;  // whole waves leave together
-    const int y = (int)(task / pairs), p = (int)(task - (long long)y * pairs);
-    const int x = 64 * p + lane;
-    const unsigned long long m = __ballot(x < W && inside((size_t)y * W + x));
-    if (lane < 2 && 2 * p + lane < WW) bits[(size_t)y * WW + 2 * p + lane] = (uint32_t)(m >> (32 * lane));
+// Bit rows from a per-pixel predicate, one thread per 16-pixel segment (two
+// per bit word).  The thread forms its segment's 16 bits (one 16-byte read
+// when the segment is aligned and inside the row), and the even thread of a
+// pair writes the word with its partner's bits above its own.  Bit i of word
+// w is column 32 w + i; bits past the row end are zero.
+template <typename SEG>
+__device__ __forceinline__ void pack_segments(SEG seg, uint32_t *__restrict__ bits, int H, int W, int WW) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nseg = 2 * WW;
+    const bool live = g < (long long)H * nseg;  // H * nseg is even: pairs are live together
+    int y = 0, s = 0;
+    uint32_t m = 0u;
+    if (live) {
+        y = (int)(g / nseg);
+        s = (int)(g - (long long)y * nseg);
+        m = seg((size_t)y * W, 16 * s, W);
+    }
+    const uint32_t hi = __shfl_xor(m, 1, 64);
+    if (live && (s & 1) == 0) bits[(size_t)y * WW + (s >> 1)] = m | (hi << 16);
 }
 
 // uint8 mask (nonzero = inside) -> bit words.
 __global__ void pack_mask_kernel(const uint8_t *__restrict__ mask, uint32_t *__restrict__ bits, int H, int W,
                                  int WW) {
-    pack_row_pair([&](size_t i) { return mask[i] != 0; }, bits, H, W, WW);
+    pack_segments(
+        [&](size_t row, int x0, int w) {
+            const uint8_t *p = mask + row + x0;
+            uint32_t m = 0u;
+            if (x0 + 16 <= w && ((uintptr_t)p & 15u) == 0) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(p);
+                const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) m |= (((v[j] >> (8 * b)) & 0xFFu) != 0u ? 1u : 0u) << (4 * j + b);
+            } else {
+                for (int i = 0; i < 16 && x0 + i < w; ++i) m |= (p[i] != 0 ? 1u : 0u) << i;
+            }
+            return m;
+        },
+        bits, H, W, WW);
 }
 
 // sign(lsf) -> bit words (lsf >= 0 -> 1, the tie rule of eq. (15)).
 __global__ void pack_sign_kernel(const float *__restrict__ lsf, uint32_t *__restrict__ bits, int H, int W, int WW) {
-    pack_row_pair([&](size_t i) { return lsf[i] >= 0.f; }, bits, H, W, WW);
+    pack_segments(
+        [&](size_t row, int x0, int w) {
+            const float *p = lsf + row + x0;
+            uint32_t m = 0u;
+            if (x0 + 16 <= w && ((uintptr_t)p & 15u) == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 q = reinterpret_cast<const float4 *>(p)[j];
+                    m |= (q.x >= 0.f ? 1u : 0u) << (4 * j) | (q.y >= 0.f ? 1u : 0u) << (4 * j + 1) |
+                         (q.z >= 0.f ? 1u : 0u) << (4 * j + 2) | (q.w >= 0.f ? 1u : 0u) << (4 * j + 3);
+                }
+            } else {
+                for (int i = 0; i < 16 && x0 + i < w; ++i) m |= (p[i] >= 0.f ? 1u : 0u) << i;
+            }
+            return m;
+        },
+        bits, H, W, WW);
 }
 
 // Per-block band min / max for the normaliser pruning (64 x 32 blocks).
@@ -101,13 +139,29 @@ size_t mbox_floats(int H, int W, int NB) {
 
 // --------------------------------------------------------------- exports
 
+// Bits -> uint8 mask (1 inside), one thread per 16-pixel segment (one
+// 16-byte store when the segment is aligned and inside the row).
 __global__ void mask_out_kernel(const uint32_t *__restrict__ b0, const uint32_t *__restrict__ b1,
                                 const DevState *__restrict__ st, uint8_t *__restrict__ mask, int H, int W, int WW) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)H * W) return;
-    const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nseg = 2 * WW;
+    if (g >= (long long)H * nseg) return;
+    const int y = (int)(g / nseg), s = (int)(g - (long long)y * nseg);
+    const int x0 = 16 * s;
+    if (x0 >= W) return;
     const uint32_t *bits = (st->iters & 1) ? b1 : b0;
-    mask[i] = (bits[(size_t)y * WW + (x >> 5)] >> (x & 31)) & 1u;
+    const uint32_t m = bits[(size_t)y * WW + (s >> 1)] >> (16 * (s & 1));
+    uint8_t *p = mask + (size_t)y * W + x0;
+    if (x0 + 16 <= W && ((uintptr_t)p & 15u) == 0) {
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            v[j] = ((m >> (4 * j)) & 1u) | ((m >> (4 * j + 1)) & 1u) << 8 | ((m >> (4 * j + 2)) & 1u) << 16 |
+                   ((m >> (4 * j + 3)) & 1u) << 24;
+        *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        for (int i = 0; i < 16 && x0 + i < W; ++i) p[i] = (uint8_t)((m >> i) & 1u);
+    }
 }
 
 // phi = G * b (or b itself when raw) on 64 x 32 tiles, with the same
@@ -480,19 +534,19 @@ hipError_t launch_init_image(const void *src, int src_dtype, int storage, int B,
     return hipErrorInvalidValue;
 }
 
-// Threads of the packing kernels: 64 per (row, word pair).
-static inline unsigned pack_blocks(int H, int WW) {
-    const long long threads = (long long)H * ((WW + 1) / 2) * 64;
+// Workgroups of the segment kernels: one thread per 16 pixels of a row (two per bit word).
+static inline unsigned seg_blocks(int H, int WW) {
+    const long long threads = (long long)H * 2 * WW;
     return (unsigned)((threads + 255) / 256);
 }
 
 hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
-    hipLaunchKernelGGL(pack_mask_kernel, dim3(pack_blocks(H, WW)), dim3(256), 0, s, mask, bits, H, W, WW);
+    hipLaunchKernelGGL(pack_mask_kernel, dim3(seg_blocks(H, WW)), dim3(256), 0, s, mask, bits, H, W, WW);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_sign(const float *lsf, uint32_t *bits, int H, int W, int WW, hipStream_t s) {
-    hipLaunchKernelGGL(pack_sign_kernel, dim3(pack_blocks(H, WW)), dim3(256), 0, s, lsf, bits, H, W, WW);
+    hipLaunchKernelGGL(pack_sign_kernel, dim3(seg_blocks(H, WW)), dim3(256), 0, s, lsf, bits, H, W, WW);
     return hipGetLastError();
 }
 
@@ -687,9 +741,8 @@ hipError_t launch_batch_prepare(ImgArgs *args, int n, hipStream_t s) {
 
 hipError_t launch_mask_out(const uint32_t *const bits[2], const DevState *st, uint8_t *mask, int H, int W, int WW,
                            hipStream_t s) {
-    const long long n = (long long)H * W;
-    hipLaunchKernelGGL(mask_out_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bits[0], bits[1], st,
-                       mask, H, W, WW);
+    hipLaunchKernelGGL(mask_out_kernel, dim3(seg_blocks(H, WW)), dim3(256), 0, s, bits[0], bits[1], st, mask, H, W,
+                       WW);
     return hipGetLastError();
 }
 

@@ -117,77 +117,143 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StepArgs A, int raw, in
 // smoothed image (one-sided on the image border), and g = 1 / (1 + |grad|^2)
 // rounded once to the storage type.  Every value is computed with the same
 // FP32 operations, in the same order, as separate whole-image passes would.
+// Each wave takes whole rows (lane = column), so no index is divided.
 constexpr int kEMX = 128, kEMY = 32;
+constexpr int kMaxTaps1 = 31;  // 2 r1 + 1 <= 31
 
 inline size_t edge_map_smem_bytes(int r1) {
     const size_t gw = kEMX + 2 + 2 * r1, gh = kEMY + 2 + 2 * r1;
-    return (gh * gw + gh * (kEMX + 2) + (size_t)(kEMY + 2) * (kEMX + 2)) * 4;
+    return (gh * gw + gh * (kEMX + 2)) * 4;
 }
 
-template <typename T, typename ST>
+// The B band values of one pixel as FP32 (zeros past B); V4: four bands read
+// with one vector load (the caller checked the alignment).
+template <typename T, bool V4>
+__device__ __forceinline__ void load_bands(const T *__restrict__ px, int B, float v[4]) {
+    if constexpr (V4) {
+        T q[4];
+        if constexpr (sizeof(T) == 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(px);
+            __builtin_memcpy(q, &f, sizeof(q));
+        } else {
+            const uint2 u = *reinterpret_cast<const uint2 *>(px);
+            __builtin_memcpy(q, &u, sizeof(q));
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[b] = to_f32<T>(q[b]);
+    } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[b] = b < B ? to_f32<T>(px[b]) : 0.f;
+    }
+}
+
+template <typename T, typename ST, bool V4>
 __global__ __launch_bounds__(kThreads) void edge_map_kernel(const T *__restrict__ src, int B, float scale,
                                                             const Taps *__restrict__ taps, int r1,
                                                             ST *__restrict__ g, int H, int W, DevState *st) {
     extern __shared__ float smem[];
+    constexpr int NW = kThreads / 64;
     const int GW = kEMX + 2 + 2 * r1, GH = kEMY + 2 + 2 * r1, SW = kEMX + 2;
-    float *sg = smem;                 // gray, GH x GW, image origin (y0 - 1 - r1, x0 - 1 - r1)
-    float *sh = sg + GH * GW;         // horizontal sums, GH x SW, origin (y0 - 1 - r1, x0 - 1)
-    float *ss = sh + GH * SW;         // smoothed image, (kEMY + 2) x SW, origin (y0 - 1, x0 - 1)
+    // gray: GH x GW from image (y0 - 1 - r1, x0 - 1 - r1); later the smoothed
+    // image, (kEMY + 2) x SW from (y0 - 1, x0 - 1).  Horizontal sums: GH x SW
+    // from (y0 - 1 - r1, x0 - 1).
+    float *sg = smem, *sh = smem + GH * GW;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int x0 = blockIdx.x * kEMX, y0 = blockIdx.y * kEMY;
     const int ts1 = 2 * r1 + 1;
-    int bad = 0;
-    for (int i = threadIdx.x; i < GH * GW; i += kThreads) {
-        const int r = i / GW, c = i - r * GW;
-        const int y = y0 - 1 - r1 + r, x = x0 - 1 - r1 + c;
-        float v = 0.f;
-        if (y >= 0 && y < H && x >= 0 && x < W) {
-            const T *px = src + ((size_t)y * W + x) * B;
-            float sum = 0.f;
-            for (int b = 0; b < B; ++b) {
-                const float f = to_f32<T>(px[b]);
-                if (!(fabsf(f) < 65536.f)) bad = 1;  // also catches NaN / Inf
-                sum += f;
-            }
-            v = scale * (sum / (float)B);
+    float k1[kMaxTaps1];
+#pragma unroll
+    for (int j = 0; j < kMaxTaps1; ++j) k1[j] = taps->k1[j];
+    // FMA chain sum_j k1[j] p[j * stride] in tap order (unrolled: the taps
+    // stay in scalar registers; the uniform test ends it after ts1 taps).
+    auto chain = [&](const float *p, int stride) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < kMaxTaps1; ++j) {
+            if (j >= ts1) break;
+            acc = fmaf(k1[j], p[j * stride], acc);
         }
-        sg[i] = v;
+        return acc;
+    };
+    // Gray rows, four per wave at a time (twelve pixel loads in flight).
+    constexpr int RB = 4;
+    int bad = 0;
+    for (int r0 = wave; r0 < GH; r0 += RB * NW) {
+        float v[RB][3][4];
+        bool ok[RB][3];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = r0 + i * NW, y = y0 - 1 - r1 + r;
+            const bool rok = r < GH && y >= 0 && y < H;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {  // GW <= 160 < 3 x 64
+                const int c = lane + 64 * q, x = x0 - 1 - r1 + c;
+                ok[i][q] = rok && c < GW && x >= 0 && x < W;
+                if (ok[i][q])
+                    load_bands<T, V4>(src + ((size_t)y * W + x) * B, B, v[i][q]);
+                else
+                    v[i][q][0] = v[i][q][1] = v[i][q][2] = v[i][q][3] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = r0 + i * NW;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int c = lane + 64 * q;
+                float sum = 0.f;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (b < B) {
+                        if (!(fabsf(v[i][q][b]) < 65536.f)) bad = 1;  // also catches NaN / Inf
+                        sum += v[i][q][b];
+                    }
+                }
+                if (r < GH && c < GW) sg[r * GW + c] = ok[i][q] ? scale * (sum / (float)B) : 0.f;
+            }
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < GH * SW; i += kThreads) {
-        const int r = i / SW, c = i - r * SW;
-        const float *row = sg + r * GW + c;
-        float acc = 0.f;
-        for (int j = 0; j < ts1; ++j) acc = fmaf(taps->k1[j], row[j], acc);
-        sh[i] = acc;
+    for (int r = wave; r < GH; r += NW) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int c = lane + 64 * q;
+            if (c < SW) sh[r * SW + c] = chain(sg + r * GW + c, 1);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < (kEMY + 2) * SW; i += kThreads) {
-        const int r = i / SW, c = i - r * SW;
-        const float *col = sh + r * SW + c;
-        float acc = 0.f;
-        for (int j = 0; j < ts1; ++j) acc = fmaf(taps->k1[j], col[j * SW], acc);
-        ss[i] = acc;
+    float *ss = sg;
+    for (int r = wave; r < kEMY + 2; r += NW) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int c = lane + 64 * q;
+            if (c < SW) ss[r * SW + c] = chain(sh + r * SW + c, SW);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kEMY * kEMX; i += kThreads) {
-        const int ty = i / kEMX, tx = i - ty * kEMX;
-        const int y = y0 + ty, x = x0 + tx;
-        if (y >= H || x >= W) continue;
-        const float *c0 = ss + (ty + 1) * SW + (tx + 1);
-        float gx, gy;
-        if (x == 0)
-            gx = c0[1] - c0[0];
-        else if (x == W - 1)
-            gx = c0[0] - c0[-1];
-        else
-            gx = 0.5f * (c0[1] - c0[-1]);
-        if (y == 0)
-            gy = c0[SW] - c0[0];
-        else if (y == H - 1)
-            gy = c0[0] - c0[-SW];
-        else
-            gy = 0.5f * (c0[SW] - c0[-SW]);
-        g[(size_t)y * W + x] = from_f32<ST>(1.f / (1.f + (gx * gx + gy * gy)));
+    for (int ty = wave; ty < kEMY; ty += NW) {
+        const int y = y0 + ty;
+        if (y >= H) break;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int tx = lane + 64 * q, x = x0 + tx;
+            if (x >= W) continue;
+            const float *c0 = ss + (ty + 1) * SW + (tx + 1);
+            float gx, gy;
+            if (x == 0)
+                gx = c0[1] - c0[0];
+            else if (x == W - 1)
+                gx = c0[0] - c0[-1];
+            else
+                gx = 0.5f * (c0[1] - c0[-1]);
+            if (y == 0)
+                gy = c0[SW] - c0[0];
+            else if (y == H - 1)
+                gy = c0[0] - c0[-SW];
+            else
+                gy = 0.5f * (c0[SW] - c0[-SW]);
+            g[(size_t)y * W + x] = from_f32<ST>(1.f / (1.f + (gx * gx + gy * gy)));
+        }
     }
     if (bad) st->bad = 1;
 }
@@ -1546,33 +1612,36 @@ hipError_t Store<ST>::init_image(const void *src, int src_dtype, int B, int NB, 
 }
 
 template <typename ST>
-hipError_t Store<ST>::edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
-                               int H, int W, DevState *st, hipStream_t s) {
+template <typename T>
+hipError_t Store<ST>::edge_map_t(const T *src, int B, float scale, const Taps *taps, int r1, ST *g, int H, int W,
+                                 DevState *st, hipStream_t s) {
     const dim3 grid((W + kEMX - 1) / kEMX, (H + kEMY - 1) / kEMY);
     const size_t sm = edge_map_smem_bytes(r1);
-    ST *out = static_cast<ST *>(g);
-    hipError_t e = hipErrorInvalidValue;
-    switch (src_dtype) {
-        case LSE_F32:
-            e = ensure_lds(edge_map_kernel<float, ST>, sm);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL((edge_map_kernel<float, ST>), grid, dim3(kThreads), sm, s,
-                                   static_cast<const float *>(src), B, scale, taps, r1, out, H, W, st);
-            break;
-        case LSE_F16:
-            e = ensure_lds(edge_map_kernel<__half, ST>, sm);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL((edge_map_kernel<__half, ST>), grid, dim3(kThreads), sm, s,
-                                   static_cast<const __half *>(src), B, scale, taps, r1, out, H, W, st);
-            break;
-        case LSE_BF16:
-            e = ensure_lds(edge_map_kernel<__hip_bfloat16, ST>, sm);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL((edge_map_kernel<__hip_bfloat16, ST>), grid, dim3(kThreads), sm, s,
-                                   static_cast<const __hip_bfloat16 *>(src), B, scale, taps, r1, out, H, W, st);
-            break;
+    if (B == 4 && (reinterpret_cast<uintptr_t>(src) % (4 * sizeof(T))) == 0) {
+        const hipError_t e = ensure_lds(edge_map_kernel<T, ST, true>, sm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((edge_map_kernel<T, ST, true>), grid, dim3(kThreads), sm, s, src, B, scale, taps, r1, g, H,
+                           W, st);
+    } else {
+        const hipError_t e = ensure_lds(edge_map_kernel<T, ST, false>, sm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((edge_map_kernel<T, ST, false>), grid, dim3(kThreads), sm, s, src, B, scale, taps, r1, g,
+                           H, W, st);
     }
-    return e != hipSuccess ? e : hipGetLastError();
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
+                               int H, int W, DevState *st, hipStream_t s) {
+    ST *out = static_cast<ST *>(g);
+    switch (src_dtype) {
+        case LSE_F32: return edge_map_t(static_cast<const float *>(src), B, scale, taps, r1, out, H, W, st, s);
+        case LSE_F16: return edge_map_t(static_cast<const __half *>(src), B, scale, taps, r1, out, H, W, st, s);
+        case LSE_BF16:
+            return edge_map_t(static_cast<const __hip_bfloat16 *>(src), B, scale, taps, r1, out, H, W, st, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename ST>

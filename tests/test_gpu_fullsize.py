@@ -109,6 +109,29 @@ def test_edge_map_matches_oracle_elementwise(dev, shape, bands, storage):
     print(f"edge map {h}x{w} B={bands} {storage}: max rel err {rel.max():.3g} (bound {tol:.3g})", flush=True)
 
 
+@pytest.mark.parametrize("src,bands,sigma1,ts1", [
+    ("f16", 4, 1.0, 9), ("bf16", 4, 1.0, 9), ("f16", 2, 1.0, 9), ("f32", 3, 0.5, 3), ("f32", 4, 5.0, 31),
+])
+def test_edge_map_input_types_and_smoothing_radii(dev, src, bands, sigma1, ts1):
+    """The edge map of 16-bit input images (four bands: one vector load per
+    pixel; two bands: a load per band) and at the smallest and the largest
+    image-smoothing template, against the oracle's FP64 g of the same input
+    values, pixel by pixel."""
+    from paper_1409_7474_amd import lse
+    h, w = 150, 301
+    sc = synth.scene_multiband(7, size=w, bands=bands, n_roofs=10, n_roads=2, height=h, width=w)
+    dtype = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[src]
+    img = torch.tensor(np.asarray(sc.image, np.float32), device=dev).to(dtype)
+    job = lse.LSE(img, torch.tensor(sc.init_edge, dtype=torch.uint8, device=dev), term="edge", sigma=1.5,
+                  ksize=11, sigma_img=sigma1, ksize_img=ts1)
+    got = job.edge_map().cpu().double().numpy()
+    x64 = img.float().cpu().double().numpy()
+    ref = oracle.edge_map(x64, sigma1, ts1, 255.0)
+    rel = np.abs(got - ref) / ref
+    tol = _edge_tol(255.0 * float(x64.max()), ts1, "f32")
+    assert rel.max() <= tol, (rel.max(), tol)
+
+
 @pytest.mark.parametrize("name", ["large", "precision"])
 def test_edge_map_full_size(dev, scenes, name):
     sc = scenes(name)

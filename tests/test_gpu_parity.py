@@ -142,6 +142,42 @@ def test_initial_lsf_and_mask_roundtrip(dev):
     assert st["iters_done"] == 0 and st["n_plus"] == int(sc.init_region.sum())
 
 
+@pytest.mark.parametrize("w", [2, 15, 16, 17, 31, 33, 100, 129])
+@pytest.mark.parametrize("off", [0, 1, 5])
+def test_mask_packing_any_width_and_alignment(dev, w, off):
+    """Mask -> bits (lse_init), bits -> mask (lse_mask) and sign(lsf) -> bits
+    (lse_set_lsf) at widths around the 16-pixel segments and 32-pixel words
+    of the packing kernels, with every buffer at an element offset that
+    breaks 16-byte alignment (off > 0): nonzero bytes are inside, and
+    lsf >= 0 is inside (eq. (15)'s tie rule, -0.0 included)."""
+    h = 9
+    rng = np.random.default_rng(100 * w + off)
+    m = ((rng.random((h, w)) < 0.5) * rng.integers(1, 256, (h, w))).astype(np.uint8)
+    img = torch.tensor(rng.random((h, w, 1), dtype=np.float32), device=dev)
+
+    mbuf = torch.zeros(h * w + 64, dtype=torch.uint8, device=dev)
+    mview = mbuf[off:off + h * w].view(h, w)
+    mview.copy_(torch.tensor(m, device=dev))
+    from paper_1409_7474_amd import lse
+    job = lse.LSE(img, mview, reinit_every=2)  # the view itself: its pointer keeps the offset
+    obuf = torch.full((h * w + 64,), 7, dtype=torch.uint8, device=dev)
+    oview = obuf[off:off + h * w].view(h, w)
+    job.mask(out=oview)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(oview.cpu().numpy(), (m != 0).astype(np.uint8))
+    rest = torch.cat([obuf[:off], obuf[off + h * w:]]).cpu().numpy()
+    assert (rest == 7).all()  # nothing written outside the mask
+
+    lsf = rng.standard_normal((h, w)).astype(np.float32)
+    lsf[rng.random((h, w)) < 0.1] = 0.0
+    lsf[rng.random((h, w)) < 0.1] = -0.0
+    fbuf = torch.zeros(h * w + 64, dtype=torch.float32, device=dev)
+    fview = fbuf[off:off + h * w].view(h, w)
+    fview.copy_(torch.tensor(lsf, device=dev))
+    job.set_lsf(fview)
+    np.testing.assert_array_equal(job.mask().cpu().numpy(), (lsf >= 0).astype(np.uint8))
+
+
 def test_runs_are_bitwise_deterministic(dev):
     sc = synth.scene_multiband(6, size=256, bands=4, n_roofs=8, n_roads=2)
     img, _ = _as_gpu(sc.image, dev)

@@ -195,7 +195,7 @@ Layout layout_of(const lse_params *p) {
         // sized for every variant, so the workspace does not depend on the tuning
         const size_t tiles = (size_t)step_tiles_max(p->height, p->width, p->term == LSE_TERM_EDGE);
         L.sched = o;
-        o = align_up(o + 3 * ((tiles + 31) / 32) * 4);
+        o = align_up(o + 6 * ((tiles + 31) / 32) * 4);  // heavy and touched records, 3 slots each
         L.plan = o;
         o = align_up(o + (1 + tiles) * 4);
     }

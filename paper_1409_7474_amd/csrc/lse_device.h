@@ -914,51 +914,60 @@ __device__ __forceinline__ uint32_t record_word(Record rec, int w) {
     return w == wc ? v : 0u;
 }
 
-// Active tiles of word w of the heavy-tile record: a tile is
-// active when it or one of its eight neighbours (in a grid of ntx tiles per
-// row) was heavy.  The record bits at tile offsets dy * ntx + dx around the
-// word are read as funnel shifts of word pairs; all eighteen loads are
-// issued straight away (no branches), then combined.
-__device__ __forceinline__ uint32_t active_word(Record heavy, int ntx, int w) {
-    const int base = 32 * w;
-    uint32_t lo[9], hi[9];
+// The schedule keeps, per iteration slot (n % 3), two records of nw words:
+// the heavy tiles (words 0 .. nw - 1 of the slot's record) and the touched
+// tiles (words 3 nw + ...): tiles into whose bit window a heavy neighbour
+// flipped owned pixels.
+__device__ __forceinline__ Record heavy_record(const uint32_t *sched, int nw, int slot) {
+    return Record{sched + (size_t)slot * nw, nw};
+}
+__device__ __forceinline__ Record touched_record(const uint32_t *sched, int nw, int slot) {
+    return Record{sched + (size_t)(3 + slot) * nw, nw};
+}
+
+// Neighbours whose bit windows reach the flipped bits f of owned word j
+// (0..2, 32 columns each) of tile row ry, for a window halo of HWB pixels on
+// every side: bit 0 left, 1 right, 2 up, 3 down, 4 up-left, 5 up-right,
+// 6 down-left, 7 down-right.
+template <int FY, int HWB>
+__device__ __forceinline__ int flip_dirs(int ry, int j, uint32_t f) {
+    static_assert(HWB < 32 && HWB <= FY, "window halo exceeds a bit word or a tile");
+    if (f == 0u) return 0;
+    const bool up = ry < HWB, dn = ry >= FY - HWB;
+    const bool lf = j == 0 && (f & ((1u << HWB) - 1u)) != 0u;
+    const bool rt = j == 2 && (f >> (32 - HWB)) != 0u;
+    return (lf ? 1 : 0) | (rt ? 2 : 0) | (up ? 4 : 0) | (dn ? 8 : 0) | (lf && up ? 16 : 0) | (rt && up ? 32 : 0) |
+           (lf && dn ? 64 : 0) | (rt && dn ? 128 : 0);
+}
+
+// Mark the neighbours of tile t (grid ntx x nty) named by dirs in a touched record.
+__device__ __forceinline__ void mark_touched(uint32_t *rec, int t, int ntx, int nty, int dirs) {
+    const int tx = t % ntx, ty = t / ntx;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int wq = (base + (k / 3 - 1) * ntx + (k % 3 - 1)) >> 5;  // floor division (arithmetic shift)
-        lo[k] = record_word(heavy, wq);
-        hi[k] = record_word(heavy, wq + 1);
+    for (int d = 0; d < 8; ++d) {
+        if (!((dirs >> d) & 1)) continue;
+        const int x = tx + (d == 0 || d == 4 || d == 6 ? -1 : (d == 1 || d == 5 || d == 7 ? 1 : 0));
+        const int y = ty + (d == 2 || d == 4 || d == 5 ? -1 : (d == 3 || d == 6 || d == 7 ? 1 : 0));
+        if (x < 0 || x >= ntx || y < 0 || y >= nty) continue;
+        const int u = y * ntx + x;
+        atomicOr(&rec[u >> 5], 1u << (u & 31));
     }
-    // Tiles of this word in the first / last column of the tile grid.
-    uint32_t first_col = 0u, last_col = 0u;
-    const int c0 = base % ntx;
-    for (int i = (ntx - c0) % ntx; i < 32; i += ntx) first_col |= 1u << i;
-    for (int i = ntx - 1 - c0; i < 32; i += ntx) last_col |= 1u << i;
-    uint32_t a = 0u;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int sh = (base + (k / 3 - 1) * ntx + (k % 3 - 1)) & 31;
-        uint32_t v = sh == 0 ? lo[k] : (lo[k] >> sh) | (hi[k] << (32 - sh));
-        if (k % 3 == 0) v &= ~first_col;  // left neighbour: not for tiles in the first column
-        if (k % 3 == 2) v &= ~last_col;   // right neighbour: not for tiles in the last column
-        a |= v;
-    }
-    return a;
 }
 
 // Tile of workgroup j of a single-image launch without a visit list,
-// computed by one wave from the previous iteration's record of heavy tiles
-// (the order of build_plan: heavy tiles, then their other neighbours).
-// Returns -1 for j >= the number of active tiles.  Every workgroup scans the
-// whole record, so this serves small tile counts only (ntiles <=
-// kPlanMinTiles: two record words per lane, kept in registers).
-__device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ heavy, int ntiles, int ntx, int j) {
+// computed by one wave from the previous iteration's records (the order of
+// build_plan: heavy tiles, then the other touched tiles).  Returns -1 for
+// j >= the number of active tiles.  Every workgroup scans the whole records,
+// so this serves small tile counts only (ntiles <= kPlanMinTiles: two
+// record words per lane, kept in registers).
+__device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sched, int slot, int ntiles, int j) {
     const int lane = (int)threadIdx.x & 63;
     if (j >= ntiles) return -1;
     constexpr int kPer = kPlanMinTiles / 32 / 64;  // words per lane (the caller keeps ntiles <= kPlanMinTiles)
     const int nw = (ntiles + 31) >> 5;
     const int w0 = lane * kPer;
     uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
-    const Record hr{heavy, nw};
+    const Record hr = heavy_record(sched, nw, slot), tr = touched_record(sched, nw, slot);
     int nh = 0, na = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
@@ -966,7 +975,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
         const int valid = max(0, min(32, ntiles - 32 * w));  // 0 past the record
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         hw[i] = record_word(hr, w) & vm;
-        aw[i] = active_word(hr, ntx, w) & vm & ~hw[i];
+        aw[i] = record_word(tr, w) & vm & ~hw[i];
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
     }
@@ -1008,15 +1017,16 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ he
 
 // Visit list of the single-image step of iteration n: the tiles that
 // iteration n - 1 recorded as heavy (not quiet), in index order, then the
-// other tiles within one tile of a heavy one.  Every other tile is settled:
-// it and its neighbours were quiet, so its bit window is still uniform, both
-// bit buffers already hold its value and its region sums are unchanged.
-// All NT threads of one workgroup call it; thread i takes a contiguous run
-// of mask words.  s_tot: 2 x NT / 64 ints of LDS.
+// other tiles it recorded as touched (a heavy neighbour flipped pixels in
+// their bit window).  Every other tile is settled: it was quiet or settled
+// in n - 1 and no pixel of its window changed, so its window is still
+// uniform, both bit buffers already hold its value and its region sums are
+// unchanged.  All NT threads of one workgroup call it; thread i takes a
+// contiguous run of record words.  s_tot: 2 x NT / 64 ints of LDS.
 template <int NT>
 __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
-    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
-    const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
+    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5;
+    const Record hr = heavy_record(E.sched_mask, nw, n % 3), tr = touched_record(E.sched_mask, nw, n % 3);
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (nw + NT - 1) / NT;
     const int w0 = tid * per;
@@ -1024,7 +1034,7 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         h = record_word(hr, w) & vm;
-        a = active_word(hr, ntx, w) & vm & ~h;
+        a = record_word(tr, w) & vm & ~h;
     };
     // List positions of this thread's first heavy and first other tile: an
     // exclusive scan over the workgroup (within the wave, then over waves).

@@ -340,9 +340,11 @@ __global__ void reset_profile_kernel(DevState *st) {
 // tiles in order).
 // Schedule record for a restart at iteration 0: every tile counts as heavy
 // in slot 0 (so every tile is visited), the other slots clear.
+// Restart: every tile heavy in the record that the next step reads (slot 0),
+// the other heavy records and all touched records empty.
 __global__ void sched_reset_kernel(uint32_t *mask, int nw, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3 * nw) return;
+    if (i >= 6 * nw) return;
     uint32_t v = 0u;
     if (i < nw) {
         const int valid = ntiles - 32 * i;
@@ -354,7 +356,7 @@ __global__ void sched_reset_kernel(uint32_t *mask, int nw, int ntiles) {
 hipError_t launch_sched_reset(const ImgArgs *a, hipStream_t s) {
     if (!a->sched_mask) return hipSuccess;
     const int nw = (a->tiles + 31) >> 5;
-    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((3 * nw + 255) / 256)), dim3(256), 0, s, a->sched_mask,
+    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((6 * nw + 255) / 256)), dim3(256), 0, s, a->sched_mask,
                        nw, a->tiles);
     return hipGetLastError();
 }
@@ -399,9 +401,8 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const ImgArgs 
         const int nw = (E.tiles + 31) >> 5, w = g - (int)s_wb[img];
         const int valid = min(32, E.tiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
-        h = record_word(hr, w) & vm;
-        a = active_word(hr, (E.W + kFX - 1) / kFX, w) & vm & ~h;
+        h = record_word(heavy_record(E.sched_mask, nw, n % 3), w) & vm;
+        a = record_word(touched_record(E.sched_mask, nw, n % 3), w) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {
@@ -460,20 +461,20 @@ hipError_t launch_batch_plan(const ImgArgs *args, const uint32_t *wbase, int nim
 }
 
 // Profiling: step n = n0 + k visited the tiles that iteration n - 1 recorded
-// as heavy (record n % 3) and their neighbours, and recorded its own heavy
-// tiles in record (n + 1) % 3; both records are intact until step n + 1.
+// as heavy or touched (records of slot n % 3), and recorded its own heavy
+// tiles in slot (n + 1) % 3; both slots are intact until step n + 1.
 __global__ __launch_bounds__(kPlanThreads) void count_tiles_kernel(const ImgArgs *__restrict__ args, int k) {
     const ImgArgs &E = args[0];
     const int n = E.n0 + k;
-    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5, ntx = (E.W + kFX - 1) / kFX;
-    const Record hr{E.sched_mask + (size_t)(n % 3) * nw, nw};
-    const uint32_t *next = E.sched_mask + (size_t)((n + 1) % 3) * nw;
+    const int ntiles = E.tiles, nw = (ntiles + 31) >> 5;
+    const Record hr = heavy_record(E.sched_mask, nw, n % 3), tr = touched_record(E.sched_mask, nw, n % 3);
+    const Record next = heavy_record(E.sched_mask, nw, (n + 1) % 3);
     unsigned long long vis = 0, heavy = 0;
     for (int w = threadIdx.x; w < nw; w += blockDim.x) {
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        vis += __popc(active_word(hr, ntx, w) & vm);
-        heavy += __popc(next[w] & vm);
+        vis += __popc((record_word(hr, w) | record_word(tr, w)) & vm);
+        heavy += __popc(record_word(next, w) & vm);
     }
     if (vis) atomicAdd(&E.st->acc_visited, vis);
     if (heavy) atomicAdd(&E.st->acc_heavy, heavy);

@@ -647,6 +647,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     __shared__ Totals tot;
     __shared__ float red[kThreads / 64 * 8];
     __shared__ int s_tile;
+    __shared__ int s_dirs;             // neighbours whose bit windows this step's flips reach (flip_dirs)
     __shared__ TileSum s_prev, s_all;  // region: the tile's latest contribution; its all-inside sums
     int ii, t;
     if (nmap && (int)blockIdx.x >= *nmap) return;  // past the end of a batch visit list
@@ -676,8 +677,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                 s_tile = (int)blockIdx.x < cnt ? tt : -1;
             }
         } else if ((threadIdx.x >> 6) == 0) {
-            const int tt = active_first_tile(E.sched_mask + (size_t)(n % 3) * nw, E.tiles, (E.W + kFX - 1) / kFX,
-                                             (int)blockIdx.x);
+            const int tt = active_first_tile(E.sched_mask, n % 3, E.tiles, (int)blockIdx.x);
             if (threadIdx.x == 0) s_tile = tt;
         }
         __syncthreads();
@@ -735,6 +735,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     }
     stage_bits_fast<G::BH>(s_bits, A.bits_in, by0, x0, H, A.WW);
     if (tid < 16) s_const[tid] = tid < 8 ? ~0u : 0u;
+    if (tid == 0) s_dirs = 0;
     if (!EDGE && tid < 8) {
         reinterpret_cast<long long *>(&s_prev)[tid] = rec_w;
         reinterpret_cast<long long *>(&s_all)[tid] = all_w;
@@ -837,8 +838,8 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             all0 = __syncthreads_and(all0);
             quiet = all1 ? 1 : (all0 ? 0 : -1);
         }
-        // Record heavy tiles: the next iteration visits them and their
-        // neighbours (whose bit windows reach their pixels).
+        // Record heavy tiles: the next iteration visits them (and those of
+        // their neighbours whose bit windows their flips reach: mark_touched).
         if (tid == 0 && quiet < 0 && E.sched_mask)
             atomicOr(&E.sched_mask[(size_t)sbn * nw + (t >> 5)], 1u << (t & 31));
         if (quiet >= 0) {
@@ -939,6 +940,11 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             // of 8 rows per wave task; blocks whose phi rows are one uniform
             // constant (interior tiles) have |grad phi| = 0: b = sign(phi).
             int flips = 0;
+            // Owned flips near the tile's sides, by the neighbours whose bit
+            // windows (the staged rows and columns of the quiet test: RU + R + 1
+            // pixels beyond the tile, one more on the right) they reach.
+            int dirs = 0;
+            constexpr int HWB = G::RU + R + 2;
             constexpr int NBC = (G::UH + kSB - 1) / kSB;
             // Per lane and chunk, fixed for the whole phase: the U column, its
             // image column, whether it lies in U and in the image, its phi
@@ -998,6 +1004,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                             const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + k] & valid;
                             A.bits_out[(size_t)y * A.WW + gw] = nw;
                             flips += __popc(nw ^ ow);
+                            dirs |= flip_dirs<G::FY, HWB>(uy - G::RU, k - 1, nw ^ ow);
                         }
                     }
                     continue;
@@ -1106,11 +1113,13 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                                 const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
                                 A.bits_out[(size_t)y * A.WW + gw] = nw;
                                 flips += __popc(nw ^ ow);
+                                dirs |= flip_dirs<G::FY, HWB>(uy - G::RU, lane - 1, nw ^ ow);
                             }
                         }
                     }
                 }
             }
+            if (dirs) atomicOr(&s_dirs, dirs);
             __syncthreads();
 
             float acc[NB];
@@ -1128,15 +1137,22 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             rs.red = red;
             reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[sbn][blockIdx.x % kBins], A.fix, !EDGE,
                               track ? &s_prev : nullptr, track ? &E.tilelast[t] : nullptr);
+            // Touched neighbours: the next iteration visits them (last, so
+            // that no barrier waits for these atomics).
+            if (tid == 0 && s_dirs && E.sched_mask)
+                mark_touched(E.sched_mask + (size_t)(3 + sbn) * nw, t, ntx, E.tiles / ntx, s_dirs);
         }
     }
     if (lead_block) {
-        // Clear the slot of iteration n + 2 and the schedule mask that
-        // iteration n + 1 will fill (nobody reads or writes them now).
+        // Clear the slot of iteration n + 2 (statistics, heavy and touched
+        // records) that iteration n + 1 will fill (nobody reads or writes it now).
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
         if (E.sched_mask)
-            for (int i = threadIdx.x; i < nw; i += kThreads) E.sched_mask[(size_t)sbr * nw + i] = 0u;
+            for (int i = threadIdx.x; i < nw; i += kThreads) {
+                E.sched_mask[(size_t)sbr * nw + i] = 0u;
+                E.sched_mask[(size_t)(3 + sbr) * nw + i] = 0u;
+            }
     }
     if constexpr (!EDGE && NB > 1)
         if (lead) record_max_pixel<NB, ST>(st, sl, tot.mkey, A.img, A.hw);

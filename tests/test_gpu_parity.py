@@ -327,22 +327,34 @@ def _heavy_tiles(bits_prev, r, edge):
     return heavy
 
 
-def _dilate_tiles(t):
-    out = t.copy()
-    nty, ntx = t.shape
-    for dy in (-1, 0, 1):
-        for dx in (-1, 0, 1):
-            src = t[max(0, -dy):nty - max(0, dy), max(0, -dx):ntx - max(0, dx)]
-            out[max(0, dy):nty - max(0, -dy), max(0, dx):ntx - max(0, -dx)] |= src
+def _touched_tiles(prev, cur, r, edge):
+    """Tiles whose bit window (the rows and columns _heavy_tiles reads: RU +
+    r + 1 pixels beyond the tile, one more on the right) holds a pixel that
+    flipped from prev to cur; the kernel marks them from each flipping tile's
+    own pixels within RU + r + 2 of its sides, a superset of those windows."""
+    h, w = prev.shape
+    fy, ru = (64, 0) if edge else (48, r)
+    hw = ru + r + 2
+    nty, ntx = -(-h // fy), -(-w // 96)
+    out = np.zeros((nty, ntx), bool)
+    for y, x in zip(*np.nonzero(prev != cur)):
+        ty, tx, ry, rx = y // fy, x // 96, y % fy, x % 96
+        dys = [0] + ([-1] if ry < hw else []) + ([1] if ry >= fy - hw else [])
+        dxs = [0] + ([-1] if rx < hw else []) + ([1] if rx >= 96 - hw else [])
+        for dy in dys:
+            for dx in dxs:
+                if (dy or dx) and 0 <= ty + dy < nty and 0 <= tx + dx < ntx:
+                    out[ty + dy, tx + dx] = True
     return out
 
 
 @pytest.mark.parametrize("term", ["region", "edge"])
 def test_profile_counts_visited_and_heavy_tiles(dev, term):
     """Profiling counts of the front-sparse schedule: the tiles a step visits
-    are the heavy tiles of the previous iteration and their neighbours (all
-    tiles right after a restart), and its heavy tiles are those whose bit
-    window is not uniform; both recomputed here from the exported masks."""
+    are the heavy tiles of the previous iteration and the neighbours whose
+    bit windows that iteration's flips reached (all tiles right after a
+    restart), and its heavy tiles are those whose bit window is not uniform;
+    both recomputed here from the exported masks."""
     from paper_1409_7474_amd import lse
     sc = synth.scene_multiband(4, size=1400, bands=4, n_roofs=12, n_roads=1, height=1100, width=1400)
     img, _ = _as_gpu(sc.image, dev)
@@ -356,15 +368,21 @@ def test_profile_counts_visited_and_heavy_tiles(dev, term):
     job.step()
     masks.append(job.mask().cpu().numpy().astype(bool))
     job.profile(lse.PROFILE_COUNT)
-    want_vis = want_heavy = 0
+    want_vis = want_heavy = touched_only = 0
     for _ in range(4):
-        want_vis += int(_dilate_tiles(_heavy_tiles(masks[-2], r, term == "edge")).sum())
+        heavy_prev = _heavy_tiles(masks[-2], r, term == "edge")
+        touched = _touched_tiles(masks[-2], masks[-1], r, term == "edge")
+        want_vis += int((heavy_prev | touched).sum())
+        touched_only += int((touched & ~heavy_prev).sum())
         want_heavy += int(_heavy_tiles(masks[-1], r, term == "edge").sum())
         job.step()
         masks.append(job.mask().cpu().numpy().astype(bool))
     p = job.profile_read()
+    print(f"{term}: visited {want_vis}, heavy {want_heavy}, touched only {touched_only}, tiles {p['tiles']}", flush=True)
     assert (p["visited_tiles"], p["heavy_tiles"]) == (want_vis, want_heavy), (p, want_vis, want_heavy)
-    assert want_heavy < want_vis < 4 * p["tiles"]  # the schedule skips settled tiles here
+    assert 0 < want_vis < 4 * p["tiles"]  # the schedule skips settled tiles here
+    if term == "edge":
+        assert touched_only > 0  # the edge front moves across tile sides: touched tiles are exercised
     job.close()
 
 

@@ -195,7 +195,7 @@ Layout layout_of(const lse_params *p) {
         // sized for every variant, so the workspace does not depend on the tuning
         const size_t tiles = (size_t)step_tiles_max(p->height, p->width, p->term == LSE_TERM_EDGE);
         L.sched = o;
-        o = align_up(o + 6 * ((tiles + 31) / 32) * 4);  // heavy and touched records, 3 slots each
+        o = align_up(o + (size_t)sched_words((int)((tiles + 31) / 32)) * 4);  // heavy records (3 slots), touched tags
         L.plan = o;
         o = align_up(o + (1 + tiles) * 4);
     }
@@ -381,6 +381,8 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
         next_binary = a.order == LSE_ORDER_LISTING && a.reinit;
     } else if (fast_radius(c->r)) {
         if (c->host_args.plan && !(region && c->NB > 1)) e = launch_plan(c->dargs, c->n, s);
+        if (e == hipSuccess && (c->prof & LSE_PROFILE_COUNT) && c->host_args.sched_mask)
+            e = launch_count_tiles(c->dargs, c->n, 0, s);
         if (e == hipSuccess)
             e = launch_step(c->dargs, nullptr, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r,
                             c->NB, region ? 0 : 1, storage, c->variant, s);
@@ -393,7 +395,7 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
     if ((c->prof & LSE_PROFILE_COUNT) && !c->dense) {
         if (launch_count_needed(a, a.raw, region ? 0 : 1, c->host_args.tilesum != nullptr, s) != hipSuccess)
             return LSE_ERR_DEVICE;
-        if (c->host_args.sched_mask && fast_radius(c->r) && launch_count_tiles(c->dargs, c->n, s) != hipSuccess)
+        if (c->host_args.sched_mask && fast_radius(c->r) && launch_count_tiles(c->dargs, c->n, 1, s) != hipSuccess)
             return LSE_ERR_DEVICE;
     }
     c->n += 1;

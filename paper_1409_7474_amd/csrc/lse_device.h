@@ -914,15 +914,29 @@ __device__ __forceinline__ uint32_t record_word(Record rec, int w) {
     return w == wc ? v : 0u;
 }
 
-// The schedule keeps, per iteration slot (n % 3), two records of nw words:
-// the heavy tiles (words 0 .. nw - 1 of the slot's record) and the touched
-// tiles (words 3 nw + ...): tiles into whose bit window a heavy neighbour
-// flipped owned pixels.
+// The schedule keeps three records of heavy tiles (iteration slots n % 3,
+// nw words each), then, from word sched_tag_offset(nw) (16-byte aligned),
+// one tag byte per tile (8 nw words): a tile is touched
+// for step n + 1 when its byte holds touch_tag(n), written by a neighbour
+// that flipped pixels inside its bit window in step n.  A byte left from an
+// iteration 128 k earlier can match again; that only adds a visit.
 __device__ __forceinline__ Record heavy_record(const uint32_t *sched, int nw, int slot) {
     return Record{sched + (size_t)slot * nw, nw};
 }
-__device__ __forceinline__ Record touched_record(const uint32_t *sched, int nw, int slot) {
-    return Record{sched + (size_t)(3 + slot) * nw, nw};
+__device__ __forceinline__ uint32_t touch_tag(int n) { return 0x80u | ((uint32_t)n & 0x7Fu); }
+
+// Touched tiles of record word w (tiles 32 w .. 32 w + 31) for step n + 1
+// (tag = touch_tag(n)); w is clamped into the record (callers mask the result).
+__device__ __forceinline__ uint32_t touched_word(const uint32_t *sched, int nw, int w, uint32_t tag) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(sched + sched_tag_offset(nw)) + 2 * min(max(w, 0), nw - 1);
+    const uint4 q0 = p[0], q1 = p[1];
+    const uint32_t v[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    uint32_t m = 0u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) m |= (((v[i] >> (8 * b)) & 0xFFu) == tag ? 1u : 0u) << (4 * i + b);
+    return m;
 }
 
 // Neighbours whose bit windows reach the flipped bits f of owned word j
@@ -940,8 +954,10 @@ __device__ __forceinline__ int flip_dirs(int ry, int j, uint32_t f) {
            (lf && dn ? 64 : 0) | (rt && dn ? 128 : 0);
 }
 
-// Mark the neighbours of tile t (grid ntx x nty) named by dirs in a touched record.
-__device__ __forceinline__ void mark_touched(uint32_t *rec, int t, int ntx, int nty, int dirs) {
+// Tag the neighbours of tile t (grid ntx x nty) named by dirs as touched
+// (plain byte stores: no atomics, each byte is one tile's).
+__device__ __forceinline__ void mark_touched(uint32_t *sched, int nw, int t, int ntx, int nty, int dirs, uint32_t tag) {
+    uint8_t *tags = reinterpret_cast<uint8_t *>(sched + sched_tag_offset(nw));
     const int tx = t % ntx, ty = t / ntx;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
@@ -949,8 +965,7 @@ __device__ __forceinline__ void mark_touched(uint32_t *rec, int t, int ntx, int 
         const int x = tx + (d == 0 || d == 4 || d == 6 ? -1 : (d == 1 || d == 5 || d == 7 ? 1 : 0));
         const int y = ty + (d == 2 || d == 4 || d == 5 ? -1 : (d == 3 || d == 6 || d == 7 ? 1 : 0));
         if (x < 0 || x >= ntx || y < 0 || y >= nty) continue;
-        const int u = y * ntx + x;
-        atomicOr(&rec[u >> 5], 1u << (u & 31));
+        tags[y * ntx + x] = (uint8_t)tag;
     }
 }
 
@@ -960,14 +975,15 @@ __device__ __forceinline__ void mark_touched(uint32_t *rec, int t, int ntx, int 
 // j >= the number of active tiles.  Every workgroup scans the whole records,
 // so this serves small tile counts only (ntiles <= kPlanMinTiles: two
 // record words per lane, kept in registers).
-__device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sched, int slot, int ntiles, int j) {
+__device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sched, int n, int ntiles, int j) {
     const int lane = (int)threadIdx.x & 63;
     if (j >= ntiles) return -1;
     constexpr int kPer = kPlanMinTiles / 32 / 64;  // words per lane (the caller keeps ntiles <= kPlanMinTiles)
     const int nw = (ntiles + 31) >> 5;
     const int w0 = lane * kPer;
     uint32_t hw[kPer], aw[kPer];                     // this lane's heavy and other active tiles
-    const Record hr = heavy_record(sched, nw, slot), tr = touched_record(sched, nw, slot);
+    const Record hr = heavy_record(sched, nw, n % 3);
+    const uint32_t tag = touch_tag(n - 1);
     int nh = 0, na = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
@@ -975,7 +991,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sc
         const int valid = max(0, min(32, ntiles - 32 * w));  // 0 past the record
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         hw[i] = record_word(hr, w) & vm;
-        aw[i] = record_word(tr, w) & vm & ~hw[i];
+        aw[i] = touched_word(sched, nw, w, tag) & vm & ~hw[i];
         nh += __popc(hw[i]);
         na += __popc(aw[i]);
     }
@@ -1017,7 +1033,7 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sc
 
 // Visit list of the single-image step of iteration n: the tiles that
 // iteration n - 1 recorded as heavy (not quiet), in index order, then the
-// other tiles it recorded as touched (a heavy neighbour flipped pixels in
+// other tiles it tagged as touched (a heavy neighbour flipped pixels in
 // their bit window).  Every other tile is settled: it was quiet or settled
 // in n - 1 and no pixel of its window changed, so its window is still
 // uniform, both bit buffers already hold its value and its region sums are
@@ -1026,7 +1042,8 @@ __device__ __forceinline__ int active_first_tile(const uint32_t *__restrict__ sc
 template <int NT>
 __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) {
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5;
-    const Record hr = heavy_record(E.sched_mask, nw, n % 3), tr = touched_record(E.sched_mask, nw, n % 3);
+    const Record hr = heavy_record(E.sched_mask, nw, n % 3);
+    const uint32_t tag = touch_tag(n - 1);
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (nw + NT - 1) / NT;
     const int w0 = tid * per;
@@ -1034,7 +1051,7 @@ __device__ __forceinline__ void build_plan(const ImgArgs &E, int n, int *s_tot) 
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         h = record_word(hr, w) & vm;
-        a = record_word(tr, w) & vm & ~h;
+        a = touched_word(E.sched_mask, nw, w, tag) & vm & ~h;
     };
     // List positions of this thread's first heavy and first other tile: an
     // exclusive scan over the workgroup (within the wave, then over waves).

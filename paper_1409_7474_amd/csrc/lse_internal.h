@@ -166,6 +166,10 @@ constexpr uint32_t kNoTile = 0xffffffffu;  // workgroup-map entry of a spare wor
 // record itself up to this many tiles (two mask words per lane of one wave);
 // larger images get a visit list from a separate pass.
 constexpr int kPlanMinTiles = 4096;
+// Schedule words for nw record words: three heavy-tile records, then (from a
+// 16-byte aligned word) one touched-tag byte per tile.
+__host__ __device__ constexpr int sched_tag_offset(int nw) { return (3 * nw + 3) & ~3; }
+__host__ __device__ constexpr int sched_words(int nw) { return sched_tag_offset(nw) + 8 * nw; }
 
 // Kernels whose code depends on the storage type T of the resident image
 // (float, __half or __hip_bfloat16).  The member functions are defined in
@@ -269,6 +273,6 @@ hipError_t launch_count_needed(const StepArgs &a, int raw, int edge, int fast_qu
 hipError_t launch_reset_profile(DevState *st, hipStream_t s);
 // Profiling: after launch k of a single image on the fast path, add the tiles
 // that step visited and the tiles it recorded as heavy to the totals.
-hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, hipStream_t s);
+hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, int heavy, hipStream_t s);
 
 }  // namespace lse

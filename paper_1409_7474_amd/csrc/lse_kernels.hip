@@ -341,10 +341,10 @@ __global__ void reset_profile_kernel(DevState *st) {
 // Schedule record for a restart at iteration 0: every tile counts as heavy
 // in slot 0 (so every tile is visited), the other slots clear.
 // Restart: every tile heavy in the record that the next step reads (slot 0),
-// the other heavy records and all touched records empty.
+// the other heavy records empty, no tile tagged.
 __global__ void sched_reset_kernel(uint32_t *mask, int nw, int ntiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 6 * nw) return;
+    if (i >= sched_words(nw)) return;
     uint32_t v = 0u;
     if (i < nw) {
         const int valid = ntiles - 32 * i;
@@ -356,7 +356,7 @@ __global__ void sched_reset_kernel(uint32_t *mask, int nw, int ntiles) {
 hipError_t launch_sched_reset(const ImgArgs *a, hipStream_t s) {
     if (!a->sched_mask) return hipSuccess;
     const int nw = (a->tiles + 31) >> 5;
-    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((6 * nw + 255) / 256)), dim3(256), 0, s, a->sched_mask,
+    hipLaunchKernelGGL(sched_reset_kernel, dim3((unsigned)((sched_words(nw) + 255) / 256)), dim3(256), 0, s, a->sched_mask,
                        nw, a->tiles);
     return hipGetLastError();
 }
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const ImgArgs 
         const int valid = min(32, E.tiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
         h = record_word(heavy_record(E.sched_mask, nw, n % 3), w) & vm;
-        a = record_word(touched_record(E.sched_mask, nw, n % 3), w) & vm & ~h;
+        a = touched_word(E.sched_mask, nw, w, touch_tag(n - 1)) & vm & ~h;
     };
     int nh = 0, na = 0;
     for (int i = 0; i < per; ++i) {
@@ -460,28 +460,29 @@ hipError_t launch_batch_plan(const ImgArgs *args, const uint32_t *wbase, int nim
     return hipGetLastError();
 }
 
-// Profiling: step n = n0 + k visited the tiles that iteration n - 1 recorded
-// as heavy or touched (records of slot n % 3), and recorded its own heavy
-// tiles in slot (n + 1) % 3; both slots are intact until step n + 1.
-__global__ __launch_bounds__(kPlanThreads) void count_tiles_kernel(const ImgArgs *__restrict__ args, int k) {
+// Profiling, step n = n0 + k.  Before the step (heavy = 0): the tiles it
+// visits, those that iteration n - 1 recorded as heavy (slot n % 3) or
+// tagged as touched (the step overwrites tags).  After it (heavy = 1): the
+// tiles it recorded as heavy (slot (n + 1) % 3, intact until step n + 1).
+__global__ __launch_bounds__(kPlanThreads) void count_tiles_kernel(const ImgArgs *__restrict__ args, int k,
+                                                                   int heavy) {
     const ImgArgs &E = args[0];
     const int n = E.n0 + k;
     const int ntiles = E.tiles, nw = (ntiles + 31) >> 5;
-    const Record hr = heavy_record(E.sched_mask, nw, n % 3), tr = touched_record(E.sched_mask, nw, n % 3);
-    const Record next = heavy_record(E.sched_mask, nw, (n + 1) % 3);
-    unsigned long long vis = 0, heavy = 0;
+    unsigned long long c = 0;
     for (int w = threadIdx.x; w < nw; w += blockDim.x) {
         const int valid = min(32, ntiles - 32 * w);
         const uint32_t vm = valid >= 32 ? ~0u : ((1u << valid) - 1u);
-        vis += __popc((record_word(hr, w) | record_word(tr, w)) & vm);
-        heavy += __popc(record_word(next, w) & vm);
+        const uint32_t m = heavy ? record_word(heavy_record(E.sched_mask, nw, (n + 1) % 3), w)
+                                 : record_word(heavy_record(E.sched_mask, nw, n % 3), w) |
+                                       touched_word(E.sched_mask, nw, w, touch_tag(n - 1));
+        c += __popc(m & vm);
     }
-    if (vis) atomicAdd(&E.st->acc_visited, vis);
-    if (heavy) atomicAdd(&E.st->acc_heavy, heavy);
+    if (c) atomicAdd(heavy ? &E.st->acc_heavy : &E.st->acc_visited, c);
 }
 
-hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, hipStream_t s) {
-    hipLaunchKernelGGL(count_tiles_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_args, k);
+hipError_t launch_count_tiles(const ImgArgs *dev_args, int k, int heavy, hipStream_t s) {
+    hipLaunchKernelGGL(count_tiles_kernel, dim3(1), dim3(kPlanThreads), 0, s, dev_args, k, heavy);
     return hipGetLastError();
 }
 

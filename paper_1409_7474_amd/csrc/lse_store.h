@@ -677,7 +677,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                 s_tile = (int)blockIdx.x < cnt ? tt : -1;
             }
         } else if ((threadIdx.x >> 6) == 0) {
-            const int tt = active_first_tile(E.sched_mask, n % 3, E.tiles, (int)blockIdx.x);
+            const int tt = active_first_tile(E.sched_mask, n, E.tiles, (int)blockIdx.x);
             if (threadIdx.x == 0) s_tile = tt;
         }
         __syncthreads();
@@ -1009,12 +1009,14 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                     }
                     continue;
                 }
-                constexpr int CG = NV >= 4 ? 2 : kCG;
-                // Rows in groups of CG (kCG; 2 for four bands, whose loaded values
-                // would otherwise exceed the register budget): gradients first
-                // (LDS), then every data-term
-                // load of the group, then the updates, so that one memory round
-                // trip serves the whole group.
+                constexpr int CG = (NV >= 4 && (V != 0 || R > 6)) ? 2 : kCG;
+                // Rows in groups of CG (kCG; 2 for four bands in the 3- and
+                // 5-wave variants and at R = 7: measured faster at 3 waves,
+                // and elsewhere the loaded values of 4 rows exceed the
+                // register budget):
+                // gradients first (LDS), then every data-term load of the
+                // group, then the updates, so that one memory round trip
+                // serves the whole group.
     #pragma unroll 1
                 for (int r0 = 0; r0 < nr; r0 += CG) {
                     float phv[CG][2], gmv[CG][2];
@@ -1137,22 +1139,18 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             rs.red = red;
             reduce_commit<NB>(rs, acc, cnt, flips, &st->slot[sbn][blockIdx.x % kBins], A.fix, !EDGE,
                               track ? &s_prev : nullptr, track ? &E.tilelast[t] : nullptr);
-            // Touched neighbours: the next iteration visits them (last, so
-            // that no barrier waits for these atomics).
+            // Touched neighbours: the next iteration visits them.
             if (tid == 0 && s_dirs && E.sched_mask)
-                mark_touched(E.sched_mask + (size_t)(3 + sbn) * nw, t, ntx, E.tiles / ntx, s_dirs);
+                mark_touched(E.sched_mask, nw, t, ntx, E.tiles / ntx, s_dirs, touch_tag(n));
         }
     }
     if (lead_block) {
-        // Clear the slot of iteration n + 2 (statistics, heavy and touched
-        // records) that iteration n + 1 will fill (nobody reads or writes it now).
+        // Clear the slot of iteration n + 2 and the schedule mask that
+        // iteration n + 1 will fill (nobody reads or writes them now).
         unsigned long long *z = reinterpret_cast<unsigned long long *>(&st->slot[(A.n + 2) % 3][0]);
         for (int i = threadIdx.x; i < (int)(kBins * sizeof(Bin) / 8); i += kThreads) z[i] = 0ull;
         if (E.sched_mask)
-            for (int i = threadIdx.x; i < nw; i += kThreads) {
-                E.sched_mask[(size_t)sbr * nw + i] = 0u;
-                E.sched_mask[(size_t)(3 + sbr) * nw + i] = 0u;
-            }
+            for (int i = threadIdx.x; i < nw; i += kThreads) E.sched_mask[(size_t)sbr * nw + i] = 0u;
     }
     if constexpr (!EDGE && NB > 1)
         if (lead) record_max_pixel<NB, ST>(st, sl, tot.mkey, A.img, A.hw);

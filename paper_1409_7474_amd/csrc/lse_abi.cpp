@@ -197,7 +197,7 @@ Layout layout_of(const lse_params *p) {
         L.sched = o;
         o = align_up(o + (size_t)sched_words((int)((tiles + 31) / 32)) * 4);  // heavy records (3 slots), touched tags
         L.plan = o;
-        o = align_up(o + (1 + tiles) * 4);
+        o = align_up(o + (1 + step_launch_grid((int)tiles)) * 4);  // length, entries, padding to the grid
     }
     L.bits0 = o;
     o = align_up(o + (size_t)p->height * WW * 4);
@@ -383,9 +383,13 @@ lse_status enqueue_step(lse_ctx *c, int stop, hipStream_t s) {
         if (c->host_args.plan && !(region && c->NB > 1)) e = launch_plan(c->dargs, c->n, s);
         if (e == hipSuccess && (c->prof & LSE_PROFILE_COUNT) && c->host_args.sched_mask)
             e = launch_count_tiles(c->dargs, c->n, 0, s);
+        // With a visit list the step reads it as a one-image step map (image
+        // index 0: every entry is below 2^31).
+        const int *plan = c->host_args.plan;
         if (e == hipSuccess)
-            e = launch_step(c->dargs, nullptr, nullptr, 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r,
-                            c->NB, region ? 0 : 1, storage, c->variant, s);
+            e = launch_step(c->dargs, plan ? reinterpret_cast<const uint32_t *>(plan + 1) : nullptr, plan,
+                            plan ? 31 : 0, step_launch_grid(c->host_args.tiles), c->n, stop, c->r, c->NB,
+                            region ? 0 : 1, storage, c->variant, s);
     } else {
         e = launch_step_generic(a, c->NB, region ? 0 : 1, storage, s);
     }
@@ -1027,7 +1031,9 @@ size_t plan_batch(lse_ctx *const *cs, int32_t n, lse_batch *b) {
             }
             b->hmap.push_back(words);
             g.step_map = b->hmap.size();
-            b->hmap.resize(b->hmap.size() + 1 + total, 0u);
+            // length, entries, and padding to the launch grid (the step
+            // kernel loads its entry before comparing with the length)
+            b->hmap.resize(b->hmap.size() + 1 + grid, 0u);
         } else {
             // Static step map over every tile: workgroup w runs on XCD w % 8;
             // XCD x takes the x-th eighth of the concatenated tiles.

@@ -648,14 +648,22 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     __shared__ float red[kThreads / 64 * 8];
     __shared__ int s_tile;
     __shared__ int s_dirs;             // neighbours whose bit windows this step's flips reach (flip_dirs)
+    __shared__ int s_uni[kThreads / 64];  // per wave: its codes of the quiet window all 1 (bit 0) / all 0 (bit 1)
     __shared__ TileSum s_prev, s_all;  // region: the tile's latest contribution; its all-inside sums
-    int ii, t;
-    if (nmap && (int)blockIdx.x >= *nmap) return;  // past the end of a batch visit list
-    if (!batch_unit(map, unit_bits, ii, t)) return;
+    int ii = 0, t = (int)blockIdx.x;
+    if (map) {
+        // Step map entry and (visit list) its length, loaded together: lists
+        // are padded to the launch grid.  Workgroups past the length have no work.
+        const uint32_t v = map[blockIdx.x];
+        const int len = nmap ? *nmap : 0x7fffffff;
+        if ((int)blockIdx.x >= len || v == kNoTile) return;
+        ii = (int)(v >> unit_bits);
+        t = (int)(v & ((1u << unit_bits) - 1u));
+    }
     const ImgArgs &E = args[ii];
-    // Single image: the active tiles, heavy ones first, from the visit list
-    // (build_plan) or, for small tile counts, from the record itself;
-    // settled tiles have nothing to do.
+    // Single image without a visit list: the active tiles of small images,
+    // heavy ones first, found by each workgroup in the records; settled
+    // tiles have nothing to do.
     const bool dyn = map == nullptr && E.sched_mask != nullptr;
     if (!map && !dyn) t = tile_of(E.tiles);
     const int n = E.n0 + k;
@@ -671,12 +679,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     for (int i = 0; i < TS; ++i) kk[i] = E.taps->k[i];
     const float *cum = E.taps->cum;
     if (dyn) {
-        if (E.plan) {
-            if (threadIdx.x == 0) {
-                const int cnt = E.plan[0], tt = E.plan[1 + blockIdx.x];
-                s_tile = (int)blockIdx.x < cnt ? tt : -1;
-            }
-        } else if ((threadIdx.x >> 6) == 0) {
+        if ((threadIdx.x >> 6) == 0) {
             const int tt = active_first_tile(E.sched_mask, n, E.tiles, (int)blockIdx.x);
             if (threadIdx.x == 0) s_tile = tt;
         }
@@ -808,10 +811,23 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
         // that phi^n of the chunk's columns reads, and (edge term) for chunk 0
         // also those of the first two phi columns of chunk 1, which the
         // gradient of its last pixels reads.
+        // The same pass notes, per wave, whether its codes of the rows the
+        // quiet test reads are all 1 or all 0, so that the test needs no
+        // barrier of its own.
+        int all1 = 1, all0 = 1;
         for (int i = tid; i < G::BH * 2; i += kThreads) {
             const int row = i >> 1, c = i & 1;
-            s_codes[i] = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, (EDGE ? 97 : 95) - G::RU + R)
-                                : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
+            const int code = c == 0 ? range_code(s_bits + row * kFWords, 31 - G::RU - R, (EDGE ? 97 : 95) - G::RU + R)
+                                    : range_code(s_bits + row * kFWords, 95 - G::RU - R, 129 + G::RU + R);
+            s_codes[i] = code;
+            if (i < (G::PH + 2 * R) * 2) {
+                all1 &= code == 1;
+                all0 &= code == 0;
+            }
+        }
+        {
+            const unsigned long long n1 = __ballot(!all1), n0 = __ballot(!all0);
+            if (lane == 0) s_uni[wave] = (n1 == 0ull ? 1 : 0) | (n0 == 0ull ? 2 : 0);
         }
         __syncthreads();
 
@@ -829,14 +845,10 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
         // iteration, which makes the next iteration visit it.
         int quiet = -1;
         if (!border && t != 0 && by0 >= 0 && by0 + G::PH + 2 * R <= H) {
-            int all1 = 1, all0 = 1;
-            for (int i = tid; i < (G::PH + 2 * R) * 2; i += kThreads) {
-                all1 &= s_codes[i] == 1;
-                all0 &= s_codes[i] == 0;
-            }
-            all1 = __syncthreads_and(all1);
-            all0 = __syncthreads_and(all0);
-            quiet = all1 ? 1 : (all0 ? 0 : -1);
+            int u = 3;
+#pragma unroll
+            for (int v = 0; v < kThreads / 64; ++v) u &= s_uni[v];
+            quiet = (u & 1) ? 1 : ((u & 2) ? 0 : -1);
         }
         // Record heavy tiles: the next iteration visits them (and those of
         // their neighbours whose bit windows their flips reach: mark_touched).

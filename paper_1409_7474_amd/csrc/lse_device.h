@@ -946,8 +946,9 @@ __device__ __forceinline__ uint32_t touched_word(const uint32_t *sched, int nw, 
 template <int FY, int HWB>
 __device__ __forceinline__ int flip_dirs(int ry, int j, uint32_t f) {
     static_assert(HWB < 32 && HWB <= FY, "window halo exceeds a bit word or a tile");
-    if (f == 0u) return 0;
-    const bool up = ry < HWB, dn = ry >= FY - HWB;
+    // Branch-free: every term is 0 when f is.
+    const bool any = f != 0u;
+    const bool up = any && ry < HWB, dn = any && ry >= FY - HWB;
     const bool lf = j == 0 && (f & ((1u << HWB) - 1u)) != 0u;
     const bool rt = j == 2 && (f >> (32 - HWB)) != 0u;
     return (lf ? 1 : 0) | (rt ? 2 : 0) | (up ? 4 : 0) | (dn ? 8 : 0) | (lf && up ? 16 : 0) | (rt && up ? 32 : 0) |

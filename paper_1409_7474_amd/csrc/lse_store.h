@@ -958,6 +958,8 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             int dirs = 0;
             constexpr int HWB = G::RU + R + 2;
             constexpr int NBC = (G::UH + kSB - 1) / kSB;
+            // Word-forming lane of a row group: row wrow, word wk of the staged row.
+            const int wrow = lane / kFWords, wk = lane - wrow * kFWords;
             // Per lane and chunk, fixed for the whole phase: the U column, its
             // image column, whether it lies in U and in the image, its phi
             // column, and the weights of the x difference (central inside,
@@ -1022,6 +1024,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                     continue;
                 }
                 constexpr int CG = (NV >= 4 && (V != 0 || R > 6)) ? 2 : kCG;
+                static_assert(CG * kFWords <= 64, "one lane per staged word of a row group");
                 // Rows in groups of CG (kCG; 2 for four bands in the 3- and
                 // 5-wave variants and at R = 7: measured faster at 3 waves,
                 // and elsewhere the loaded values of 4 rows exceed the
@@ -1105,30 +1108,36 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                                     coef[i][c] = w * region_D<NB>(v[i][c], a, m);
                             }
                     }
+                    // The rows' ballots go to the lanes that form their words
+                    // (lane L: word L % kFWords of row L / kFWords), which
+                    // then write the whole group's words at once.
+                    unsigned long long w0 = 0ull, w1 = 0ull;
     #pragma unroll
                     for (int i = 0; i < CG; ++i) {
-                        if (r0 + i >= nr) break;
-                        const int uy = u0 + r0 + i;
-                        const int y = y0 - G::RU + uy;
-                        const bool rowok = y >= 0 && y < H;
     #pragma unroll
                         for (int c = 0; c < 2; ++c)
                             if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
                         const unsigned long long m0 = __ballot(pred[i][0]);
                         const unsigned long long m1 = __ballot(pred[i][1]);
-                        if (lane < kFWords) {
-                            const uint32_t word = bits_extract(m0, 32 - G::RU, lane) | bits_extract(m1, 96 - G::RU, lane);
-                            s_bn[uy * kFWords + lane] = word;
-                            const int gw = (x0 >> 5) - 1 + lane;
-                            if (lane >= 1 && lane <= 3 && uy >= G::RU && uy < G::RU + G::FY && rowok && gw < A.WW) {
-                                const int xs = gw * 32;
-                                const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
-                                const uint32_t nw = word & valid;
-                                const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + lane] & valid;
-                                A.bits_out[(size_t)y * A.WW + gw] = nw;
-                                flips += __popc(nw ^ ow);
-                                dirs |= flip_dirs<G::FY, HWB>(uy - G::RU, lane - 1, nw ^ ow);
-                            }
+                        if (wrow == i) {
+                            w0 = m0;
+                            w1 = m1;
+                        }
+                    }
+                    if (wrow < CG && r0 + wrow < nr) {
+                        const int uy = u0 + r0 + wrow;
+                        const int y = y0 - G::RU + uy;
+                        const uint32_t word = bits_extract(w0, 32 - G::RU, wk) | bits_extract(w1, 96 - G::RU, wk);
+                        s_bn[uy * kFWords + wk] = word;
+                        const int gw = (x0 >> 5) - 1 + wk;
+                        if (wk >= 1 && wk <= 3 && uy >= G::RU && uy < G::RU + G::FY && y >= 0 && y < H && gw < A.WW) {
+                            const int xs = gw * 32;
+                            const uint32_t valid = (W - xs >= 32) ? ~0u : ((1u << (W - xs)) - 1u);
+                            const uint32_t nw = word & valid;
+                            const uint32_t ow = s_bits[(uy + 1 + R) * kFWords + wk] & valid;
+                            A.bits_out[(size_t)y * A.WW + gw] = nw;
+                            flips += __popc(nw ^ ow);
+                            dirs |= flip_dirs<G::FY, HWB>(uy - G::RU, wk - 1, nw ^ ow);
                         }
                     }
                 }

@@ -559,10 +559,12 @@ hipError_t init_ctx(lse_ctx *c, const lse_params *p, const void *image_dev, cons
     if (e == hipSuccess) e = launch_sched_reset(&c->host_args, st);
     if (e == hipSuccess) {
         if (c->region) {
-            e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st, c->fix,
-                                  p->term == LSE_TERM_REGION ? 0 : 2, st);
-            if (e == hipSuccess && c->NB > 1)
-                e = launch_mbox(c->img, p->height, p->width, c->NB, p->storage, c->boxes, st);
+            if (c->NB > 1)  // bands stored (region term), with the normaliser boxes
+                e = launch_init_image_box(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, p->height,
+                                          p->width, c->st, c->fix, c->boxes, st);
+            else
+                e = launch_init_image(image_dev, p->image_dtype, p->storage, p->bands, c->NB, c->img, c->hw, c->st,
+                                      c->fix, p->term == LSE_TERM_REGION ? 0 : 2, st);
             if (e == hipSuccess && L.tilesum)
                 e = launch_tile_sums(c->dargs, c->host_args.tiles, c->r, c->NB, p->storage,
                                      reinterpret_cast<TileSum *>(base + L.tilesum), st);

@@ -183,7 +183,11 @@ struct Store {
     template <typename S>
     static hipError_t edge_map_t(const S *src, int B, float scale, const Taps *taps, int r1, T *g, int H, int W,
                                  DevState *st, hipStream_t s);
-    static hipError_t mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s);
+    static hipError_t init_image_box(const void *src, int src_dtype, int B, int NB, void *dst, int H, int W,
+                                     DevState *st, float fix, float *boxes, hipStream_t s);
+    template <typename S>
+    static hipError_t init_image_box_t(const S *src, int B, int NB, T *dst, int H, int W, DevState *st, float fix,
+                                       float *boxes, hipStream_t s);
     static hipError_t stats(const StepArgs &a, int NB, int raw, int slot, hipStream_t s);
     static hipError_t step(const ImgArgs *args, const uint32_t *map, const int *nmap, int unit_bits, unsigned grid,
                            int k, int stop, int r, int NB, int edge, int variant, hipStream_t s);
@@ -235,7 +239,11 @@ hipError_t launch_stats(const StepArgs &a, int NB, int storage, int raw, int slo
 hipError_t launch_edge_map(const void *src, int src_dtype, int B, float scale, const Taps *taps, int r1, void *g,
                            int H, int W, int storage, DevState *st, hipStream_t s);
 size_t mbox_floats(int H, int W, int NB);
-hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float *boxes, hipStream_t s);
+// Region image of NB = 2 or 4 stored bands (init_image mode 0) and its
+// normaliser boxes (per 64 x 32 block, the band minima and maxima of the
+// stored values) in one pass.
+hipError_t launch_init_image_box(const void *src, int src_dtype, int storage, int B, int NB, void *dst, int H, int W,
+                                 DevState *st, float fix, float *boxes, hipStream_t s);
 // Step / normaliser launches over ImgArgs: map == nullptr runs image args[0]
 // (grid = step_launch_grid / mpass_groups); else map[blockIdx.x] holds
 // (image << unit_bits) | unit, or kNoTile.  A step map built on the device

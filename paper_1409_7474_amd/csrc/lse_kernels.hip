@@ -621,11 +621,13 @@ hipError_t launch_edge_map(const void *src, int src_dtype, int B, float scale, c
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_mbox(const void *img, int H, int W, int NB, int storage, float *boxes, hipStream_t s) {
+hipError_t launch_init_image_box(const void *src, int src_dtype, int storage, int B, int NB, void *dst, int H, int W,
+                                 DevState *st, float fix, float *boxes, hipStream_t s) {
     switch (storage) {
-        case LSE_F32: return Store<float>::mbox(img, H, W, NB, boxes, s);
-        case LSE_F16: return Store<__half>::mbox(img, H, W, NB, boxes, s);
-        case LSE_BF16: return Store<__hip_bfloat16>::mbox(img, H, W, NB, boxes, s);
+        case LSE_F32: return Store<float>::init_image_box(src, src_dtype, B, NB, dst, H, W, st, fix, boxes, s);
+        case LSE_F16: return Store<__half>::init_image_box(src, src_dtype, B, NB, dst, H, W, st, fix, boxes, s);
+        case LSE_BF16:
+            return Store<__hip_bfloat16>::init_image_box(src, src_dtype, B, NB, dst, H, W, st, fix, boxes, s);
     }
     return hipErrorInvalidValue;
 }

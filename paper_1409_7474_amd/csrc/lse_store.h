@@ -258,64 +258,155 @@ __global__ __launch_bounds__(kThreads) void edge_map_kernel(const T *__restrict_
     if (bad) st->bad = 1;
 }
 
+// Region image with several stored bands and its pruning boxes in one pass
+// (init_image mode 0 together with the normaliser's block boxes): each workgroup converts
+// kIBoxBlocks 64 x 32 blocks (a wave takes every fourth row, lane = column),
+// stores each pixel's NB values with one vector store, and reduces both the
+// block's band minima / maxima of the stored values (the normaliser boxes)
+// and, as init_image does, the image statistics lines of the stored values.
+constexpr int kIBoxBlocks = 4;
+
+template <typename ST, int NB>
+__device__ __forceinline__ void store_px(ST *__restrict__ dst, long long pix, const ST (&q)[NB]) {
+    if constexpr (sizeof(ST) == 4) {
+        float *f = reinterpret_cast<float *>(dst) + pix * NB;
+        if constexpr (NB == 4)
+            *reinterpret_cast<float4 *>(f) = make_float4(q[0], q[1], q[2], q[3]);
+        else
+            *reinterpret_cast<float2 *>(f) = make_float2(q[0], q[1]);
+    } else {
+        uint32_t u[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) u[b] = __builtin_bit_cast(unsigned short, q[b]);
+        unsigned short *h = reinterpret_cast<unsigned short *>(dst) + pix * NB;
+        if constexpr (NB == 4)
+            *reinterpret_cast<uint2 *>(h) = make_uint2(u[0] | (u[1] << 16), u[2] | (u[3] << 16));
+        else
+            *reinterpret_cast<uint32_t *>(h) = u[0] | (u[1] << 16);
+    }
+}
+
+template <typename T, typename ST, int NB, bool V4>
+__global__ __launch_bounds__(kThreads) void init_image_box_kernel(const T *__restrict__ src, int B, ST *__restrict__ dst,
+                                                                  int H, int W, DevState *st, float fix,
+                                                                  float *__restrict__ boxes) {
+    static_assert(NB == 2 || NB == 4, "boxes are kept for two or four stored bands");
+    constexpr int NWV = kThreads / 64, RW = kMBY / NWV;
+    __shared__ float sbox[NWV][2 * NB];
+    __shared__ float red[NWV][4][3];
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int nbx = (W + kMBX - 1) / kMBX, nblk = nbx * ((H + kMBY - 1) / kMBY);
+    float sum[4] = {0.f, 0.f, 0.f, 0.f};
+    float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int qb = 0; qb < kIBoxBlocks; ++qb) {
+        const int blk = blockIdx.x * kIBoxBlocks + qb;
+        if (blk >= nblk) break;
+        const int x = (blk % nbx) * kMBX + lane, y0 = (blk / nbx) * kMBY + wave;
+        float v[RW][4];
+        bool ok[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {  // every row load of the wave in flight
+            const int y = y0 + i * NWV;
+            ok[i] = x < W && y < H;
+            if (ok[i])
+                load_bands<T, V4>(src + ((size_t)y * W + x) * B, B, v[i]);
+            else
+                v[i][0] = v[i][1] = v[i][2] = v[i][3] = 0.f;
+        }
+        float lo[NB], hi[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            lo[b] = INFINITY;
+            hi[b] = -INFINITY;
+        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            if (!ok[i]) continue;
+            ST q[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (b < B && !(fabsf(v[i][b]) < 65536.f)) bad = 1;  // also catches NaN / Inf
+                q[b] = from_f32<ST>(b < B ? v[i][b] : 0.f);
+                const float s = to_f32<ST>(q[b]);
+                lo[b] = fminf(lo[b], s);
+                hi[b] = fmaxf(hi[b], s);
+                if (b < B) {
+                    if (!(fabsf(s) < 65536.f)) bad = 1;  // overflow of the storage type
+                    sum[b] += s;
+                    mn[b] = fminf(mn[b], s);
+                    mx[b] = fmaxf(mx[b], s);
+                }
+            }
+            store_px<ST, NB>(dst, (long long)(y0 + i * NWV) * W + x, q);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            lo[b] = wave_min_f(lo[b]);
+            hi[b] = wave_max_f(hi[b]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                sbox[wave][b] = lo[b];
+                sbox[wave][NB + b] = hi[b];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * NB) {
+            const int k = threadIdx.x;
+            float r = sbox[0][k];
+            for (int w = 1; w < NWV; ++w) r = k < NB ? fminf(r, sbox[w][k]) : fmaxf(r, sbox[w][k]);
+            boxes[(size_t)blk * 2 * NB + k] = r;
+        }
+        __syncthreads();  // sbox is reused by the next block
+    }
+    if (bad) st->bad = 1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float s = wave_sum_f(sum[b]);
+        const float lo = wave_min_f(mn[b]);
+        const float hi = wave_max_f(mx[b]);
+        if (lane == 0) {
+            red[wave][b][0] = s;
+            red[wave][b][1] = lo;
+            red[wave][b][2] = hi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ImgBin &bin = st->img[blockIdx.x % kBins];
+        for (int b = 0; b < B; ++b) {
+            float s = 0.f, lo = INFINITY, hi = -INFINITY;
+            for (int w = 0; w < NWV; ++w) {
+                s += red[w][b][0];
+                lo = fminf(lo, red[w][b][1]);
+                hi = fmaxf(hi, red[w][b][2]);
+            }
+            atomicAdd(reinterpret_cast<unsigned long long *>(&bin.total[b]),
+                      (unsigned long long)__float2ll_rn(s * fix));
+            atomicMin(&bin.imin_key[b], float_key(lo));
+            atomicMax(&bin.imax_key[b], float_key(hi));
+        }
+    }
+}
+
 // ------------------------------------------------------------ normaliser
 
 // Normaliser M = max_x |D(x)| of eq. (17), for B > 1 (B = 1 uses the closed
 // form from the image min / max, since D is then monotone in I).
 //
-// Exact, with pruning: the image is cut into 64 x 32 blocks whose per-band
-// min / max are stored at init.  D is affine in the pixel value, so over a
+// Normaliser M of eq. (17), exact, with pruning: the image is cut into
+// 64 x 32 blocks whose per-band min / max init_image_box_kernel stores at
+// init.  D is affine in the pixel value, so over a
 // block |D| is bounded by its value at the box corners; a rounding margin
 // makes the bound hold for the FP32 D of every pixel.  The previous
 // iteration's maximising pixel, evaluated with the current means, gives a
 // lower bound LB <= M; only blocks whose bound reaches LB can hold the
 // maximum, and only those are read.  With no previous pixel (LB = 0) every
 // block is read.  The result (value and pixel) equals a full scan bit for bit.
-template <int NB, typename ST>
-__global__ __launch_bounds__(kThreads) void mbox_kernel(const ST *__restrict__ img, int H, int W,
-                                                         float *__restrict__ boxes) {
-    __shared__ float red[kThreads / 64][2 * NB];
-    const int nbx = (W + kMBX - 1) / kMBX;
-    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float lo[NB], hi[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        lo[b] = INFINITY;
-        hi[b] = -INFINITY;
-    }
-    const int x = bx * kMBX + lane;
-    for (int r = wave; r < kMBY; r += kThreads / 64) {
-        const int y = by * kMBY + r;
-        if (x < W && y < H) {
-            const Px<NB> p = load_px<ST, NB>(img, (long long)y * W + x);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                lo[b] = fminf(lo[b], p.v[b]);
-                hi[b] = fmaxf(hi[b], p.v[b]);
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        lo[b] = wave_min_f(lo[b]);
-        hi[b] = wave_max_f(hi[b]);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            red[wave][b] = lo[b];
-            red[wave][NB + b] = hi[b];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * NB) {
-        const int k = threadIdx.x;
-        float v = red[0][k];
-        for (int w = 1; w < kThreads / 64; ++w) v = k < NB ? fminf(v, red[w][k]) : fmaxf(v, red[w][k]);
-        boxes[(size_t)blockIdx.x * 2 * NB + k] = v;
-    }
-}
+// (mpass_kernel below.)
 
 // Workgroup -> (image, unit) of a launch: single image (map == nullptr) or an
 // entry of a batch map, image index in the high bits, unit (tile or block
@@ -1680,15 +1771,37 @@ hipError_t Store<ST>::edge_map(const void *src, int src_dtype, int B, float scal
 }
 
 template <typename ST>
-hipError_t Store<ST>::mbox(const void *img, int H, int W, int NB, float *boxes, hipStream_t s) {
-    const unsigned nblk = (unsigned)(((W + kMBX - 1) / kMBX) * ((H + kMBY - 1) / kMBY));
-    const ST *p = static_cast<const ST *>(img);
-    switch (NB) {
-        case 2: hipLaunchKernelGGL((mbox_kernel<2, ST>), dim3(nblk), dim3(kThreads), 0, s, p, H, W, boxes); break;
-        case 4: hipLaunchKernelGGL((mbox_kernel<4, ST>), dim3(nblk), dim3(kThreads), 0, s, p, H, W, boxes); break;
-        default: return hipErrorInvalidValue;
+template <typename T>
+hipError_t Store<ST>::init_image_box_t(const T *src, int B, int NB, ST *dst, int H, int W, DevState *st, float fix,
+                                       float *boxes, hipStream_t s) {
+    const int nblk = ((W + kMBX - 1) / kMBX) * ((H + kMBY - 1) / kMBY);
+    const dim3 grid((unsigned)((nblk + kIBoxBlocks - 1) / kIBoxBlocks)), block(kThreads);
+    const bool v4 = B == 4 && (reinterpret_cast<uintptr_t>(src) % (4 * sizeof(T))) == 0;
+    if (NB == 4) {
+        if (v4)
+            hipLaunchKernelGGL((init_image_box_kernel<T, ST, 4, true>), grid, block, 0, s, src, B, dst, H, W, st, fix, boxes);
+        else
+            hipLaunchKernelGGL((init_image_box_kernel<T, ST, 4, false>), grid, block, 0, s, src, B, dst, H, W, st, fix,
+                               boxes);
+    } else if (NB == 2) {
+        hipLaunchKernelGGL((init_image_box_kernel<T, ST, 2, false>), grid, block, 0, s, src, B, dst, H, W, st, fix, boxes);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t Store<ST>::init_image_box(const void *src, int src_dtype, int B, int NB, void *dst, int H, int W,
+                                     DevState *st, float fix, float *boxes, hipStream_t s) {
+    ST *d = static_cast<ST *>(dst);
+    switch (src_dtype) {
+        case LSE_F32: return init_image_box_t(static_cast<const float *>(src), B, NB, d, H, W, st, fix, boxes, s);
+        case LSE_F16: return init_image_box_t(static_cast<const __half *>(src), B, NB, d, H, W, st, fix, boxes, s);
+        case LSE_BF16:
+            return init_image_box_t(static_cast<const __hip_bfloat16 *>(src), B, NB, d, H, W, st, fix, boxes, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // The statistics kernel uses the same tiling as the step kernel that would

@@ -680,6 +680,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+DENSE_WARMUP, DENSE_TIMED = 5, 20  # launches of the fully active roofline measurement
+
+
 def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_region, kname_edge):
     """Roofline of a fully active step: the state is an 8 x 8 checkerboard
     (loaded as the smoothed LSF of a binary function, Table I step 4), so
@@ -687,17 +690,19 @@ def dense_rooflines(args, lse, torch, img, params, terms, h, w, nb, sids, kname_
     step is the first after the load; its kernel time comes from the events
     of its own dispatch.  Algorithmic bytes per pixel: the image (region:
     B x 4 B) or edge map (4 B) read once, and the stored LSF read and written
-    once in FP32 (8 B)."""
+    once in FP32 (8 B).  The GPU clocks settle over the first launches of a
+    process, so this measurement takes at least DENSE_WARMUP untimed and
+    DENSE_TIMED timed launches whatever --steps and --warmup are."""
     cb = torch.tensor(checkerboard(h, w), device=img.device)
     res = {}
-    reps = max(args.steps, 3)
+    reps = max(args.steps, DENSE_TIMED)
     for t in terms:
         nbytes = lse.lse_workspace_bytes(params[t])
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=img.device)
         ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
         s = sids[t]
         ctx = lse.lse_init(params[t], img.data_ptr(), cb.data_ptr(), ptr, nbytes, s)
-        for _ in range(max(args.warmup, 1)):
+        for _ in range(max(args.warmup, DENSE_WARMUP)):
             lse.lse_set_mask(ctx, cb.data_ptr(), True, 0, s)
             lse.lse_step(ctx, s)
         lse.lse_profile(ctx, lse.PROFILE_TIMING)

@@ -775,19 +775,25 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
                                            const float *__restrict__ cum, float (&acc)[NB], int &cnt) {
     using G = FastGeom<R, false>;
     static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");
+    static_assert(kFX == 96 && kThreads == 256, "three waves cover the owned columns by row segments");
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = wave_id();
-    const int chunk = wave & 1, seg = wave >> 1;
-    const int ox = chunk * 64 + lane;
-    const int x = x0 + ox;
-    const bool colok = ox < kFX && x < W;
-    // The window of this chunk's columns (bits of code_rows_owned) reaches
-    // outside the image only next to the left or right edge.
-    border = border && span_outside(x0, W, chunk == 0 ? 32 - R : 96 - R, chunk == 0 ? 96 + R : 128 + R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.f;
     cnt = 0;
-    const int urow0 = seg * G::SEGD;  // U row of output row 0 of this segment's window
+    // Waves 0 and 2: columns 0..63, rows of segment 0 / 1.  Wave 1: columns
+    // 64..95, lanes 0..31 on segment 0 and lanes 32..63 on segment 1 (so no
+    // lane idles).  Wave 3 has no statistics work.
+    if (wave == 3) return;
+    const int chunk = wave & 1;
+    const int seg = chunk ? (lane >> 5) : (wave >> 1);
+    const int ox = chunk ? 64 + (lane & 31) : lane;
+    const int x = x0 + ox;
+    const bool colok = x < W;
+    // The window of this chunk's columns (bits of code_rows_owned) reaches
+    // outside the image only next to the left or right edge.
+    border = border && span_outside(x0, W, chunk == 0 ? 32 - R : 96 - R, chunk == 0 ? 96 + R : 128 + R);
+    const int urow0 = seg * G::SEGD;  // U row of output row 0 of this lane's segment window
     static_assert(G::SEGD <= 32, "inside flags of a segment fit one 32-bit mask");
     // Pass 1: which output rows of this lane's column are on the + side.
     uint32_t inmask = 0u;
@@ -808,7 +814,16 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
             // the sign is needed, so this holds at the image edges too: bits
             // outside the image are zero, so an all-ones window lies inside
             // the image, and an all-zeros one gives minus a positive sum.
-            const int uni = block_code(codes, rb, kSB + 2 * R, chunk);
+            // Wave 1 holds blocks of both segments: it skips only when both
+            // are uniform (a computed uniform window gives the same sign).
+            int uni;
+            if (chunk) {
+                const int u0 = block_code(codes, blk * kSB, kSB + 2 * R, 1);
+                const int u1 = block_code(codes, G::SEGD + blk * kSB, kSB + 2 * R, 1);
+                uni = (u0 >= 0 && u1 >= 0) ? (seg ? u1 : u0) : -1;
+            } else {
+                uni = block_code(codes, rb, kSB + 2 * R, 0);
+            }
             if (uni >= 0) {
                 if (uni == 1) inmask |= ((1u << kSB) - 1u) << (blk * kSB);
                 have_win = false;

@@ -1058,15 +1058,21 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
             // gx = ar * phi(x+1) + al * phi(x-1) + ac * phi(x), each case
             // rounding exactly as 0.5 (phi(x+1) - phi(x-1)), phi(1) - phi(0)
             // or phi(W-1) - phi(W-2) does.
-            // (The phi column of U column xb = 32 - RU + 64 c + lane is
-            // 64 c + lane + 1; ac = -(ar + al).)
+            // (The phi column of U column xb = 32 - RU + ucol is ucol + 1;
+            // ac = -(ar + al).)
+            // In the edge term U is the tile itself (RU = 0), so chunk 1 holds
+            // only 32 columns: there each lane half takes its own row (lanes
+            // 0-31 row 2j, lanes 32-63 row 2j + 1 of a packed slot).
+            constexpr bool PK = G::RU == 0;
+            const int hl = lane >> 5;
+            const int ucol[2] = {lane, PK ? 64 + (lane & 31) : 64 + lane};
             const int cx0 = x0 - G::RU + lane;
             bool cok[2];
             float ar[2], al[2];
     #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int x = cx0 + 64 * c;
-                cok[c] = 64 * c + lane < 96 + 2 * G::RU && x >= 0 && x < W;
+                const int x = x0 - G::RU + ucol[c];
+                cok[c] = ucol[c] < 96 + 2 * G::RU && x >= 0 && x < W;
                 const bool first = x == 0, last = x == W - 1;
                 ar[c] = first ? 1.f : (last ? 0.f : 0.5f);
                 al[c] = first ? 0.f : (last ? -1.f : -0.5f);
@@ -1123,96 +1129,170 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                 // gradients first (LDS), then every data-term load of the
                 // group, then the updates, so that one memory round trip
                 // serves the whole group.
+                // Slots of a row group: one wave-wide pass each, over (row,
+                // chunk) pairs, or in the edge term CG rows of chunk 0 and
+                // CG / 2 packed row pairs of chunk 1.
+                static_assert(!PK || CG % 2 == 0, "packed slots take row pairs");
+                constexpr int NS = PK ? CG + CG / 2 : 2 * CG;
     #pragma unroll 1
                 for (int r0 = 0; r0 < nr; r0 += CG) {
-                    float phv[CG][2], gmv[CG][2];
-                    bool need[CG][2], pred[CG][2];
-                    // Data term of each pixel: the region term (B values per pixel) loads
-                    // it as soon as the pixel's gradient is known (fewer live registers,
-                    // earlier loads); the edge term loads the group afterwards (measured
-                    // faster there).
-                    Px<NV> v[CG][2];
-                    int pixv[CG][2];
+                    // The rows' ballots go to the lanes that form their words
+                    // (lane L: word L % kFWords of row L / kFWords), which
+                    // then write the whole group's words at once.
+                    unsigned long long w0 = 0ull, w1 = 0ull;
+                    if constexpr (PK) {
+                        float phv[NS], gmv[NS];
+                        bool need[NS], pred[NS];
+                        Px<NV> v[NS];
+                        int pixv[NS];
     #pragma unroll
-                    for (int i = 0; i < CG; ++i) {
-                        // Row quantities are the same in every lane (scalar).
-                        const int uy = u0 + r0 + i;
-                        const int y = y0 - G::RU + uy;
-                        const bool rowok = r0 + i < nr && y >= 0 && y < H;
-                        // Rows past U read phi row UH instead (in the array; the
-                        // results are masked).  The y difference like the x one.
-                        const float *prow = s_phi + (min(uy, G::UH - 1) + 1) * G::PS;
-                        const float dr = y == 0 ? 1.f : (y == H - 1 ? 0.f : 0.5f);
-                        const float ur = y == 0 ? 0.f : (y == H - 1 ? -1.f : -0.5f);
-                        const float cr0 = y == 0 ? -1.f : (y == H - 1 ? 1.f : 0.f);
-                        const int rowpix = y * W;
-    #pragma unroll
-                        for (int c = 0; c < 2; ++c) {
+                        for (int s = 0; s < NS; ++s) {
+                            const int c = s >= CG ? 1 : 0;
+                            // Row of the slot: per lane in a packed slot.
+                            const int i = s < CG ? s : 2 * (s - CG) + hl;
+                            const int uy = u0 + r0 + i;
+                            const int y = y0 - G::RU + uy;
+                            const bool rowok = r0 + i < nr && y >= 0 && y < H;
+                            // Rows past U read phi row UH instead (in the array; the
+                            // results are masked).  The y difference like the x one.
+                            const float *prow = s_phi + (min(uy, G::UH - 1) + 1) * G::PS;
+                            const float dr = y == 0 ? 1.f : (y == H - 1 ? 0.f : 0.5f);
+                            const float ur = y == 0 ? 0.f : (y == H - 1 ? -1.f : -0.5f);
+                            const float cr0 = y == 0 ? -1.f : (y == H - 1 ? 1.f : 0.f);
+                            const int rowpix = y * W;
                             const bool ok = rowok && cok[c];
-                            if (EDGE && ucs[c] >= 0) {  // constant phi over this chunk's gradients
-                                phv[i][c] = 0.f;
-                                pred[i][c] = ok && ucs[c] == 1;
-                                need[i][c] = false;
-                                gmv[i][c] = 0.f;
+                            if (ucs[c] >= 0) {  // constant phi over this chunk's gradients
+                                phv[s] = 0.f;
+                                pred[s] = ok && ucs[c] == 1;
+                                need[s] = false;
+                                gmv[s] = 0.f;
                             } else {
                                 // All five values are read (branch-free: lanes
                                 // outside U read phi inside the array) and the
                                 // image-border cases are weights, so the reads of
                                 // a group are in flight together.
-                                const float *cc = prow + 64 * c + lane + 1;
+                                const float *cc = prow + ucol[c] + 1;
                                 const float c0 = cc[0], cl = cc[-1], cr = cc[1], cu = cc[-G::PS], cd = cc[G::PS];
                                 const float gx = fmaf(ar[c], cr, fmaf(al[c], cl, -(ar[c] + al[c]) * c0));
                                 const float gy = fmaf(dr, cd, fmaf(ur, cu, cr0 * c0));
                                 const float g2 = gx * gx + gy * gy;
-                                phv[i][c] = c0;
-                                pred[i][c] = ok && c0 >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
-                                need[i][c] = ok && g2 != 0.f;
+                                phv[s] = c0;
+                                pred[s] = ok && c0 >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                                need[s] = ok && g2 != 0.f;
                                 // The hardware square root (within 1 ulp, one
                                 // instruction instead of the ~15 of a correctly
                                 // rounded one): it moves u by at most
                                 // dt |R| |grad phi| 2^-23 < 3e-6, inside the band
                                 // where FP32 cannot decide the sign like FP64.
-                                gmv[i][c] = __builtin_amdgcn_sqrtf(g2);
+                                gmv[s] = __builtin_amdgcn_sqrtf(g2);
                             }
-                            const int pix = rowpix + cx0 + 64 * c;
-                            pixv[i][c] = pix;
-                            if constexpr (!EDGE)
-                                v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pix * PB : kNoLoad);
+                            const int pix = rowpix + x0 + ucol[c];
+                            pixv[s] = pix;
                         }
-                    }
-                    if constexpr (EDGE) {
     #pragma unroll
-                        for (int i = 0; i < CG; ++i)
+                        for (int s = 0; s < NS; ++s)
+                            v[s] = buffer_px<ST, NV>(img_rs, need[s] ? (uint32_t)pixv[s] * PB : kNoLoad);
+                        float coef[NS];
     #pragma unroll
-                            for (int c = 0; c < 2; ++c)
-                                v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
-                    }
-                    float coef[CG][2];
-                    {
+                        for (int s = 0; s < NS; ++s) coef[s] = A.dt * v[s].v[0];
+                        // A packed slot's ballot holds row 2j's chunk-1 bits in
+                        // its low half and row 2j + 1's in its high half.
     #pragma unroll
-                        for (int i = 0; i < CG; ++i)
+                        for (int s = 0; s < NS; ++s) {
+                            if (need[s]) pred[s] = fmaf(coef[s], gmv[s], phv[s]) >= 0.f;
+                            const unsigned long long m = __ballot(pred[s]);
+                            if (s >= CG) {
+                                if ((wrow >> 1) == s - CG) w1 = (wrow & 1) ? m >> 32 : m & 0xffffffffull;
+                            } else if (wrow == s) {
+                                w0 = m;
+                            }
+                        }
+                    } else {
+                        float phv[CG][2], gmv[CG][2];
+                        bool need[CG][2], pred[CG][2];
+                        // Data term of each pixel: the region term (B values per pixel) loads
+                        // it as soon as the pixel's gradient is known (fewer live registers,
+                        // earlier loads); the edge term loads the group afterwards (measured
+                        // faster there).
+                        Px<NV> v[CG][2];
+                        int pixv[CG][2];
+    #pragma unroll
+                        for (int i = 0; i < CG; ++i) {
+                            // Row quantities are the same in every lane (scalar).
+                            const int uy = u0 + r0 + i;
+                            const int y = y0 - G::RU + uy;
+                            const bool rowok = r0 + i < nr && y >= 0 && y < H;
+                            // Rows past U read phi row UH instead (in the array; the
+                            // results are masked).  The y difference like the x one.
+                            const float *prow = s_phi + (min(uy, G::UH - 1) + 1) * G::PS;
+                            const float dr = y == 0 ? 1.f : (y == H - 1 ? 0.f : 0.5f);
+                            const float ur = y == 0 ? 0.f : (y == H - 1 ? -1.f : -0.5f);
+                            const float cr0 = y == 0 ? -1.f : (y == H - 1 ? 1.f : 0.f);
+                            const int rowpix = y * W;
     #pragma unroll
                             for (int c = 0; c < 2; ++c) {
-                                if constexpr (EDGE)
-                                    coef[i][c] = A.dt * v[i][c].v[0];
-                                else
-                                    coef[i][c] = w * region_D<NB>(v[i][c], a, m);
+                                const bool ok = rowok && cok[c];
+                                if (EDGE && ucs[c] >= 0) {  // constant phi over this chunk's gradients
+                                    phv[i][c] = 0.f;
+                                    pred[i][c] = ok && ucs[c] == 1;
+                                    need[i][c] = false;
+                                    gmv[i][c] = 0.f;
+                                } else {
+                                    // All five values are read (branch-free: lanes
+                                    // outside U read phi inside the array) and the
+                                    // image-border cases are weights, so the reads of
+                                    // a group are in flight together.
+                                    const float *cc = prow + 64 * c + lane + 1;
+                                    const float c0 = cc[0], cl = cc[-1], cr = cc[1], cu = cc[-G::PS], cd = cc[G::PS];
+                                    const float gx = fmaf(ar[c], cr, fmaf(al[c], cl, -(ar[c] + al[c]) * c0));
+                                    const float gy = fmaf(dr, cd, fmaf(ur, cu, cr0 * c0));
+                                    const float g2 = gx * gx + gy * gy;
+                                    phv[i][c] = c0;
+                                    pred[i][c] = ok && c0 >= 0.f;  // |grad phi| = 0: u = phi exactly (eq. (18))
+                                    need[i][c] = ok && g2 != 0.f;
+                                    // The hardware square root (within 1 ulp, one
+                                    // instruction instead of the ~15 of a correctly
+                                    // rounded one): it moves u by at most
+                                    // dt |R| |grad phi| 2^-23 < 3e-6, inside the band
+                                    // where FP32 cannot decide the sign like FP64.
+                                    gmv[i][c] = __builtin_amdgcn_sqrtf(g2);
+                                }
+                                const int pix = rowpix + cx0 + 64 * c;
+                                pixv[i][c] = pix;
+                                if constexpr (!EDGE)
+                                    v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pix * PB : kNoLoad);
                             }
-                    }
-                    // The rows' ballots go to the lanes that form their words
-                    // (lane L: word L % kFWords of row L / kFWords), which
-                    // then write the whole group's words at once.
-                    unsigned long long w0 = 0ull, w1 = 0ull;
+                        }
+                        if constexpr (EDGE) {
     #pragma unroll
-                    for (int i = 0; i < CG; ++i) {
+                            for (int i = 0; i < CG; ++i)
     #pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
-                        const unsigned long long m0 = __ballot(pred[i][0]);
-                        const unsigned long long m1 = __ballot(pred[i][1]);
-                        if (wrow == i) {
-                            w0 = m0;
-                            w1 = m1;
+                                for (int c = 0; c < 2; ++c)
+                                    v[i][c] = buffer_px<ST, NV>(img_rs, need[i][c] ? (uint32_t)pixv[i][c] * PB : kNoLoad);
+                        }
+                        float coef[CG][2];
+                        {
+    #pragma unroll
+                            for (int i = 0; i < CG; ++i)
+    #pragma unroll
+                                for (int c = 0; c < 2; ++c) {
+                                    if constexpr (EDGE)
+                                        coef[i][c] = A.dt * v[i][c].v[0];
+                                    else
+                                        coef[i][c] = w * region_D<NB>(v[i][c], a, m);
+                                }
+                        }
+    #pragma unroll
+                        for (int i = 0; i < CG; ++i) {
+    #pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                if (need[i][c]) pred[i][c] = fmaf(coef[i][c], gmv[i][c], phv[i][c]) >= 0.f;
+                            const unsigned long long m0 = __ballot(pred[i][0]);
+                            const unsigned long long m1 = __ballot(pred[i][1]);
+                            if (wrow == i) {
+                                w0 = m0;
+                                w1 = m1;
+                            }
                         }
                     }
                     if (wrow < CG && r0 + wrow < nr) {

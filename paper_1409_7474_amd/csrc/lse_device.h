@@ -614,8 +614,13 @@ struct FastGeom {
     static constexpr int UH = FY + 2 * RU;       // rows where b^n is computed
     static constexpr int PH = UH + 2;            // rows of phi^n
     static constexpr int PW = kFX + 2 * RU + 2;  // columns of phi^n (<= 128)
-    static constexpr int NBLK = (PH + 2 * kSB - 1) / (2 * kSB);  // window blocks per segment
-    static constexpr int SEG = NBLK * kSB;       // phi rows per wave (2 segments x 2 chunks)
+    // Rows per block of the phi pass's rolling window: kSB in the region
+    // term (its PH = 2 (mod 16) wastes 2 rows); in the edge term the block
+    // height that splits PH into two segments of at most 11-row blocks with
+    // the fewest rows past PH (66 rows: 2 x 3 x 11, none).
+    static constexpr int NBLK = EDGE ? (PH + 21) / 22 : (PH + 2 * kSB - 1) / (2 * kSB);  // window blocks per segment
+    static constexpr int KB = EDGE ? (PH + 2 * NBLK - 1) / (2 * NBLK) : kSB;
+    static constexpr int SEG = NBLK * KB;        // phi rows per wave (2 segments x 2 chunks)
     static constexpr int PHP = 2 * SEG;          // phi rows allocated (>= PH)
     static constexpr int BH = PHP + 2 * R;       // staged rows of b^{n-1}
     static constexpr int SEGD = FY / 2;          // statistics rows per wave

@@ -984,25 +984,26 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                         if (lane == 0) s_pcode[q * 2 + chunk] = 2;
                     }
                 } else {
-                    constexpr int NW = 2 * R + kSB;
+                    constexpr int KB = G::KB;
+                    constexpr int NW = 2 * R + KB;
                     float win[NW];
                     const int brow0 = seg * G::SEG;  // staged bit row of window entry 0
                     const HPad pad = hpad_of<R>(x, W, cborder, cum);
                     bool have_win = false;
     #pragma unroll 1
                     for (int blk = 0; blk < G::NBLK; ++blk) {
-                        const int rb = brow0 + blk * kSB;
+                        const int rb = brow0 + blk * KB;
                         int uni = -1;
-                        if (!cborder && by0 + rb >= 0 && by0 + rb + kSB + 2 * R <= H)
-                            uni = block_code(s_codes, rb, kSB + 2 * R, chunk);
+                        if (!cborder && by0 + rb >= 0 && by0 + rb + KB + 2 * R <= H)
+                            uni = block_code(s_codes, rb, KB + 2 * R, chunk);
                         if (uni >= 0) {
                             const float v = uni ? phi_one : phi_zero;
     #pragma unroll
-                            for (int j = 0; j < kSB; ++j) {
+                            for (int j = 0; j < KB; ++j) {
                                 const int q = rb + j;
                                 if (p < G::PW && q < G::PH) s_phi[q * G::PS + p] = colok ? v : 0.f;
                             }
-                            if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = uni;
+                            if (lane < KB) s_pcode[(rb + lane) * 2 + chunk] = uni;
                             have_win = false;
                             continue;
                         }
@@ -1016,23 +1017,23 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                             }
                         }
     #pragma unroll
-                        for (int t2 = 0; t2 < kSB; ++t2) {
+                        for (int t2 = 0; t2 < KB; ++t2) {
                             const int brow = rb + 2 * R + t2;
                             const int y = by0 + brow;
                             const float v = hconv_fast<R, G::NCH>(s_bits + brow * kFWords, xb, pad, lut);
                             win[2 * R + t2] = (y >= 0 && y < H) ? v : 0.f;
                         }
     #pragma unroll
-                        for (int j = 0; j < kSB; ++j) {
+                        for (int j = 0; j < KB; ++j) {
                             float ph = 0.f;
     #pragma unroll
                             for (int i = 0; i < TS; ++i) ph = fmaf(kk[i], win[j + i], ph);
                             const int q = rb + j, y = py0 + q;  // phi row q <-> bit rows q .. q + 2R
                             if (p < G::PW && q < G::PH) s_phi[q * G::PS + p] = (colok && y >= 0 && y < H) ? ph : 0.f;
                         }
-                        if (lane < kSB) s_pcode[(rb + lane) * 2 + chunk] = 2;
+                        if (lane < KB) s_pcode[(rb + lane) * 2 + chunk] = 2;
     #pragma unroll
-                        for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + kSB];
+                        for (int t2 = 0; t2 < 2 * R; ++t2) win[t2] = win[t2 + KB];
                         have_win = true;
                     }
                 }

@@ -73,6 +73,69 @@ __device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
     return v;
 }
 
+// Integer reductions over a whole wave without LDS traffic (the shuffles
+// above are LDS permutes, which queue behind the phi pass's table lookups of
+// other workgroups): a butterfly inside each row of 16 lanes by DPP moves
+// (quad permutes for lane distances 1 and 2, row rotations by 4 and 8), after
+// which every lane holds its row's result, then the four row results read
+// into scalar registers.  Exact for any order; every lane of the wave must be
+// active.  The result is the same in every lane.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    return ((unsigned long long)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l) {
+    return ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppRor4 = 0x124;  // row_ror:4
+constexpr int kDppRor8 = 0x128;  // row_ror:8
+
+__device__ __forceinline__ long long wave_sum_ll_dpp(long long x) {
+    unsigned long long v = (unsigned long long)x;
+    v += dpp_u64<kDppXor1>(v);
+    v += dpp_u64<kDppXor2>(v);
+    v += dpp_u64<kDppRor4>(v);
+    v += dpp_u64<kDppRor8>(v);
+    return (long long)(lane_u64(v, 0) + lane_u64(v, 16) + lane_u64(v, 32) + lane_u64(v, 48));
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64_dpp(unsigned long long v) {
+    auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+    v = mx(v, dpp_u64<kDppXor1>(v));
+    v = mx(v, dpp_u64<kDppXor2>(v));
+    v = mx(v, dpp_u64<kDppRor4>(v));
+    v = mx(v, dpp_u64<kDppRor8>(v));
+    return mx(mx(lane_u64(v, 0), lane_u64(v, 16)), mx(lane_u64(v, 32), lane_u64(v, 48)));
+}
+
+__device__ __forceinline__ int wave_sum_i_dpp(int x) {
+    uint32_t v = (uint32_t)x;
+    v += dpp_u32<kDppXor1>(v);
+    v += dpp_u32<kDppXor2>(v);
+    v += dpp_u32<kDppRor4>(v);
+    v += dpp_u32<kDppRor8>(v);
+    return (int)((uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+                 (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+}
+
+template <bool MAX>
+__device__ __forceinline__ unsigned int wave_ext_u_dpp(unsigned int v) {
+    auto ex = [](unsigned int a, unsigned int b) { return MAX ? max(a, b) : min(a, b); };
+    v = ex(v, dpp_u32<kDppXor1>(v));
+    v = ex(v, dpp_u32<kDppXor2>(v));
+    v = ex(v, dpp_u32<kDppRor4>(v));
+    v = ex(v, dpp_u32<kDppRor8>(v));
+    return ex(ex((unsigned int)__builtin_amdgcn_readlane((int)v, 0), (unsigned int)__builtin_amdgcn_readlane((int)v, 16)),
+              ex((unsigned int)__builtin_amdgcn_readlane((int)v, 32), (unsigned int)__builtin_amdgcn_readlane((int)v, 48)));
+}
+
 __device__ __forceinline__ int block_linear_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
 
@@ -134,10 +197,10 @@ __device__ __forceinline__ void totals_commit(bool want_img, TotalsRegs &r, Tota
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (wave == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r.v[k] = wave_sum_ll(r.v[k]);
-        r.np = wave_sum_ll(r.np);
-        r.fl = wave_sum_ll(r.fl);
-        r.mk = wave_max_u64(r.mk);
+        for (int k = 0; k < 4; ++k) r.v[k] = wave_sum_ll_dpp(r.v[k]);
+        r.np = wave_sum_ll_dpp(r.np);
+        r.fl = wave_sum_ll_dpp(r.fl);
+        r.mk = wave_max_u64_dpp(r.mk);
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) t->sum[k] = r.v[k];
@@ -154,9 +217,9 @@ __device__ __forceinline__ void totals_commit(bool want_img, TotalsRegs &r, Tota
     } else if (wave == 1 && want_img) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            r.v[k] = wave_sum_ll(r.v[k]);
-            r.lo[k] = wave_min_u(r.lo[k]);
-            r.hi[k] = wave_max_u(r.hi[k]);
+            r.v[k] = wave_sum_ll_dpp(r.v[k]);
+            r.lo[k] = wave_ext_u_dpp<false>(r.lo[k]);
+            r.hi[k] = wave_ext_u_dpp<true>(r.hi[k]);
         }
         if (lane == 0) {
 #pragma unroll
@@ -482,9 +545,9 @@ __device__ __forceinline__ void block_reduce(const TileSmem &s, float (&acc)[NB]
     if (with_sums) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[b] = wave_sum_f(acc[b]);
-        cnt = wave_sum_i(cnt);
+        cnt = wave_sum_i_dpp(cnt);
     }
-    flips = wave_sum_i(flips);
+    flips = wave_sum_i_dpp(flips);
     if (lane == 0) {
         float *rw = s.red + wave * 8;
 #pragma unroll

@@ -125,6 +125,21 @@ __device__ __forceinline__ int wave_sum_i_dpp(int x) {
                  (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
 }
 
+// FP32 sum in a fixed order: the row butterfly above (every lane of a row
+// then holds its row's sum, lane 0 in the order ((l0 + l1) + (l2 + l3)) + ...),
+// then the rows as (r0 + r1) + (r2 + r3) from lanes 0, 16, 32 and 48.
+__device__ __forceinline__ float wave_sum_f_dpp(float x) {
+    x += __uint_as_float(dpp_u32<kDppXor1>(__float_as_uint(x)));
+    x += __uint_as_float(dpp_u32<kDppXor2>(__float_as_uint(x)));
+    x += __uint_as_float(dpp_u32<kDppRor4>(__float_as_uint(x)));
+    x += __uint_as_float(dpp_u32<kDppRor8>(__float_as_uint(x)));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
 template <bool MAX>
 __device__ __forceinline__ unsigned int wave_ext_u_dpp(unsigned int v) {
     auto ex = [](unsigned int a, unsigned int b) { return MAX ? max(a, b) : min(a, b); };
@@ -536,7 +551,7 @@ __device__ __forceinline__ void stats_tile(const TileSmem &s, const ST *__restri
 }
 
 // Workgroup reduction of (NB sums, count, flips): the totals are valid in
-// thread 0.  FP32 sums in a fixed order (wave butterfly, then waves in
+// thread 0.  FP32 sums in a fixed order (wave_sum_f_dpp, then waves in
 // order), so a tile's partial sums are a function of its data alone.
 template <int NB>
 __device__ __forceinline__ void block_reduce(const TileSmem &s, float (&acc)[NB], int cnt, int flips, bool with_sums,
@@ -544,7 +559,7 @@ __device__ __forceinline__ void block_reduce(const TileSmem &s, float (&acc)[NB]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (with_sums) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = wave_sum_f(acc[b]);
+        for (int b = 0; b < NB; ++b) acc[b] = wave_sum_f_dpp(acc[b]);
         cnt = wave_sum_i_dpp(cnt);
     }
     flips = wave_sum_i_dpp(flips);

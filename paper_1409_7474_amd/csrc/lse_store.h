@@ -537,7 +537,7 @@ __global__ __launch_bounds__(kThreads) void mpass_kernel(const ImgArgs *__restri
             }
         }
     }
-    best = wave_max_u64(best);
+    best = wave_max_u64_dpp(best);
     if (lane == 0) wkey[wave] = best;
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -182,8 +182,45 @@ struct TotalsRegs {
     int done, bad, raw;
 };
 
-__device__ __forceinline__ void totals_issue(const DevState *st, int sl, bool want_img, TotalsRegs &r) {
+__device__ __forceinline__ void totals_issue(const DevState *st, int sl, bool want_img, TotalsRegs &r,
+                                             bool split = false, bool want_sums = true, bool want_keys = true) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (split) {
+        // Four waves share the reductions: 0 the sums, 1 the band totals,
+        // 2 count, flips, maximum key and flags, 3 the band minimum and
+        // maximum keys (only the wanted ones are loaded).
+        const Bin &b = st->slot[sl][lane];
+        const ImgBin &ib = st->img[lane];
+        if (wave == 0) {
+            if (want_sums) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) r.v[k] = b.sum[k];
+            }
+        } else if (wave == 1) {
+            if (want_img) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) r.v[k] = ib.total[k];
+            }
+        } else if (wave == 2) {
+            r.fl = (long long)b.flips;
+            if (want_sums) {
+                r.np = (long long)b.nplus;
+                r.mk = b.mkey;
+            }
+            if (lane == 0) {
+                r.done = st->done;
+                r.bad = st->bad;
+                r.raw = st->raw;
+            }
+        } else if (want_img && want_keys) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.lo[k] = ib.imin_key[k];
+                r.hi[k] = ib.imax_key[k];
+            }
+        }
+        return;
+    }
     if (wave == 0) {
         const Bin &b = st->slot[sl][lane];
 #pragma unroll
@@ -208,8 +245,55 @@ __device__ __forceinline__ void totals_issue(const DevState *st, int sl, bool wa
     }
 }
 
-__device__ __forceinline__ void totals_commit(bool want_img, TotalsRegs &r, Totals *t) {
+// Reduce what totals_issue loaded and write `t` (the caller then synchronises
+// the workgroup).  With `split` (four waves), the fields a caller did not
+// want are written as zeros.
+__device__ __forceinline__ void totals_commit(bool want_img, TotalsRegs &r, Totals *t, bool split = false,
+                                              bool want_sums = true, bool want_keys = true) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (split) {
+        if (wave == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.v[k] = want_sums ? wave_sum_ll_dpp(r.v[k]) : 0;
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) t->sum[k] = r.v[k];
+            }
+        } else if (wave == 1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.v[k] = want_img ? wave_sum_ll_dpp(r.v[k]) : 0;
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) t->total[k] = r.v[k];
+            }
+        } else if (wave == 2) {
+            r.fl = wave_sum_ll_dpp(r.fl);
+            r.np = want_sums ? wave_sum_ll_dpp(r.np) : 0;
+            r.mk = want_sums ? wave_max_u64_dpp(r.mk) : 0ull;
+            if (lane == 0) {
+                t->nplus = (unsigned long long)r.np;
+                t->flips = (unsigned long long)r.fl;
+                t->mkey = r.mk;
+                t->done = r.done;
+                t->bad = r.bad;
+                t->raw = r.raw;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.lo[k] = want_img && want_keys ? wave_ext_u_dpp<false>(r.lo[k]) : 0u;
+                r.hi[k] = want_img && want_keys ? wave_ext_u_dpp<true>(r.hi[k]) : 0u;
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    t->imin_key[k] = r.lo[k];
+                    t->imax_key[k] = r.hi[k];
+                }
+            }
+        }
+        return;
+    }
     if (wave == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) r.v[k] = wave_sum_ll_dpp(r.v[k]);

@@ -820,8 +820,12 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     // record and all-inside sums, issued before the statistics loads so that
     // the memory round trips overlap.
     const bool track = !EDGE && E.tilelast != nullptr;
+    // The totals this kernel reads: the edge term only the flips and flags;
+    // the band minimum and maximum only for one band (the closed-form M).
+    // Four waves share the reductions.
+    static_assert(kThreads == 256, "the totals reductions are split over four waves");
     TotalsRegs tregs;
-    totals_issue(st, sl, !EDGE, tregs);
+    totals_issue(st, sl, !EDGE, tregs, true, !EDGE, NB == 1);
     long long rec_w = 0, all_w = 0;
     if (!EDGE && tid < 8) {
         if (track) rec_w = reinterpret_cast<const long long *>(&E.tilelast[t])[tid];
@@ -834,7 +838,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
         reinterpret_cast<long long *>(&s_prev)[tid] = rec_w;
         reinterpret_cast<long long *>(&s_all)[tid] = all_w;
     }
-    totals_commit(!EDGE, tregs, &tot);
+    totals_commit(!EDGE, tregs, &tot, true, !EDGE, NB == 1);
     __syncthreads();
     // Tile 0 leads: every iteration visits it (it is always recorded heavy).
     const bool lead_block = t == 0;

@@ -804,11 +804,22 @@ __device__ __forceinline__ bool span_outside(int x0, int W, int lo, int hi) {
     return x0 - 32 + lo < 0 || x0 - 32 + hi > W - 1;
 }
 
+// The horizontal-sum tables in registers: chunk c in v[c] (lane m holds the
+// sum for bit pattern m), and the last chunk's entries for patterns 0 and 1
+// (scalar), which a one-bit last chunk selects between instead of a permute.
 template <int NCH>
-__device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, int (&lut)[NCH]) {
+struct LutRegs {
+    int v[NCH];
+    float t0, t1;
+};
+
+template <int NCH>
+__device__ __forceinline__ void load_luts(const Taps *__restrict__ taps, LutRegs<NCH> &lut) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) lut[c] = __float_as_int(taps->lut[c][lane]);
+    for (int c = 0; c < NCH; ++c) lut.v[c] = __float_as_int(taps->lut[c][lane]);
+    lut.t0 = taps->lut[NCH - 1][0];
+    lut.t1 = taps->lut[NCH - 1][1];
 }
 
 // Zero padding of the horizontal taps at image column x (only where the
@@ -844,7 +855,7 @@ __device__ __forceinline__ HPad hpad_of(int x, int W, bool border, const float *
 // 64 lanes active (ds_bpermute).  `pad` is the lane's zero-padding correction
 // (hpad_of; all zero away from the left and right image edges).
 template <int R, int NCH>
-__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, HPad pad, const int (&lut)[NCH]) {
+__device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, HPad pad, const LutRegs<NCH> &lut) {
     constexpr int TS = 2 * R + 1;
     constexpr uint32_t FULL = (1u << TS) - 1u;
     const int ws = xb - R;
@@ -855,7 +866,10 @@ __device__ __forceinline__ float hconv_fast(const uint32_t *row, int xb, HPad pa
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const int idx = (int)((win >> (6 * c)) & 63u);
-        h += __int_as_float(__builtin_amdgcn_ds_bpermute(idx << 2, lut[c]));
+        if (c == NCH - 1 && TS - 6 * c == 1)
+            h += (idx & 1) ? lut.t1 : lut.t0;  // the same table entry, by a select
+        else
+            h += __int_as_float(__builtin_amdgcn_ds_bpermute(idx << 2, lut.v[c]));
     }
     return h - pad.corr;
 }
@@ -938,7 +952,7 @@ __device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, i
 template <int R, int NB, typename ST>
 __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes, const ST *__restrict__ img,
                                            int x0, int y0, int H, int W, bool border, bool raw,
-                                           const int (&lut)[FastGeom<R, false>::NCH], const float (&kk)[2 * R + 1],
+                                           const LutRegs<FastGeom<R, false>::NCH> &lut, const float (&kk)[2 * R + 1],
                                            const float *__restrict__ cum, float (&acc)[NB], int &cnt) {
     using G = FastGeom<R, false>;
     static_assert(G::SEGD % kSB == 0, "statistics segment must be a whole number of blocks");

@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
     const int nw = (E.tiles + 31) >> 5;                  // words of one schedule mask
     const int sbn = (n + 1) % 3, sbr = (n + 2) % 3;     // masks written / cleared by this iteration
     // Tables do not depend on the tile: their loads overlap the schedule's.
-    int lut[G::NCH];
+    LutRegs<G::NCH> lut;
     load_luts<G::NCH>(E.taps, lut);
     float kk[TS];
 #pragma unroll
@@ -1379,7 +1379,7 @@ __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const ImgArgs *__re
     const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > E.W;
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
     for (int i = threadIdx.x; i < G::UH * kFWords; i += kThreads) s_bn[i] = ~0u;
-    int lut[G::NCH];
+    LutRegs<G::NCH> lut;
     load_luts<G::NCH>(E.taps, lut);
     float kk[2 * R + 1];
 #pragma unroll
@@ -1414,7 +1414,7 @@ __global__ __launch_bounds__(kThreads) void stats_fast_kernel(StepArgs A, int ra
     uint32_t *s_bn = reinterpret_cast<uint32_t *>(smem);
     const int x0 = blockIdx.x * kFX, y0 = blockIdx.y * G::FY;
     const bool border = x0 - 2 * R - 2 < 0 || x0 + kFX + 2 * R + 2 > A.W;
-    int lut[G::NCH];
+    LutRegs<G::NCH> lut;
     load_luts<G::NCH>(A.taps, lut);
     float kk[2 * R + 1];
 #pragma unroll

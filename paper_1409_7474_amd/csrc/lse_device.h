@@ -949,7 +949,9 @@ __device__ __forceinline__ void code_rows_owned(const uint32_t *bn, int nrows, i
 // Every owned pixel of the image is read once (dense streaming); blocks of
 // 8 rows whose whole bit window is uniform take the sign without the
 // Gaussian sums (their value would be the same constant in every pixel).
-template <int R, int NB, typename ST>
+// GR: image rows per load group (two groups in flight); the sums do not
+// depend on it (each lane adds its rows in order).
+template <int R, int NB, typename ST, int GR = 4>
 __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes, const ST *__restrict__ img,
                                            int x0, int y0, int H, int W, bool border, bool raw,
                                            const LutRegs<FastGeom<R, false>::NCH> &lut, const float (&kk)[2 * R + 1],
@@ -1051,7 +1053,7 @@ __device__ __forceinline__ void stats_fast(const uint32_t *bn, const int *codes,
     const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (uint32_t)((unsigned long long)H * W * PB));
     const uint32_t off0 = (uint32_t)(((y0 + urow0) * W + x) * PB);
     const uint32_t rstride = (uint32_t)(W * PB);
-    constexpr int GR = 4;
+    static_assert(G::SEGD % (2 * GR) == 0, "load groups come in pairs");
     Px<NB> ba[GR], bb[GR];
     auto load_group = [&](Px<NB>(&buf)[GR], int g) {
 #pragma unroll

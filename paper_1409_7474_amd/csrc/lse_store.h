@@ -1329,7 +1329,11 @@ __global__ __launch_bounds__(kThreads, (StepVariant<EDGE, V>::OCC)) void step_fa
                 // D: statistics of phi^{n+1} = G * b^n for the next iteration.
                 code_rows_owned<R>(s_bn, G::UH, s_codes);
                 __syncthreads();
-                stats_fast<R, NB, ST>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, H, W, border, false,
+                // Groups of 6 image rows (a 24-row segment in about two memory
+                // round trips instead of three) where the register budget
+                // allows it: at 5 waves per SIMD they spill.
+                constexpr int GRD = (StepVariant<EDGE, V>::OCC <= 4 && G::SEGD % 12 == 0) ? 6 : 4;
+                stats_fast<R, NB, ST, GRD>(s_bn, s_codes, static_cast<const ST *>(A.img), x0, y0, H, W, border, false,
                                       lut, kk, cum, acc, cnt);
             }
             TileSmem rs;

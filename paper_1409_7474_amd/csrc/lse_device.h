@@ -46,33 +46,6 @@ __device__ __forceinline__ float wave_min_f(float v) {
     return v;
 }
 
-__device__ __forceinline__ long long wave_sum_ll(long long v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
-__device__ __forceinline__ unsigned int wave_max_u(unsigned int v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned int)__shfl_xor(v, m, 64));
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const unsigned long long o = (unsigned long long)__shfl_xor((long long)v, m, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ unsigned int wave_min_u(unsigned int v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, (unsigned int)__shfl_xor(v, m, 64));
-    return v;
-}
-
 // Integer reductions over a whole wave without LDS traffic (the shuffles
 // above are LDS permutes, which queue behind the phi pass's table lookups of
 // other workgroups): a butterfly inside each row of 16 lanes by DPP moves
